@@ -1,0 +1,221 @@
+/*
+ * ppcmh.h -- C-ABI of the MI355X library for periodic Parareal with a multi-harmonic
+ * coarse correction (PP-PC) applied to the 2-D eddy-current problem
+ *
+ *     M du/dt + K(u) u = f(t),   t in (0, T),   u(0) = u(T)
+ *
+ * of Kulchytska-Ruchka, De Gersem and Schoeps (arXiv:1905.13076), Section 2, eq. (1).
+ *
+ * Conventions for every function:
+ *   - return 0 (PPC_OK) on success, > 0 for completion with a warning (outputs written),
+ *     < 0 for an error (no output written; ppc_last_error() explains);
+ *   - all indices are 0-based int32, all reals IEEE double unless stated;
+ *   - the caller owns every buffer it passes; the library copies what it needs during
+ *     the call and keeps no caller pointer afterwards;
+ *   - argument checks happen on the host before any device work, so argument errors
+ *     are reported identically on machines without a GPU;
+ *   - "host pointer" means ordinary CPU memory, "device pointer" means memory of the
+ *     handle's GPU (e.g. from hipMalloc or a torch CUDA tensor);
+ *   - a handle is used by one host thread at a time; distinct handles are independent.
+ *
+ * Vectors of nodal values are indexed by mesh node (length n_nodes) with the
+ * Dirichlet nodes held at 0.  A set of coarse samples U (Section 2: U_n at
+ * T_n = n T / N, n = 0..N-1) is stored row-major as U[n * n_nodes + node].
+ */
+#ifndef PPCMH_H
+#define PPCMH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PPC_ABI_VERSION 1
+
+/* status codes */
+#define PPC_OK 0
+#define PPC_NOT_CONVERGED 1   /* warning: outputs hold the last iterate */
+#define PPC_ERR_ARG (-1)      /* invalid argument (null, size, non-finite, range) */
+#define PPC_ERR_MESH (-2)     /* degenerate/invalid mesh (zero area, bad index, no Dirichlet
+                                 node, node in no triangle, no free node) */
+#define PPC_ERR_DEVICE (-3)   /* HIP runtime error or no usable GPU */
+#define PPC_ERR_OOM (-4)      /* device allocation failed */
+#define PPC_ERR_NONFINITE (-5)/* NaN/Inf in a residual (e.g. exp overflow of the B-H law) */
+#define PPC_ERR_BREAKDOWN (-6)/* COCG breakdown: rho or p^T A p vanished */
+#define PPC_ERR_NEWTON (-7)   /* Newton / line search failed in a fine step */
+
+/* reluctivity laws (per material) */
+#define PPC_LAW_LINEAR 0      /* nu = const */
+#define PPC_LAW_BRAUER 1      /* nu(b2) = k1 exp(k2 b2) + k3, b2 = |B|^2 = |grad A|^2 */
+
+typedef struct ppc_handle ppc_handle;
+typedef struct ppc_problem ppc_problem;
+
+/* Triangular P1 mesh (Section 4 uses "the finite element method"; linear triangles
+ * are this library's element).  Triangles may have either orientation. */
+typedef struct {
+    int32_t n_nodes;
+    const double* xy;     /* host, [2 * n_nodes], (x, y) interleaved, metres */
+    int32_t n_tri;
+    const int32_t* tri;   /* host, [3 * n_tri] node indices */
+    int32_t n_dir;
+    const int32_t* dir;   /* host, [n_dir] nodes with A = 0 (homogeneous Dirichlet) */
+} ppc_mesh;
+
+typedef struct {
+    int32_t law;          /* PPC_LAW_LINEAR or PPC_LAW_BRAUER */
+    double nu;            /* linear reluctivity (m/H), > 0; unused for Brauer */
+    double k1, k2, k3;    /* Brauer constants: k1 >= 0, k2 >= 0, k3 > 0 */
+} ppc_law;
+
+/* Materials per triangle: the conductivity sigma defines M (Section 2: "the
+ * (singular) conductivity matrix"; sigma = 0 gives zero rows), the law defines K(u). */
+typedef struct {
+    const double* sigma;    /* host, [n_tri], S/m, >= 0 */
+    const int32_t* mat_id;  /* host, [n_tri], index into table */
+    int32_t n_mat;
+    const ppc_law* table;   /* host, [n_mat] */
+} ppc_material;
+
+/* Excitation f(t) = i(t) * F with F_i = sum_e js_e |T_e| / 3 (P1 load of a uniform
+ * source density) and i(t) = sum_h amp_h sin(2 pi order_h f0 t + phase_h); Section 4
+ * drives the cable with a 50 Hz sinusoidal current. */
+typedef struct {
+    const double* js;       /* host, [n_tri], source current density per ampere (A/m^2/A) */
+    double f0;              /* fundamental frequency (Hz) */
+    int32_t n_h;            /* number of terms, >= 0 */
+    const int32_t* order;   /* host, [n_h] */
+    const double* amp;      /* host, [n_h] (A) */
+    const double* phase;    /* host, [n_h] (rad) */
+} ppc_excitation;
+
+/* Solver parameters.  Fill with ppc_params_default() and override. */
+typedef struct {
+    double T;               /* period (s), > 0 (Section 2) */
+    int32_t N;              /* Parareal subintervals, even, >= 2 (Section 2) */
+    int32_t m;              /* implicit-Euler fine steps per subinterval, >= 1 (Section 4) */
+    int32_t shift_mode;     /* 0: exact DFT symbol of eq. (9), (1 - e^{-i w_p dT})/dT;
+                               1: harmonic-balance shift i w_p (eq. (12)) */
+    int32_t lin_mode;       /* coarse stiffness of a nonlinear problem: 0 = time average
+                               of the differential reluctivity tensor, 1 = of the chord nu */
+    int32_t init_mode;      /* U^0 when no U_init is given: 0 auto (1 if all laws linear,
+                               else 2), 1 linear coarse periodic solve at u = 0, 2 zero */
+    int32_t precision;      /* 0: FP64 fine solves; 1: FP32 PCG refined by FP64 Newton */
+    double tol_ppc;         /* stop when ||J||_F / ||U||_F <= tol_ppc */
+    int32_t max_iters;      /* maximum coarse corrections */
+    double tol_newton;      /* ||R|| <= tol_newton (||f(t)|| + ||M u_prev|| / dt) */
+    int32_t max_newton;     /* Newton iterations per fine step */
+    double tol_lin;         /* PCG: ||r|| <= max(tol_lin ||R||, 0.5 tol_newton scale) */
+    int32_t max_lin;        /* PCG iteration cap per Newton step */
+    double tol_cocg;        /* COCG: ||r|| <= tol_cocg ||b|| per harmonic */
+    int32_t max_cocg;       /* COCG iteration cap */
+    int32_t block;          /* fine-kernel workgroup size (0: library choice) */
+    int32_t reserved[7];
+} ppc_params;
+
+/* Counters and timings of the last solve (all chains, all iterations). */
+typedef struct {
+    int32_t status;
+    int32_t iterations;          /* coarse corrections applied (fine sweeps = iterations+1) */
+    int32_t fine_launches;       /* fine-sweep kernel launches */
+    int32_t coarse_solves;       /* harmonic COCG launches */
+    int64_t newton_total;        /* Newton iterations over every chain and step */
+    int64_t lin_total;           /* PCG iterations over every chain */
+    int64_t cocg_total;          /* COCG iterations summed over harmonics */
+    int32_t newton_max;          /* largest Newton count of one fine step */
+    int32_t lin_max;             /* largest PCG count of one Newton step */
+    int32_t cocg_max;            /* largest COCG count of one harmonic solve */
+    int32_t lin_capped;          /* PCG solves that hit max_lin */
+    double fine_ms;              /* device time in fine-sweep kernels (hipEvents) */
+    double coarse_ms;            /* device time in the coarse correction */
+    double total_ms;             /* device time of the whole solve */
+    double jump;                 /* ||U_0 - F_N(U_{N-1})|| of the last sweep (eq. (4), n=0) */
+    double eps;                  /* last ||J||_F / ||U||_F */
+    double max_b_steel;          /* max |B| over nonlinear elements at the returned U (T) */
+    int32_t n_free, nnz, n_tri, reserved_i;
+} ppc_stats;
+
+/* ABI version (PPC_ABI_VERSION). */
+int ppc_version(void);
+
+/* Defaults: T = 0.02, N = 10, m = 20, shift 0, lin 0, init 0, FP64, tol_ppc 1e-12,
+ * max_iters 60, tol_newton 1e-13, max_newton 50, tol_lin 1e-8, max_lin 20000,
+ * tol_cocg 1e-10, max_cocg 20000.  Returns PPC_ERR_ARG on a null pointer. */
+int ppc_params_default(ppc_params* p);
+
+/* Message of the last error on this handle (never null; valid until the next call on
+ * the handle).  With a null handle: the last error of a failed ppc_create or of a
+ * host-only call on this thread. */
+const char* ppc_last_error(const ppc_handle* h);
+
+/* Host-only check of a problem description (Section 2, eq. (1) inputs).  Returns
+ * PPC_OK, PPC_ERR_ARG or PPC_ERR_MESH; touches no device.  msg may be null. */
+int ppc_validate(const ppc_mesh* mesh, const ppc_material* mat, const ppc_excitation* exc,
+                 char* msg, int32_t msg_len);
+
+/* Host-only check of solver parameters against a problem size (N even, m >= 1, ...). */
+int ppc_validate_params(const ppc_params* p, char* msg, int32_t msg_len);
+
+/* Open a handle on GPU `device`: sets the device, creates the library's stream and
+ * events.  PPC_ERR_DEVICE when no GPU is present.  *out is null on failure. */
+int ppc_create(int32_t device, ppc_handle** out);
+
+/* Release a handle (null-safe).  Problems created on it must be destroyed first. */
+int ppc_destroy(ppc_handle* h);
+
+/* Copy a problem to the device and run the set-up kernels: element gradient
+ * coefficients, areas, unit stiffness K0_e, conductivity mass M, load F, the CSR
+ * pattern of the free nodes and the element->entry maps (Section 2, eq. (1) with P1
+ * elements).  Validates first (as ppc_validate).  *out is null on failure. */
+int ppc_problem_create(ppc_handle* h, const ppc_mesh* mesh, const ppc_material* mat,
+                       const ppc_excitation* exc, ppc_problem** out);
+
+/* Free a problem's device memory (null-safe). */
+int ppc_problem_destroy(ppc_problem* pr);
+
+/* Sizes of a problem: free nodes, CSR entries among free nodes, triangles, nodes. */
+int ppc_problem_info(const ppc_problem* pr, int32_t* n_free, int32_t* nnz, int32_t* n_tri,
+                     int32_t* n_nodes);
+
+/* Periodic steady state by PP-PC (Section 2, eq. (4); coarse problem of eqs. (8)-(10)
+ * solved per harmonic after a DFT along time, Section 3, eqs. (11)-(14)).
+ *   U_init     host, [N * n_nodes] or null (then params->init_mode decides U^0)
+ *   U_out      host, [N * n_nodes]: the returned coarse samples U_n (row n = time T_n)
+ *   resid_out  host, [max_iters + 1] or null: eps^k = ||J^k||_F / ||U^k||_F per sweep
+ *   iters_out  host, or null: coarse corrections applied
+ *   stats      host, or null
+ * Returns PPC_OK, PPC_NOT_CONVERGED (outputs hold the last iterate) or an error. */
+int ppc_solve(ppc_handle* h, ppc_problem* pr, const ppc_params* p, const double* U_init,
+              double* U_out, double* resid_out, int32_t* iters_out, ppc_stats* stats);
+
+/* As ppc_solve with U_init / U_out as DEVICE pointers on the handle's GPU; the work is
+ * ordered on `stream` (a hipStream_t, null = the library's stream) and complete on
+ * return.  resid_out, iters_out and stats stay host pointers.  ppc_solve is this call
+ * plus host<->device copies. */
+int ppc_solve_device(ppc_handle* h, ppc_problem* pr, const ppc_params* p,
+                     const double* U_init_dev, double* U_out_dev, double* resid_out,
+                     int32_t* iters_out, ppc_stats* stats, void* stream);
+
+/* One fine sweep (Section 2, eqs. (2)-(3)): F_out[n mod N] = F_n(U_in[n-1]) for
+ * n = 1..N, all chains in one launch.  U_in / F_out are DEVICE pointers
+ * [N * n_nodes]; newton_out / lin_out are host [N] or null (per-chain Newton and PCG
+ * iteration totals).  Returns PPC_ERR_NEWTON / PPC_ERR_NONFINITE if a chain failed. */
+int ppc_fine_sweep_device(ppc_handle* h, ppc_problem* pr, const ppc_params* p,
+                          const double* U_in_dev, double* F_out_dev, int32_t* newton_out,
+                          int32_t* lin_out, void* stream);
+
+/* One coarse correction (Section 3, eqs. (11)-(14), in correction form): from the
+ * samples U and jumps J (DEVICE [N * n_nodes]; J[n] = F_n - U_n mod N) compute
+ * dU (DEVICE [N * n_nodes]) solving Q dU_n - C dU_{n-1} = Q J_n cyclically, with
+ * C = M/dT, Q = C + Kbar(U) (eq. (10)).  cocg_out: host [N/2 + 1] or null (COCG
+ * iterations per harmonic). */
+int ppc_coarse_correction_device(ppc_handle* h, ppc_problem* pr, const ppc_params* p,
+                                 const double* U_dev, const double* J_dev, double* dU_dev,
+                                 int32_t* cocg_out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PPCMH_H */

@@ -1,0 +1,113 @@
+"""ctypes declarations of the C-ABI in include/ppcmh.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_char_p, c_double, c_int, c_int32, c_int64, c_void_p
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libppcmh.so")
+
+PPC_OK = 0
+PPC_NOT_CONVERGED = 1
+PPC_ERR_ARG = -1
+PPC_ERR_MESH = -2
+PPC_ERR_DEVICE = -3
+PPC_ERR_OOM = -4
+PPC_ERR_NONFINITE = -5
+PPC_ERR_BREAKDOWN = -6
+PPC_ERR_NEWTON = -7
+
+STATUS_NAMES = {0: "ok", 1: "not converged", -1: "argument", -2: "mesh", -3: "device",
+                -4: "out of memory", -5: "non-finite", -6: "breakdown", -7: "newton"}
+
+PD = POINTER(c_double)
+PI = POINTER(c_int32)
+
+
+class Mesh(ctypes.Structure):
+    _fields_ = [("n_nodes", c_int32), ("xy", PD), ("n_tri", c_int32), ("tri", PI),
+                ("n_dir", c_int32), ("dir", PI)]
+
+
+class Law(ctypes.Structure):
+    _fields_ = [("law", c_int32), ("nu", c_double), ("k1", c_double), ("k2", c_double),
+                ("k3", c_double)]
+
+
+class Material(ctypes.Structure):
+    _fields_ = [("sigma", PD), ("mat_id", PI), ("n_mat", c_int32), ("table", POINTER(Law))]
+
+
+class Excitation(ctypes.Structure):
+    _fields_ = [("js", PD), ("f0", c_double), ("n_h", c_int32), ("order", PI), ("amp", PD),
+                ("phase", PD)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("T", c_double), ("N", c_int32), ("m", c_int32), ("shift_mode", c_int32),
+                ("lin_mode", c_int32), ("init_mode", c_int32), ("precision", c_int32),
+                ("tol_ppc", c_double), ("max_iters", c_int32), ("tol_newton", c_double),
+                ("max_newton", c_int32), ("tol_lin", c_double), ("max_lin", c_int32),
+                ("tol_cocg", c_double), ("max_cocg", c_int32), ("block", c_int32),
+                ("reserved", c_int32 * 7)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("status", c_int32), ("iterations", c_int32), ("fine_launches", c_int32),
+                ("coarse_solves", c_int32), ("newton_total", c_int64), ("lin_total", c_int64),
+                ("cocg_total", c_int64), ("newton_max", c_int32), ("lin_max", c_int32),
+                ("cocg_max", c_int32), ("lin_capped", c_int32), ("fine_ms", c_double),
+                ("coarse_ms", c_double), ("total_ms", c_double), ("jump", c_double),
+                ("eps", c_double), ("max_b_steel", c_double), ("n_free", c_int32),
+                ("nnz", c_int32), ("n_tri", c_int32), ("reserved_i", c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved_i"}
+
+
+# name -> (restype, argtypes); every symbol declared in include/ppcmh.h
+SIGNATURES = {
+    "ppc_version": (c_int, []),
+    "ppc_params_default": (c_int, [POINTER(Params)]),
+    "ppc_last_error": (c_char_p, [c_void_p]),
+    "ppc_validate": (c_int, [POINTER(Mesh), POINTER(Material), POINTER(Excitation), c_char_p, c_int32]),
+    "ppc_validate_params": (c_int, [POINTER(Params), c_char_p, c_int32]),
+    "ppc_create": (c_int, [c_int32, POINTER(c_void_p)]),
+    "ppc_destroy": (c_int, [c_void_p]),
+    "ppc_problem_create": (c_int, [c_void_p, POINTER(Mesh), POINTER(Material), POINTER(Excitation),
+                                   POINTER(c_void_p)]),
+    "ppc_problem_destroy": (c_int, [c_void_p]),
+    "ppc_problem_info": (c_int, [c_void_p, PI, PI, PI, PI]),
+    "ppc_solve": (c_int, [c_void_p, c_void_p, POINTER(Params), PD, PD, PD, PI, POINTER(Stats)]),
+    "ppc_solve_device": (c_int, [c_void_p, c_void_p, POINTER(Params), c_void_p, c_void_p, PD, PI,
+                                 POINTER(Stats), c_void_p]),
+    "ppc_fine_sweep_device": (c_int, [c_void_p, c_void_p, POINTER(Params), c_void_p, c_void_p, PI, PI,
+                                      c_void_p]),
+    "ppc_coarse_correction_device": (c_int, [c_void_p, c_void_p, POINTER(Params), c_void_p, c_void_p,
+                                             c_void_p, PI, c_void_p]),
+}
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libppcmh.so and declare its signatures.  Raises if it is missing: the
+    product has no fallback path."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP library {path} is not built; run python -m paper_1905_13076_amd.build")
+    # torch ships its own HIP runtime (soname libamdhip64.so.7).  Loading torch first
+    # makes the dynamic linker bind this library to that same runtime instead of
+    # mapping a second one into the process, so torch tensors and the library share
+    # one device context.
+    import torch  # noqa: F401
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib

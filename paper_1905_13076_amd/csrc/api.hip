@@ -1,0 +1,502 @@
+// C-ABI entry points and the PP-PC driver (Section 2, eq. (4); Section 3).
+//
+// Driver per iteration k (all arithmetic in kernels; the host only sequences launches
+// and reads three scalars and the per-chain counters):
+//   fine sweep F_n(U^k_{n-1}) for every chain in one launch;
+//   jumps J_n = F_n - U^k_{n mod N}, eps^k = ||J||_F / ||U^k||_F (the tolerance quantity
+//     of Section 4 is not stated in the paper; this is the reading);
+//   stop and return U^k if eps^k <= tol;
+//   coarse correction U^{k+1} = U^k + dU (linearise, right-hand side, DFT along time,
+//     COCG per harmonic, inverse DFT + update).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "internal.hpp"
+
+namespace ppc {
+
+void fail(int code, const std::string& msg) { throw Error{code, msg}; }
+
+void hip_check(hipError_t e, const char* what) {
+    if (e == hipSuccess) return;
+    const int code = (e == hipErrorOutOfMemory) ? PPC_ERR_OOM : PPC_ERR_DEVICE;
+    fail(code, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+namespace {
+
+thread_local std::string g_thread_error;
+
+size_t pad64(size_t n) { return (n + 63) / 64 * 64; }
+
+template <typename T>
+T* dalloc(size_t n) {
+    void* p = nullptr;
+    if (n == 0) n = 1;
+    const hipError_t e = hipMalloc(&p, n * sizeof(T));
+    if (e != hipSuccess) fail(PPC_ERR_OOM, "hipMalloc of " + std::to_string(n * sizeof(T)) + " bytes failed");
+    return static_cast<T*>(p);
+}
+
+void set_msg(char* msg, int32_t len, const std::string& s) {
+    if (!msg || len <= 0) return;
+    const size_t k = std::min((size_t)len - 1, s.size());
+    std::memcpy(msg, s.data(), k);
+    msg[k] = '\0';
+}
+
+template <typename Fn>
+int guarded(ppc_handle* h, Fn&& fn) {
+    std::string err;
+    int code = PPC_OK;
+    try {
+        return fn();
+    } catch (const Error& e) {
+        code = e.code;
+        err = e.msg;
+    } catch (const std::bad_alloc&) {
+        code = PPC_ERR_OOM;
+        err = "host allocation failed";
+    } catch (const std::exception& e) {
+        code = PPC_ERR_ARG;
+        err = e.what();
+    } catch (...) {
+        code = PPC_ERR_ARG;
+        err = "unknown failure";
+    }
+    if (h) h->last_error = err;
+    g_thread_error = err;
+    return code;
+}
+
+__global__ void k_fill(long n, double v, double* __restrict__ x) {
+    for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) x[k] = v;
+}
+
+void fill(double* x, long n, double v, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill, dim3(1024), dim3(256), 0, s, n, v, x);
+    PPC_HIP(hipGetLastError());
+}
+
+float elapsed(hipEvent_t a, hipEvent_t b) {
+    float ms = 0.f;
+    PPC_HIP(hipEventElapsedTime(&ms, a, b));
+    return ms;
+}
+
+}  // namespace
+
+void workspace_free(Workspace& w) {
+    void* ptrs[] = {w.fvec, w.fpcg, w.fjac, w.felem, w.fcount, w.U, w.F, w.J, w.R, w.kbar,
+                    w.nubar, w.rhat, w.cwork, w.sig, w.ccount, w.twiddle, w.partial, w.scal};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    if (w.host_scal) (void)hipHostFree(w.host_scal);
+    w = Workspace{};
+}
+
+void ensure_workspace(ppc_problem* pr, const ppc_params* p) {
+    Workspace& w = pr->ws;
+    if (w.N == p->N) return;
+    workspace_free(w);
+    const DeviceMesh& d = pr->mesh;
+    const size_t N = p->N, H = N / 2 + 1;
+    w.n_pad = pad64(d.n_free);
+    w.nnz_pad = pad64(d.nnz);
+    w.ne_pad = pad64(d.n_tri);
+    w.fvec = dalloc<double>(N * kFineVec * w.n_pad);
+    w.fpcg = dalloc<double>(N * kPcgVec * w.n_pad);     // sized for FP64, also used as FP32
+    w.fjac = dalloc<double>(N * w.nnz_pad);
+    w.felem = dalloc<double>(N * 8 * w.ne_pad);
+    w.fcount = dalloc<int>(N * 8);
+    w.U = dalloc<double>(N * d.n_free);
+    w.F = dalloc<double>(N * d.n_free);
+    w.J = dalloc<double>(N * d.n_free);
+    w.R = dalloc<double>(N * d.n_free);
+    w.kbar = dalloc<double>(d.nnz);
+    w.nubar = dalloc<double>(3 * (size_t)d.n_tri);
+    w.rhat = dalloc<double2>(2 * H * d.n_free);
+    w.cwork = dalloc<double2>(H * 4 * w.n_pad);
+    w.sig = dalloc<double2>(H);
+    w.ccount = dalloc<int>(H * 4);
+    w.twiddle = dalloc<double2>(N);
+    w.partial = dalloc<double>(256 * 3);
+    w.scal = dalloc<double>(16);
+    void* hp = nullptr;
+    PPC_HIP(hipHostMalloc(&hp, 16 * sizeof(double), hipHostMallocDefault));
+    w.host_scal = static_cast<double*>(hp);
+    w.N = p->N;
+}
+
+namespace {
+
+struct SweepCounts {
+    int status = 0;
+    int64_t newton = 0, lin = 0;
+    int newton_max = 0, lin_max = 0, capped = 0;
+    int fail_chain = -1, fail_step = -1;
+};
+
+SweepCounts read_chain_counts(ppc_problem* pr, int N, hipStream_t s, int32_t* newton_out,
+                              int32_t* lin_out) {
+    std::vector<int> c(8 * (size_t)N);
+    PPC_HIP(hipMemcpyAsync(c.data(), pr->ws.fcount, c.size() * sizeof(int), hipMemcpyDeviceToHost, s));
+    PPC_HIP(hipStreamSynchronize(s));
+    SweepCounts r;
+    for (int k = 0; k < N; ++k) {
+        const int* q = c.data() + 8 * k;
+        if (q[0] != 0 && r.status == 0) {
+            r.status = q[0];
+            r.fail_chain = k;
+            r.fail_step = q[6];
+        }
+        r.newton += q[1];
+        r.lin += q[2];
+        r.newton_max = std::max(r.newton_max, q[3]);
+        r.lin_max = std::max(r.lin_max, q[4]);
+        r.capped += q[5];
+        if (newton_out) newton_out[k] = q[1];
+        if (lin_out) lin_out[k] = q[2];
+    }
+    return r;
+}
+
+void check_sweep(const SweepCounts& c) {
+    if (c.status != 0)
+        fail(c.status, "fine chain " + std::to_string(c.fail_chain + 1) + " failed at step " +
+                           std::to_string(c.fail_step) +
+                           (c.status == PPC_ERR_NONFINITE ? " (non-finite residual)" : " (Newton did not converge)"));
+}
+
+int read_cocg(ppc_problem* pr, int H, hipStream_t s, int32_t* cocg_out, int64_t* total, int* mx) {
+    std::vector<int> c(4 * (size_t)H);
+    PPC_HIP(hipMemcpyAsync(c.data(), pr->ws.ccount, c.size() * sizeof(int), hipMemcpyDeviceToHost, s));
+    PPC_HIP(hipStreamSynchronize(s));
+    int status = 0;
+    for (int p = 0; p < H; ++p) {
+        if (c[4 * p] != 0 && status == 0) status = c[4 * p];
+        if (cocg_out) cocg_out[p] = c[4 * p + 1];
+        if (total) *total += c[4 * p + 1];
+        if (mx) *mx = std::max(*mx, c[4 * p + 1]);
+    }
+    if (status != 0)
+        fail(status, status == PPC_ERR_BREAKDOWN ? "COCG breakdown in a harmonic solve" : "non-finite COCG residual");
+    return 0;
+}
+
+hipStream_t pick_stream(ppc_handle* h, void* stream) {
+    return stream ? static_cast<hipStream_t>(stream) : h->stream;
+}
+
+void check_handle_problem(ppc_handle* h, ppc_problem* pr) {
+    if (!h) fail(PPC_ERR_ARG, "null handle");
+    if (!pr) fail(PPC_ERR_ARG, "null problem");
+    if (pr->h != h) fail(PPC_ERR_ARG, "problem belongs to another handle");
+}
+
+void check_params(const ppc_params* p) {
+    std::string msg;
+    const int rc = validate_params(p, msg);
+    if (rc != PPC_OK) fail(rc, msg);
+}
+
+int solve_device(ppc_handle* h, ppc_problem* pr, const ppc_params* p, const double* U_init_dev,
+                 double* U_out_dev, double* resid_out, int32_t* iters_out, ppc_stats* st,
+                 hipStream_t s) {
+    PPC_HIP(hipSetDevice(h->device));
+    ensure_workspace(pr, p);
+    Workspace& w = pr->ws;
+    const DeviceMesh& d = pr->mesh;
+    const int N = p->N, H = N / 2 + 1, n = d.n_free;
+    ppc_stats S{};
+    S.n_free = d.n_free;
+    S.nnz = d.nnz;
+    S.n_tri = d.n_tri;
+    hipEvent_t* ev = h->ev;
+    PPC_HIP(hipEventRecord(ev[4], s));
+    if (U_init_dev) {
+        launch_to_free(pr, N, U_init_dev, w.U, s);
+    } else {
+        int mode = p->init_mode;
+        if (mode == 0) mode = d.nonlinear ? 2 : 1;
+        if (mode == 2) {
+            fill(w.U, (long)N * n, 0.0, s);
+        } else {
+            launch_coarse(pr, p, nullptr, nullptr, w.U, false, true, s);
+            read_cocg(pr, H, s, nullptr, &S.cocg_total, &S.cocg_max);
+            S.coarse_solves++;
+        }
+    }
+    int status = PPC_NOT_CONVERGED;
+    int k = 0;
+    for (k = 0; k <= p->max_iters; ++k) {
+        PPC_HIP(hipEventRecord(ev[0], s));
+        launch_fine_sweep(pr, p, w.U, w.F, s);
+        PPC_HIP(hipEventRecord(ev[1], s));
+        S.fine_launches++;
+        launch_jumps(pr, N, w.U, w.F, w.J, w.scal, s);
+        PPC_HIP(hipMemcpyAsync(w.host_scal, w.scal, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+        const SweepCounts c = read_chain_counts(pr, N, s, nullptr, nullptr);  // synchronises
+        S.fine_ms += elapsed(ev[0], ev[1]);
+        S.newton_total += c.newton;
+        S.lin_total += c.lin;
+        S.newton_max = std::max(S.newton_max, c.newton_max);
+        S.lin_max = std::max(S.lin_max, c.lin_max);
+        S.lin_capped += c.capped;
+        check_sweep(c);
+        const double jj = w.host_scal[0], uu = w.host_scal[1], j0 = w.host_scal[2];
+        const double eps = uu > 0.0 ? std::sqrt(jj) / std::sqrt(uu) : (jj == 0.0 ? 0.0 : INFINITY);
+        if (!std::isfinite(jj)) fail(PPC_ERR_NONFINITE, "non-finite jump norm");
+        if (resid_out) resid_out[k] = eps;
+        S.eps = eps;
+        S.jump = std::sqrt(j0);
+        if (eps <= p->tol_ppc) {
+            status = PPC_OK;
+            break;
+        }
+        if (k == p->max_iters) break;
+        PPC_HIP(hipEventRecord(ev[2], s));
+        launch_coarse(pr, p, w.U, w.J, w.U, true, false, s);
+        PPC_HIP(hipEventRecord(ev[3], s));
+        read_cocg(pr, H, s, nullptr, &S.cocg_total, &S.cocg_max);  // synchronises
+        S.coarse_ms += elapsed(ev[2], ev[3]);
+        S.coarse_solves++;
+    }
+    S.iterations = std::min(k, p->max_iters);
+    if (U_out_dev) launch_to_nodal(pr, N, w.U, U_out_dev, s);
+    if (d.nonlinear) {
+        launch_max_b(pr, N, w.U, w.scal + 4, s);
+        PPC_HIP(hipMemcpyAsync(w.host_scal + 4, w.scal + 4, sizeof(double), hipMemcpyDeviceToHost, s));
+    }
+    PPC_HIP(hipEventRecord(ev[5], s));
+    PPC_HIP(hipStreamSynchronize(s));
+    S.max_b_steel = d.nonlinear ? w.host_scal[4] : 0.0;
+    S.total_ms = elapsed(ev[4], ev[5]);
+    S.status = status;
+    if (iters_out) *iters_out = S.iterations;
+    if (st) *st = S;
+    return status;
+}
+
+}  // namespace
+}  // namespace ppc
+
+using namespace ppc;
+
+extern "C" {
+
+int ppc_version(void) { return PPC_ABI_VERSION; }
+
+int ppc_params_default(ppc_params* p) {
+    if (!p) return PPC_ERR_ARG;
+    std::memset(p, 0, sizeof(*p));
+    p->T = 0.02;
+    p->N = 10;
+    p->m = 20;
+    p->shift_mode = 0;
+    p->lin_mode = 0;
+    p->init_mode = 0;
+    p->precision = 0;
+    p->tol_ppc = 1e-12;
+    p->max_iters = 60;
+    p->tol_newton = 1e-13;
+    p->max_newton = 50;
+    p->tol_lin = 1e-8;
+    p->max_lin = 20000;
+    p->tol_cocg = 1e-10;
+    p->max_cocg = 20000;
+    p->block = 0;
+    return PPC_OK;
+}
+
+const char* ppc_last_error(const ppc_handle* h) {
+    return h ? h->last_error.c_str() : g_thread_error.c_str();
+}
+
+int ppc_validate(const ppc_mesh* mesh, const ppc_material* mat, const ppc_excitation* exc, char* msg,
+                 int32_t msg_len) {
+    std::string m;
+    const int rc = validate_problem(mesh, mat, exc, m);
+    set_msg(msg, msg_len, rc == PPC_OK ? std::string("ok") : m);
+    if (rc != PPC_OK) g_thread_error = m;
+    return rc;
+}
+
+int ppc_validate_params(const ppc_params* p, char* msg, int32_t msg_len) {
+    std::string m;
+    const int rc = validate_params(p, m);
+    set_msg(msg, msg_len, rc == PPC_OK ? std::string("ok") : m);
+    if (rc != PPC_OK) g_thread_error = m;
+    return rc;
+}
+
+int ppc_create(int32_t device, ppc_handle** out) {
+    return guarded(nullptr, [&]() -> int {
+        if (!out) fail(PPC_ERR_ARG, "null output pointer");
+        *out = nullptr;
+        if (device < 0) fail(PPC_ERR_ARG, "negative device index");
+        int count = 0;
+        const hipError_t e = hipGetDeviceCount(&count);
+        if (e != hipSuccess || count == 0) fail(PPC_ERR_DEVICE, "no usable GPU (hipGetDeviceCount)");
+        if (device >= count) fail(PPC_ERR_ARG, "device index out of range");
+        PPC_HIP(hipSetDevice(device));
+        auto* h = new ppc_handle();
+        h->device = device;
+        try {
+            PPC_HIP(hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking));
+            for (auto& ev : h->ev) PPC_HIP(hipEventCreate(&ev));
+        } catch (...) {
+            ppc_destroy(h);
+            throw;
+        }
+        *out = h;
+        return PPC_OK;
+    });
+}
+
+int ppc_destroy(ppc_handle* h) {
+    if (!h) return PPC_OK;
+    if (h->n_problems != 0) {
+        h->last_error = "destroy the handle's problems first";
+        return PPC_ERR_ARG;
+    }
+    (void)hipSetDevice(h->device);
+    for (auto& ev : h->ev)
+        if (ev) (void)hipEventDestroy(ev);
+    if (h->stream) (void)hipStreamDestroy(h->stream);
+    delete h;
+    return PPC_OK;
+}
+
+int ppc_problem_create(ppc_handle* h, const ppc_mesh* mesh, const ppc_material* mat,
+                       const ppc_excitation* exc, ppc_problem** out) {
+    return guarded(h, [&]() -> int {
+        if (!out) fail(PPC_ERR_ARG, "null output pointer");
+        *out = nullptr;
+        if (!h) fail(PPC_ERR_ARG, "null handle");
+        std::string msg;
+        const int rc = validate_problem(mesh, mat, exc, msg);
+        if (rc != PPC_OK) fail(rc, msg);
+        PPC_HIP(hipSetDevice(h->device));
+        auto* pr = new ppc_problem();
+        pr->h = h;
+        try {
+            build_problem(pr, mesh, mat, exc, h->stream);
+        } catch (...) {
+            mesh_free(pr->mesh);
+            if (pr->lawtab) (void)hipFree(pr->lawtab);
+            if (pr->wavtab) (void)hipFree(pr->wavtab);
+            delete pr;
+            throw;
+        }
+        h->n_problems++;
+        *out = pr;
+        return PPC_OK;
+    });
+}
+
+int ppc_problem_destroy(ppc_problem* pr) {
+    if (!pr) return PPC_OK;
+    if (pr->h) (void)hipSetDevice(pr->h->device);
+    workspace_free(pr->ws);
+    mesh_free(pr->mesh);
+    if (pr->lawtab) (void)hipFree(pr->lawtab);
+    if (pr->wavtab) (void)hipFree(pr->wavtab);
+    if (pr->h) pr->h->n_problems--;
+    delete pr;
+    return PPC_OK;
+}
+
+int ppc_problem_info(const ppc_problem* pr, int32_t* n_free, int32_t* nnz, int32_t* n_tri,
+                     int32_t* n_nodes) {
+    if (!pr) return PPC_ERR_ARG;
+    if (n_free) *n_free = pr->mesh.n_free;
+    if (nnz) *nnz = pr->mesh.nnz;
+    if (n_tri) *n_tri = pr->mesh.n_tri;
+    if (n_nodes) *n_nodes = pr->mesh.n_nodes;
+    return PPC_OK;
+}
+
+int ppc_solve_device(ppc_handle* h, ppc_problem* pr, const ppc_params* p, const double* U_init_dev,
+                     double* U_out_dev, double* resid_out, int32_t* iters_out, ppc_stats* stats,
+                     void* stream) {
+    return guarded(h, [&]() -> int {
+        check_handle_problem(h, pr);
+        check_params(p);
+        if (!U_out_dev) fail(PPC_ERR_ARG, "null U_out");
+        return solve_device(h, pr, p, U_init_dev, U_out_dev, resid_out, iters_out, stats,
+                            pick_stream(h, stream));
+    });
+}
+
+int ppc_solve(ppc_handle* h, ppc_problem* pr, const ppc_params* p, const double* U_init,
+              double* U_out, double* resid_out, int32_t* iters_out, ppc_stats* stats) {
+    return guarded(h, [&]() -> int {
+        check_handle_problem(h, pr);
+        check_params(p);
+        if (!U_out) fail(PPC_ERR_ARG, "null U_out");
+        PPC_HIP(hipSetDevice(h->device));
+        const size_t cnt = (size_t)p->N * pr->mesh.n_nodes;
+        double* du = dalloc<double>(cnt);
+        double* di = nullptr;
+        int rc = PPC_OK;
+        try {
+            if (U_init) {
+                di = dalloc<double>(cnt);
+                PPC_HIP(hipMemcpyAsync(di, U_init, cnt * sizeof(double), hipMemcpyHostToDevice, h->stream));
+            }
+            rc = solve_device(h, pr, p, di, du, resid_out, iters_out, stats, h->stream);
+            PPC_HIP(hipMemcpyAsync(U_out, du, cnt * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+            PPC_HIP(hipStreamSynchronize(h->stream));
+        } catch (...) {
+            (void)hipFree(du);
+            if (di) (void)hipFree(di);
+            throw;
+        }
+        (void)hipFree(du);
+        if (di) (void)hipFree(di);
+        return rc;
+    });
+}
+
+int ppc_fine_sweep_device(ppc_handle* h, ppc_problem* pr, const ppc_params* p, const double* U_in_dev,
+                          double* F_out_dev, int32_t* newton_out, int32_t* lin_out, void* stream) {
+    return guarded(h, [&]() -> int {
+        check_handle_problem(h, pr);
+        check_params(p);
+        if (!U_in_dev || !F_out_dev) fail(PPC_ERR_ARG, "null U_in or F_out");
+        PPC_HIP(hipSetDevice(h->device));
+        hipStream_t s = pick_stream(h, stream);
+        ensure_workspace(pr, p);
+        launch_to_free(pr, p->N, U_in_dev, pr->ws.U, s);
+        launch_fine_sweep(pr, p, pr->ws.U, pr->ws.F, s);
+        const SweepCounts c = read_chain_counts(pr, p->N, s, newton_out, lin_out);
+        check_sweep(c);
+        launch_to_nodal(pr, p->N, pr->ws.F, F_out_dev, s);
+        PPC_HIP(hipStreamSynchronize(s));
+        return PPC_OK;
+    });
+}
+
+int ppc_coarse_correction_device(ppc_handle* h, ppc_problem* pr, const ppc_params* p, const double* U_dev,
+                                 const double* J_dev, double* dU_dev, int32_t* cocg_out, void* stream) {
+    return guarded(h, [&]() -> int {
+        check_handle_problem(h, pr);
+        check_params(p);
+        if (!U_dev || !J_dev || !dU_dev) fail(PPC_ERR_ARG, "null U, J or dU");
+        PPC_HIP(hipSetDevice(h->device));
+        hipStream_t s = pick_stream(h, stream);
+        ensure_workspace(pr, p);
+        launch_to_free(pr, p->N, U_dev, pr->ws.U, s);
+        launch_to_free(pr, p->N, J_dev, pr->ws.J, s);
+        launch_coarse(pr, p, pr->ws.U, pr->ws.J, pr->ws.F, false, false, s);
+        read_cocg(pr, p->N / 2 + 1, s, cocg_out, nullptr, nullptr);
+        launch_to_nodal(pr, p->N, pr->ws.F, dU_dev, s);
+        PPC_HIP(hipStreamSynchronize(s));
+        return PPC_OK;
+    });
+}
+
+}  // extern "C"

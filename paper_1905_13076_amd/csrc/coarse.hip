@@ -1,0 +1,500 @@
+// Coarse periodic correction (Section 3) and the per-iteration jumps (Section 2).
+//
+// In the linear case eq. (4) with the implicit-Euler coarse propagator of eq. (8) is
+// the block-cyclic system G U^{k+1} = r^k of eq. (9); since r^k = G U^k + Q J^k with
+// the jumps J_n = F_n - U_n (n mod N), the new iterate is U^{k+1} = U^k + dU with
+//     Q dU_n - C dU_{n-1} = Q J_n    (cyclic in n),   C = M/dT,  Q = C + Kbar  (eq. (10)).
+// The DFT along time (eqs. (11)-(13)) turns G into the blocks Kbar + sigma_p M with
+// sigma_p = (1 - exp(-i w_p dT))/dT, w_p = 2 pi p / T, one independent complex-symmetric
+// system per harmonic p = 0..N/2 (the negative harmonics are the conjugates); the
+// inverse transform (eq. (14)) returns dU.  For a nonlinear problem the paper defers
+// the treatment of the coarse matrices; here Kbar is frozen at the time average over
+// the coarse samples of the differential reluctivity (or of the chord reluctivity).
+//
+// Kernels: jumps + norms (two-level fixed-order reduction), linearisation per element,
+// Kbar by slot gather, coarse right-hand side R_n = Q J_n (the matrix read once per
+// row for all samples), DFT along time with a twiddle table, one workgroup per
+// harmonic running Jacobi-preconditioned COCG in complex FP64 (van der Vorst and
+// Melissen's conjugate-orthogonal CG for complex symmetric matrices), and the inverse
+// DFT fused with the update U += dU.
+#include <cmath>
+
+#include "internal.hpp"
+
+namespace ppc {
+
+namespace {
+constexpr int kRedBlocks = 256;
+
+__device__ inline double2 cmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ inline double2 cdiv(double2 a, double2 b) {
+    const double s = fabs(b.x) > fabs(b.y) ? fabs(b.x) : fabs(b.y);
+    const double bx = b.x / s, by = b.y / s;
+    const double d = bx * bx + by * by;
+    return make_double2((a.x * bx + a.y * by) / d / s, (a.y * bx - a.x * by) / d / s);
+}
+
+template <int K>
+__device__ inline void block_sum_d(double (&v)[K], double* lds, int& phase) {
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    double* buf = lds + phase * 16 * K;
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < K; ++k) buf[w * K + k] = v[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        double s = 0.0;
+        for (int j = 0; j < nw; ++j) s += buf[j * K + k];
+        v[k] = s;
+    }
+    phase ^= 1;
+}
+}  // namespace
+
+// J = F - U over [N][n]; per-block partial sums of ||J||^2, ||U||^2, ||J_0||^2
+__global__ void k_jumps(long total, int n, const double* __restrict__ U, const double* __restrict__ F,
+                        double* __restrict__ J, double* __restrict__ part) {
+    __shared__ double lds[2 * 16 * 3];
+    int ph = 0;
+    double v[3] = {0.0, 0.0, 0.0};
+    for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < total; k += (long)gridDim.x * blockDim.x) {
+        const double j = F[k] - U[k];
+        if (J) J[k] = j;
+        v[0] += j * j;
+        v[1] += U[k] * U[k];
+        if (k < n) v[2] += j * j;
+    }
+    block_sum_d<3>(v, lds, ph);
+    if (threadIdx.x == 0)
+        for (int q = 0; q < 3; ++q) part[3 * blockIdx.x + q] = v[q];
+}
+
+__global__ void k_sum_partials(int nb, int K, const double* __restrict__ part, double* __restrict__ out) {
+    if (threadIdx.x < K) {
+        double s = 0.0;
+        for (int b = 0; b < nb; ++b) s += part[K * b + threadIdx.x];
+        out[threadIdx.x] = s;
+    }
+}
+
+// Per element: time average over the samples of nu I + 2 nu' g g^T (lin_mode 0) or of
+// nu I (lin_mode 1), g = grad A_h.  U null means one sample u = 0.
+__global__ void k_linearise(int ne, int n, int nsamp, const double* __restrict__ U,
+                            const int* __restrict__ efree, const double* __restrict__ gx,
+                            const double* __restrict__ gy, const double* __restrict__ area,
+                            const double* __restrict__ k0, const int* __restrict__ mat,
+                            const double* __restrict__ lawtab, int lin_mode,
+                            double* __restrict__ nub) {
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < ne; e += gridDim.x * blockDim.x) {
+        int g[3];
+        double ax[3], ay[3];
+        for (int q = 0; q < 3; ++q) {
+            g[q] = efree[q * ne + e];
+            ax[q] = gx[q * ne + e];
+            ay[q] = gy[q * ne + e];
+        }
+        const double* L = lawtab + 5 * mat[e];
+        const bool brauer = L[0] != 0.0;
+        double sxx = 0.0, sxy = 0.0, syy = 0.0;
+        const int ns = U ? nsamp : 1;
+        for (int s = 0; s < ns; ++s) {
+            double uv[3];
+            for (int q = 0; q < 3; ++q) uv[q] = (U && g[q] >= 0) ? U[(long)s * n + g[q]] : 0.0;
+            double nu, dnu = 0.0, gxx = 0.0, gyy = 0.0;
+            if (lin_mode == 0) {
+                gxx = ax[0] * uv[0] + ax[1] * uv[1] + ax[2] * uv[2];
+                gyy = ay[0] * uv[0] + ay[1] * uv[1] + ay[2] * uv[2];
+                const double b2 = gxx * gxx + gyy * gyy;
+                if (brauer) {
+                    const double ex = exp(L[3] * b2);
+                    nu = L[2] * ex + L[4];
+                    dnu = L[2] * L[3] * ex;
+                } else {
+                    nu = L[1];
+                }
+            } else {
+                // chord: nu at b2 = u.(K0 u)/A
+                const double k00 = k0[e], k01 = k0[ne + e], k02 = k0[2 * ne + e];
+                const double k11 = k0[3 * ne + e], k12 = k0[4 * ne + e], k22 = k0[5 * ne + e];
+                const double w0 = k00 * uv[0] + k01 * uv[1] + k02 * uv[2];
+                const double w1 = k01 * uv[0] + k11 * uv[1] + k12 * uv[2];
+                const double w2 = k02 * uv[0] + k12 * uv[1] + k22 * uv[2];
+                const double b2 = (uv[0] * w0 + uv[1] * w1 + uv[2] * w2) / area[e];
+                nu = brauer ? L[2] * exp(L[3] * b2) + L[4] : L[1];
+            }
+            sxx += nu + 2.0 * dnu * gxx * gxx;
+            sxy += 2.0 * dnu * gxx * gyy;
+            syy += nu + 2.0 * dnu * gyy * gyy;
+        }
+        nub[e] = sxx / ns;
+        nub[ne + e] = sxy / ns;
+        nub[2 * ne + e] = syy / ns;
+    }
+}
+
+// Kbar_s = sum over contributions (e, a, b) of A_e g_a^T nubar_e g_b
+__global__ void k_kbar(int nnz, int ne, const int* __restrict__ slot_ptr, const int* __restrict__ slot_src,
+                       const double* __restrict__ area, const double* __restrict__ gx,
+                       const double* __restrict__ gy, const double* __restrict__ nub,
+                       double* __restrict__ kbar) {
+    for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < nnz; s += gridDim.x * blockDim.x) {
+        double acc = 0.0;
+        for (int k = slot_ptr[s]; k < slot_ptr[s + 1]; ++k) {
+            const int code = slot_src[k];
+            const int e = code / 9, ab = code - 9 * e;
+            const int qa = ab / 3, qb = ab - 3 * qa;
+            const double xa = gx[qa * ne + e], ya = gy[qa * ne + e];
+            const double xb = gx[qb * ne + e], yb = gy[qb * ne + e];
+            acc += area[e] * (nub[e] * xa * xb + nub[ne + e] * (xa * yb + ya * xb) + nub[2 * ne + e] * ya * yb);
+        }
+        kbar[s] = acc;
+    }
+}
+
+// R[s][i] = sum_k (M_k / dT + Kbar_k) J[s][col_k]
+__global__ void k_coarse_rhs(int n, int N, const int* __restrict__ rowptr, const int* __restrict__ colidx,
+                             const double* __restrict__ mval, const double* __restrict__ kbar,
+                             double inv_dT, const double* __restrict__ J, double* __restrict__ R) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int s = blockIdx.y;
+    if (i >= n || s >= N) return;
+    const double* Js = J + (long)s * n;
+    double acc = 0.0;
+    for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) acc += (mval[k] * inv_dT + kbar[k]) * Js[colidx[k]];
+    R[(long)s * n + i] = acc;
+}
+
+// R[s][i] = i(T_s) F_i with row 0 carrying T_N = T (the coarse excitation rows of eq. (9))
+__global__ void k_excitation_rows(int n, int N, double T, const double* __restrict__ fload,
+                                  const double* __restrict__ wav, int n_h, double f0,
+                                  double* __restrict__ R) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int s = blockIdx.y;
+    if (i >= n || s >= N) return;
+    const double t = s == 0 ? T : s * (T / N);
+    double cur = 0.0;
+    for (int h = 0; h < n_h; ++h) cur = cur + wav[3 * h + 1] * sin(2.0 * M_PI * wav[3 * h] * f0 * t + wav[3 * h + 2]);
+    R[(long)s * n + i] = cur * fload[i];
+}
+
+__global__ void k_twiddle(int N, double2* __restrict__ tw) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= N) return;
+    double s, c;
+    sincospi(2.0 * k / N, &s, &c);
+    tw[k] = make_double2(c, -s);   // exp(-2 pi i k / N)
+}
+
+// Rhat[p][i] = sum_s R[s][i] exp(-2 pi i p s / N), p = 0..N/2
+__global__ void k_dft(int n, int N, const double* __restrict__ R, const double2* __restrict__ tw,
+                      double2* __restrict__ Rh) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int p = blockIdx.y;
+    if (i >= n) return;
+    double re = 0.0, im = 0.0;
+    for (int s = 0; s < N; ++s) {
+        const double r = R[(long)s * n + i];
+        const double2 w = tw[(int)(((long)p * s) % N)];
+        re += r * w.x;
+        im += r * w.y;
+    }
+    Rh[(long)p * n + i] = make_double2(re, im);
+}
+
+// One workgroup per harmonic: (Kbar + sigma_p M) x = b by Jacobi-preconditioned COCG.
+__global__ __launch_bounds__(1024) void k_cocg(int n, int H, const int* __restrict__ rowptr,
+                                               const int* __restrict__ colidx,
+                                               const double* __restrict__ kbar,
+                                               const double* __restrict__ mval,
+                                               const int* __restrict__ diag,
+                                               const double2* __restrict__ sig,
+                                               const double2* __restrict__ B, double2* __restrict__ X,
+                                               double2* __restrict__ work, long n_pad, double tol,
+                                               int max_it, int* __restrict__ count) {
+    __shared__ double lds[2 * 16 * 3];
+    int ph = 0;
+    const int p = blockIdx.x;
+    const double2 sg = sig[p];
+    const double2* b = B + (long)p * n;
+    double2* x = X + (long)p * n;
+    double2* r = work + ((long)p * 4 + 0) * n_pad;
+    double2* pv = work + ((long)p * 4 + 1) * n_pad;
+    double2* q = work + ((long)p * 4 + 2) * n_pad;
+    double2* dv = work + ((long)p * 4 + 3) * n_pad;
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const int d = diag[i];
+        const double2 D = make_double2(kbar[d] + sg.x * mval[d], sg.y * mval[d]);
+        const double2 di = cdiv(make_double2(1.0, 0.0), D);
+        dv[i] = di;
+        const double2 ri = b[i];
+        const double2 zi = cmul(di, ri);
+        r[i] = ri;
+        pv[i] = zi;
+        x[i] = make_double2(0.0, 0.0);
+        const double2 rz = cmul(ri, zi);
+        v[0] += rz.x;
+        v[1] += rz.y;
+        v[2] += ri.x * ri.x + ri.y * ri.y;
+    }
+    block_sum_d<3>(v, lds, ph);
+    double2 rho = make_double2(v[0], v[1]);
+    const double bn2 = v[2];
+    double rr = bn2;
+    const double target2 = tol * tol * bn2;
+    int k = 0, status = 0;
+    constexpr int G = kRowGroup;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int sub = lane % G, grp = lane / G;
+    constexpr int RPW = 64 / G;
+    while (rr > target2 && k < max_it) {
+        // q = (Kbar + sigma M) p ;  mu = p^T q
+        double m2[2] = {0.0, 0.0};
+        for (int base = wave * RPW; base < n; base += nw * RPW) {
+            const int i = base + grp;
+            double ax = 0.0, ay = 0.0, bx = 0.0, by = 0.0;
+            if (i < n) {
+                const int k1 = rowptr[i + 1];
+                for (int kk = rowptr[i] + sub; kk < k1; kk += G) {
+                    const double2 pc = pv[colidx[kk]];
+                    const double kv = kbar[kk], mv = mval[kk];
+                    ax += kv * pc.x;
+                    ay += kv * pc.y;
+                    bx += mv * pc.x;
+                    by += mv * pc.y;
+                }
+            }
+#pragma unroll
+            for (int off = G / 2; off > 0; off >>= 1) {
+                ax += __shfl_xor(ax, off);
+                ay += __shfl_xor(ay, off);
+                bx += __shfl_xor(bx, off);
+                by += __shfl_xor(by, off);
+            }
+            if (i < n && sub == 0) {
+                const double2 qi = make_double2(ax + sg.x * bx - sg.y * by, ay + sg.x * by + sg.y * bx);
+                q[i] = qi;
+                const double2 pq = cmul(pv[i], qi);
+                m2[0] += pq.x;
+                m2[1] += pq.y;
+            }
+        }
+        block_sum_d<2>(m2, lds, ph);
+        const double2 mu = make_double2(m2[0], m2[1]);
+        if (mu.x == 0.0 && mu.y == 0.0) { status = PPC_ERR_BREAKDOWN; break; }
+        const double2 alpha = cdiv(rho, mu);
+        double v2[3] = {0.0, 0.0, 0.0};
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            const double2 pi = pv[i], qi = q[i];
+            const double2 ap = cmul(alpha, pi), aq = cmul(alpha, qi);
+            double2 xi = x[i];
+            xi.x += ap.x;
+            xi.y += ap.y;
+            x[i] = xi;
+            double2 ri = r[i];
+            ri.x -= aq.x;
+            ri.y -= aq.y;
+            r[i] = ri;
+            const double2 rz = cmul(ri, cmul(dv[i], ri));
+            v2[0] += rz.x;
+            v2[1] += rz.y;
+            v2[2] += ri.x * ri.x + ri.y * ri.y;
+        }
+        block_sum_d<3>(v2, lds, ph);
+        const double2 rho_new = make_double2(v2[0], v2[1]);
+        rr = v2[2];
+        ++k;
+        if (rr <= target2) break;
+        if (rho_new.x == 0.0 && rho_new.y == 0.0) { status = PPC_ERR_BREAKDOWN; break; }
+        if (!isfinite(rr)) { status = PPC_ERR_NONFINITE; break; }
+        const double2 beta = cdiv(rho_new, rho);
+        rho = rho_new;
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            const double2 zi = cmul(dv[i], r[i]);
+            const double2 bp = cmul(beta, pv[i]);
+            pv[i] = make_double2(zi.x + bp.x, zi.y + bp.y);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        count[4 * p + 0] = status;
+        count[4 * p + 1] = k;
+        count[4 * p + 2] = (rr <= target2) ? 1 : 0;
+    }
+}
+
+// dU[s][i] = (1/N) [ Re X_0 + (-1)^s Re X_{N/2} + 2 sum_{p=1}^{N/2-1} Re(X_p e^{+2 pi i p s/N}) ]
+// written to out (accumulate: out += dU)
+__global__ void k_idft(int n, int N, const double2* __restrict__ X, const double2* __restrict__ tw,
+                       double* __restrict__ out, int accumulate) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int s = blockIdx.y;
+    if (i >= n) return;
+    const int H = N / 2;
+    double acc = X[i].x;
+    acc += ((s & 1) ? -1.0 : 1.0) * X[(long)H * n + i].x;
+    double sum = 0.0;
+    for (int p = 1; p < H; ++p) {
+        const double2 xp = X[(long)p * n + i];
+        const double2 w = tw[(int)(((long)p * s) % N)];   // exp(-i theta); use its conjugate
+        sum += xp.x * w.x + xp.y * w.y;                     // Re(x e^{+i theta})
+    }
+    acc += 2.0 * sum;
+    const double du = acc / N;
+    const long k = (long)s * n + i;
+    if (accumulate) out[k] += du;
+    else out[k] = du;
+}
+
+__global__ void k_to_nodal(int n, int nn, int N, const int* __restrict__ free_node,
+                           const double* __restrict__ Uf, double* __restrict__ Un) {
+    const long total = (long)N * nn;
+    for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < total; k += (long)gridDim.x * blockDim.x)
+        Un[k] = 0.0;
+}
+
+__global__ void k_scatter_free(int n, int nn, int N, const int* __restrict__ free_node,
+                               const double* __restrict__ Uf, double* __restrict__ Un) {
+    const long total = (long)N * n;
+    for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < total; k += (long)gridDim.x * blockDim.x) {
+        const long s = k / n;
+        const int i = (int)(k - s * n);
+        Un[s * nn + free_node[i]] = Uf[k];
+    }
+}
+
+__global__ void k_gather_free(int n, int nn, int N, const int* __restrict__ free_node,
+                              const double* __restrict__ Un, double* __restrict__ Uf) {
+    const long total = (long)N * n;
+    for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < total; k += (long)gridDim.x * blockDim.x) {
+        const long s = k / n;
+        const int i = (int)(k - s * n);
+        Uf[k] = Un[s * nn + free_node[i]];
+    }
+}
+
+// max |B| over Brauer elements and samples (per-block partial maxima)
+__global__ void k_max_b(int ne, int n, int N, const double* __restrict__ U, const int* __restrict__ efree,
+                        const double* __restrict__ gx, const double* __restrict__ gy,
+                        const int* __restrict__ mat, const double* __restrict__ lawtab,
+                        double* __restrict__ part) {
+    __shared__ double red[1024];
+    double mx = 0.0;
+    const long total = (long)N * ne;
+    for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < total; k += (long)gridDim.x * blockDim.x) {
+        const long s = k / ne;
+        const int e = (int)(k - s * ne);
+        if (lawtab[5 * mat[e]] == 0.0) continue;
+        double bx = 0.0, by = 0.0;
+        for (int q = 0; q < 3; ++q) {
+            const int g = efree[q * ne + e];
+            const double uv = g >= 0 ? U[s * n + g] : 0.0;
+            bx += gx[q * ne + e] * uv;
+            by += gy[q * ne + e] * uv;
+        }
+        mx = fmax(mx, sqrt(bx * bx + by * by));
+    }
+    red[threadIdx.x] = mx;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void k_max_partials(int nb, const double* __restrict__ part, double* __restrict__ out) {
+    if (threadIdx.x == 0) {
+        double m = 0.0;
+        for (int b = 0; b < nb; ++b) m = fmax(m, part[b]);
+        out[0] = m;
+    }
+}
+
+// ------------------------------------------------------------------------------------
+// host launchers
+// ------------------------------------------------------------------------------------
+void launch_jumps(ppc_problem* pr, int N, const double* U, const double* F, double* J,
+                  double* out3, hipStream_t s) {
+    const int n = pr->mesh.n_free;
+    const long total = (long)N * n;
+    hipLaunchKernelGGL(k_jumps, dim3(kRedBlocks), dim3(256), 0, s, total, n, U, F, J, pr->ws.partial);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, s, kRedBlocks, 3, pr->ws.partial, out3);
+    PPC_HIP(hipGetLastError());
+}
+
+void launch_coarse(ppc_problem* pr, const ppc_params* p, const double* U, const double* J,
+                   double* dU, bool accumulate, bool excitation_rhs, hipStream_t s) {
+    const DeviceMesh& d = pr->mesh;
+    Workspace& w = pr->ws;
+    const int n = d.n_free, ne = d.n_tri, N = p->N, H = N / 2 + 1;
+    const double dT = p->T / N;
+    const int eb = 256;
+    const int eg = std::max(1, std::min((ne + eb - 1) / eb, 4096));
+    hipLaunchKernelGGL(k_linearise, dim3(eg), dim3(eb), 0, s, ne, n, N, excitation_rhs ? nullptr : U,
+                       d.efree, d.gx, d.gy, d.area, d.k0, d.mat, pr->lawtab, p->lin_mode, w.nubar);
+    const int sg = std::max(1, std::min((d.nnz + eb - 1) / eb, 4096));
+    hipLaunchKernelGGL(k_kbar, dim3(sg), dim3(eb), 0, s, d.nnz, ne, d.slot_ptr, d.slot_src, d.area, d.gx,
+                       d.gy, w.nubar, w.kbar);
+    const dim3 rg((n + 255) / 256, N);
+    if (excitation_rhs)
+        hipLaunchKernelGGL(k_excitation_rows, rg, dim3(256), 0, s, n, N, p->T, d.fload, pr->wavtab,
+                           pr->wave.n_h, pr->wave.f0, w.R);
+    else
+        hipLaunchKernelGGL(k_coarse_rhs, rg, dim3(256), 0, s, n, N, d.rowptr, d.colidx, d.mval, w.kbar,
+                           1.0 / dT, J, w.R);
+    hipLaunchKernelGGL(k_twiddle, dim3((N + 255) / 256), dim3(256), 0, s, N, w.twiddle);
+    hipLaunchKernelGGL(k_dft, dim3((n + 255) / 256, H), dim3(256), 0, s, n, N, w.R, w.twiddle, w.rhat);
+    // shifts sigma_p on the host: p = 0..N/2
+    std::vector<double2> sig(H);
+    for (int q = 0; q < H; ++q) {
+        if (p->shift_mode == 0) {
+            const double th = 2.0 * M_PI * q / N;
+            sig[q] = make_double2((1.0 - std::cos(th)) / dT, std::sin(th) / dT);
+        } else {
+            sig[q] = make_double2(0.0, 2.0 * M_PI * q / p->T);
+        }
+    }
+    PPC_HIP(hipMemcpyAsync(w.sig, sig.data(), H * sizeof(double2), hipMemcpyHostToDevice, s));
+    double2* X = w.rhat + (long)H * n;   // solution block follows the right-hand sides
+    hipLaunchKernelGGL(k_cocg, dim3(H), dim3(kCocgBlock), 0, s, n, H, d.rowptr, d.colidx, w.kbar, d.mval,
+                       d.diag, w.sig, w.rhat, X, w.cwork, (long)w.n_pad, p->tol_cocg, p->max_cocg,
+                       w.ccount);
+    hipLaunchKernelGGL(k_idft, dim3((n + 255) / 256, N), dim3(256), 0, s, n, N, X, w.twiddle, dU,
+                       accumulate ? 1 : 0);
+    PPC_HIP(hipGetLastError());
+}
+
+void launch_to_nodal(const ppc_problem* pr, int N, const double* Ufree, double* Unodal,
+                     hipStream_t s) {
+    const DeviceMesh& d = pr->mesh;
+    hipLaunchKernelGGL(k_to_nodal, dim3(1024), dim3(256), 0, s, d.n_free, d.n_nodes, N, d.free_node,
+                       Ufree, Unodal);
+    hipLaunchKernelGGL(k_scatter_free, dim3(1024), dim3(256), 0, s, d.n_free, d.n_nodes, N, d.free_node,
+                       Ufree, Unodal);
+    PPC_HIP(hipGetLastError());
+}
+
+void launch_to_free(const ppc_problem* pr, int N, const double* Unodal, double* Ufree,
+                    hipStream_t s) {
+    const DeviceMesh& d = pr->mesh;
+    hipLaunchKernelGGL(k_gather_free, dim3(1024), dim3(256), 0, s, d.n_free, d.n_nodes, N, d.free_node,
+                       Unodal, Ufree);
+    PPC_HIP(hipGetLastError());
+}
+
+void launch_max_b(ppc_problem* pr, int N, const double* U, double* out, hipStream_t s) {
+    const DeviceMesh& d = pr->mesh;
+    hipLaunchKernelGGL(k_max_b, dim3(kRedBlocks), dim3(256), 0, s, d.n_tri, d.n_free, N, U, d.efree, d.gx,
+                       d.gy, d.mat, pr->lawtab, pr->ws.partial);
+    hipLaunchKernelGGL(k_max_partials, dim3(1), dim3(64), 0, s, kRedBlocks, pr->ws.partial, out);
+    PPC_HIP(hipGetLastError());
+}
+
+}  // namespace ppc

@@ -1,0 +1,447 @@
+// Fine sweep: all N fine propagators F_n (Section 2, eqs. (2)-(3)) in one launch.
+//
+// One workgroup owns one chain n = 1..N: it starts from U_{n-1} at T_{n-1} and takes
+// m implicit-Euler steps of size dt = T/(N m).  Each step solves
+//     R(u) = M (u - u_prev)/dt + K(u) u - i(t_j) F = 0,   t_j = T_{n-1} + j dt,
+// by damped Newton with the exact Jacobian
+//     J = M/dt + sum_e [ nu_e K0_e + (2 nu'_e / A_e) (K0_e u_e)(K0_e u_e)^T ],
+// (nu' = d nu / d|B|^2) assembled element-wise into CSR values by a deterministic gather
+// over a slot -> contribution list (no atomics), and solved by Jacobi-PCG.
+//
+// Mapping to CDNA: the chain's vectors, Jacobian values and element scratch live in HBM
+// (L2 / MALL resident for small meshes); every phase is a workgroup-wide pass with
+// coalesced row / element streams; the CSR SpMV gives kRowGroup lanes of a 64-wide
+// wave to each row so that value and column streams are read contiguously; dot
+// products are wave-shuffle trees followed by a fixed-order sum over the waves, so
+// results are bitwise reproducible.  The PCG scalar type S is double (FP64 form) or
+// float (mixed form: FP32 Jacobian and PCG, FP64 Newton residual refining it).
+#include <cfloat>
+#include <cmath>
+
+#include "internal.hpp"
+
+namespace ppc {
+
+struct FineArgs {
+    int n, ne, nnz, N, m;
+    double T, dt, fnorm;
+    double tol_newton, tol_lin;
+    int max_newton, max_lin;
+    const int* rowptr;
+    const int* colidx;
+    const int* diag;
+    const int* slot_ptr;
+    const int* slot_src;
+    const int* node_ptr;
+    const int* node_src;
+    const int* efree;
+    const int* mat;
+    const double* area;
+    const double* k0;
+    const double* sigma;
+    const double* mval;
+    const double* fload;
+    const double* lawtab;   // [n_mat][5]: law, nu, k1, k2, k3
+    const double* wavtab;   // [n_h][3]: order, amp, phase
+    int n_h;
+    double f0;
+    const double* U;        // [N][n]
+    double* F;              // [N][n]
+    double* vec;            // [N][kFineVec][n_pad]
+    void* pcg;              // [N][kPcgVec][n_pad] of S
+    void* jac;              // [N][nnz_pad] of S
+    double* elem;           // [N][8][ne_pad]
+    int* count;             // [N][8]
+    long n_pad, nnz_pad, ne_pad;
+};
+
+// Imposed current i(t) = sum_h amp_h sin(2 pi order_h f0 t + phase_h).
+__device__ inline double current(double t, double f0, int n_h, const double* __restrict__ w) {
+    double s = 0.0;
+    for (int h = 0; h < n_h; ++h) s = s + w[3 * h + 1] * sin(2.0 * M_PI * w[3 * h] * f0 * t + w[3 * h + 2]);
+    return s;
+}
+
+// Brauer / linear reluctivity and its derivative with respect to b2 = |B|^2.
+__device__ inline void reluct(const double* __restrict__ lawtab, int mid, double b2, double& nu,
+                              double& dnu) {
+    const double* L = lawtab + 5 * mid;
+    if (L[0] == 0.0) {
+        nu = L[1];
+        dnu = 0.0;
+    } else {
+        const double e = exp(L[3] * b2);
+        nu = L[2] * e + L[4];
+        dnu = L[2] * L[3] * e;
+    }
+}
+
+// Sum of K values over the workgroup in a fixed order; every thread gets the result.
+template <typename T, int K>
+__device__ inline void block_sum(T (&v)[K], T* lds, int& phase) {
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    T* buf = lds + phase * 16 * K;
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < K; ++k) buf[w * K + k] = v[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        T s = 0;
+        for (int j = 0; j < nw; ++j) s += buf[j * K + k];
+        v[k] = s;
+    }
+    phase ^= 1;
+}
+
+enum { E_F0 = 0, E_W0 = 3, E_NU = 6, E_SF = 7 };
+enum { V_U = 0, V_UP = 1, V_R = 2, V_RT = 3 };
+enum { P_R = 0, P_P = 1, P_Q = 2, P_X = 3, P_D = 4 };
+enum { C_STATUS = 0, C_NEWTON = 1, C_LIN = 2, C_NEWTON_MAX = 3, C_LIN_MAX = 4, C_CAPPED = 5,
+       C_FAILSTEP = 6 };
+
+// Element pass at ut = u + lam du (du may be null): w = K0 ut, b2 = ut.w/A, nu, nu',
+// and the element force nu w_a + (M_e (ut - u_prev))_a / dt.
+template <typename D>
+__device__ inline void element_pass(const FineArgs& a, const double* __restrict__ u,
+                                    const D* __restrict__ du, double lam,
+                                    const double* __restrict__ up, double* __restrict__ el,
+                                    double inv_dt) {
+    const int ne = a.ne;
+    const long P = a.ne_pad;
+    for (int e = threadIdx.x; e < ne; e += blockDim.x) {
+        double ut[3], d[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const int g = a.efree[q * ne + e];
+            double v = 0.0, vp = 0.0;
+            if (g >= 0) {
+                v = u[g];
+                if (du) v = v + lam * (double)du[g];
+                vp = up[g];
+            }
+            ut[q] = v;
+            d[q] = v - vp;
+        }
+        const double k00 = a.k0[e], k01 = a.k0[ne + e], k02 = a.k0[2 * ne + e];
+        const double k11 = a.k0[3 * ne + e], k12 = a.k0[4 * ne + e], k22 = a.k0[5 * ne + e];
+        const double w0 = k00 * ut[0] + k01 * ut[1] + k02 * ut[2];
+        const double w1 = k01 * ut[0] + k11 * ut[1] + k12 * ut[2];
+        const double w2 = k02 * ut[0] + k12 * ut[1] + k22 * ut[2];
+        const double A = a.area[e];
+        const double b2 = (ut[0] * w0 + ut[1] * w1 + ut[2] * w2) / A;
+        double nu, dnu;
+        reluct(a.lawtab, a.mat[e], b2, nu, dnu);
+        const double cm = a.sigma[e] * A / 12.0;
+        const double ds = d[0] + d[1] + d[2];
+        el[(E_F0 + 0) * P + e] = nu * w0 + cm * (d[0] + ds) * inv_dt;
+        el[(E_F0 + 1) * P + e] = nu * w1 + cm * (d[1] + ds) * inv_dt;
+        el[(E_F0 + 2) * P + e] = nu * w2 + cm * (d[2] + ds) * inv_dt;
+        el[(E_W0 + 0) * P + e] = w0;
+        el[(E_W0 + 1) * P + e] = w1;
+        el[(E_W0 + 2) * P + e] = w2;
+        el[E_NU * P + e] = nu;
+        el[E_SF * P + e] = 2.0 * dnu / A;
+    }
+}
+
+// Node pass: R_i = sum of incident element forces - i(t) F_i; returns partial ||R||^2.
+__device__ inline double node_pass(const FineArgs& a, const double* __restrict__ el, double cur,
+                                   double* __restrict__ R) {
+    const long P = a.ne_pad;
+    double part = 0.0;
+    for (int i = threadIdx.x; i < a.n; i += blockDim.x) {
+        double acc = 0.0;
+        for (int k = a.node_ptr[i]; k < a.node_ptr[i + 1]; ++k) {
+            const int code = a.node_src[k];
+            const int e = code / 3, q = code - 3 * e;
+            acc += el[(E_F0 + q) * P + e];
+        }
+        acc = acc - cur * a.fload[i];
+        R[i] = acc;
+        part += acc * acc;
+    }
+    return part;
+}
+
+// Jacobian values by slot gather, then the Jacobi inverse diagonal.
+template <typename S>
+__device__ inline void assemble(const FineArgs& a, const double* __restrict__ el, double inv_dt,
+                                S* __restrict__ jv, S* __restrict__ dinv) {
+    const long P = a.ne_pad;
+    const int ne = a.ne;
+    for (int s = threadIdx.x; s < a.nnz; s += blockDim.x) {
+        double acc = a.mval[s] * inv_dt;
+        for (int k = a.slot_ptr[s]; k < a.slot_ptr[s + 1]; ++k) {
+            const int code = a.slot_src[k];
+            const int e = code / 9, ab = code - 9 * e;
+            const int qa = ab / 3, qb = ab - 3 * qa;
+            const int lo = qa < qb ? qa : qb, hi = qa < qb ? qb : qa;
+            const int kidx = lo == 0 ? hi : (lo == 1 ? 2 + hi : 5);
+            acc += el[E_NU * P + e] * a.k0[kidx * ne + e] +
+                   el[E_SF * P + e] * el[(E_W0 + qa) * P + e] * el[(E_W0 + qb) * P + e];
+        }
+        jv[s] = (S)acc;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < a.n; i += blockDim.x) dinv[i] = (S)1 / jv[a.diag[i]];
+}
+
+// q = J p on kRowGroup lanes per row; returns this lane's partial of p.q
+template <typename S>
+__device__ inline S spmv_dot(int n, const int* __restrict__ rowptr, const int* __restrict__ colidx,
+                             const S* __restrict__ val, const S* __restrict__ p, S* __restrict__ q) {
+    constexpr int G = kRowGroup;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int sub = lane % G, grp = lane / G;
+    constexpr int RPW = 64 / G;
+    S part = 0;
+    for (int base = wave * RPW; base < n; base += nw * RPW) {
+        const int i = base + grp;
+        S acc = 0;
+        if (i < n) {
+            const int k1 = rowptr[i + 1];
+            for (int k = rowptr[i] + sub; k < k1; k += G) acc += val[k] * p[colidx[k]];
+        }
+#pragma unroll
+        for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+        if (i < n && sub == 0) {
+            q[i] = acc;
+            part += p[i] * acc;
+        }
+    }
+    return part;
+}
+
+// ||M x||^2 partial, same lane-group layout (used for the step's residual scale)
+__device__ inline double mass_norm2(const FineArgs& a, const double* __restrict__ x) {
+    constexpr int G = kRowGroup;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int sub = lane % G, grp = lane / G;
+    constexpr int RPW = 64 / G;
+    double part = 0.0;
+    for (int base = wave * RPW; base < a.n; base += nw * RPW) {
+        const int i = base + grp;
+        double acc = 0.0;
+        if (i < a.n) {
+            const int k1 = a.rowptr[i + 1];
+            for (int k = a.rowptr[i] + sub; k < k1; k += G) acc += a.mval[k] * x[a.colidx[k]];
+        }
+#pragma unroll
+        for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+        if (i < a.n && sub == 0) part += acc * acc;
+    }
+    return part;
+}
+
+template <typename S>
+__global__ __launch_bounds__(1024) void k_fine_sweep(FineArgs a) {
+    __shared__ double lds_d[2 * 16 * 4];
+    __shared__ S lds_s[2 * 16 * 4];
+    int ph_d = 0, ph_s = 0;
+    const int c = blockIdx.x;                 // chain n = c + 1
+    const int n = a.n;
+    const long NP = a.n_pad;
+    double* vec = a.vec + (long)c * kFineVec * NP;
+    double* u = vec + V_U * NP;
+    double* up = vec + V_UP * NP;
+    double* R = vec + V_R * NP;
+    double* Rt = vec + V_RT * NP;
+    S* pv = reinterpret_cast<S*>(a.pcg) + (long)c * kPcgVec * NP;
+    S* pr = pv + P_R * NP;
+    S* pp = pv + P_P * NP;
+    S* pq = pv + P_Q * NP;
+    S* px = pv + P_X * NP;
+    S* pd = pv + P_D * NP;
+    S* jv = reinterpret_cast<S*>(a.jac) + (long)c * a.nnz_pad;
+    double* el = a.elem + (long)c * 8 * a.ne_pad;
+
+    const double* U0 = a.U + (long)c * n;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) u[i] = U0[i];
+    __syncthreads();
+
+    const double t0 = (double)c * (a.T / a.N);
+    const double inv_dt = 1.0 / a.dt;
+    int status = 0, fail_step = -1;
+    int newton_total = 0, lin_total = 0, newton_max = 0, lin_max = 0, capped = 0;
+
+    for (int j = 1; j <= a.m && status == 0; ++j) {
+        const double t = t0 + j * a.dt;
+        for (int i = threadIdx.x; i < n; i += blockDim.x) up[i] = u[i];
+        __syncthreads();
+        const double cur = current(t, a.f0, a.n_h, a.wavtab);
+        double v1[1] = {mass_norm2(a, up)};
+        block_sum<double, 1>(v1, lds_d, ph_d);
+        const double scale = fabs(cur) * a.fnorm + sqrt(v1[0]) / a.dt;
+        const double target = a.tol_newton * scale;
+
+        element_pass<double>(a, u, nullptr, 0.0, up, el, inv_dt);
+        __syncthreads();
+        double v2[1] = {node_pass(a, el, cur, R)};
+        block_sum<double, 1>(v2, lds_d, ph_d);
+        double rn = sqrt(v2[0]);
+        if (!isfinite(rn)) { status = PPC_ERR_NONFINITE; fail_step = j; break; }
+
+        int it = 0;
+        for (;; ++it) {
+            if (rn <= target) break;
+            if (it == a.max_newton) { status = PPC_ERR_NEWTON; fail_step = j; break; }
+            assemble<S>(a, el, inv_dt, jv, pd);
+            __syncthreads();
+            // ---- Jacobi-PCG on J x = -R, x0 = 0 -------------------------------------------
+            S loc[2] = {0, 0};
+            for (int i = threadIdx.x; i < n; i += blockDim.x) {
+                const S r = (S)(-R[i]);
+                const S z = pd[i] * r;
+                pr[i] = r;
+                pp[i] = z;
+                px[i] = 0;
+                loc[0] += r * z;
+                loc[1] += r * r;
+            }
+            block_sum<S, 2>(loc, lds_s, ph_s);
+            S rz = loc[0];
+            double rr = (double)loc[1];
+            const double ltarget = fmax(a.tol_lin * rn, 0.5 * target);
+            int k = 0;
+            while (rr > ltarget * ltarget && k < a.max_lin) {
+                S pqv[1] = {spmv_dot<S>(n, a.rowptr, a.colidx, jv, pp, pq)};
+                block_sum<S, 1>(pqv, lds_s, ph_s);
+                if (!(pqv[0] > (S)0)) break;            // loss of positivity: stop, Newton decides
+                const S alpha = rz / pqv[0];
+                S l2[2] = {0, 0};
+                for (int i = threadIdx.x; i < n; i += blockDim.x) {
+                    px[i] += alpha * pp[i];
+                    const S r = pr[i] - alpha * pq[i];
+                    pr[i] = r;
+                    l2[0] += r * (pd[i] * r);
+                    l2[1] += r * r;
+                }
+                block_sum<S, 2>(l2, lds_s, ph_s);
+                const S beta = l2[0] / rz;
+                rz = l2[0];
+                rr = (double)l2[1];
+                for (int i = threadIdx.x; i < n; i += blockDim.x) pp[i] = pd[i] * pr[i] + beta * pp[i];
+                __syncthreads();
+                ++k;
+            }
+            lin_total += k;
+            lin_max = k > lin_max ? k : lin_max;
+            if (k == a.max_lin) ++capped;
+            // ---- Newton update with backtracking -------------------------------------------
+            double nrm[2] = {0.0, 0.0};
+            for (int i = threadIdx.x; i < n; i += blockDim.x) {
+                const double dv = (double)px[i];
+                nrm[0] += dv * dv;
+                nrm[1] += u[i] * u[i];
+            }
+            block_sum<double, 2>(nrm, lds_d, ph_d);
+            if (sqrt(nrm[0]) <= 4.0 * DBL_EPSILON * sqrt(nrm[1])) {
+                for (int i = threadIdx.x; i < n; i += blockDim.x) u[i] = u[i] + (double)px[i];
+                __syncthreads();
+                ++it;
+                break;
+            }
+            double lam = 1.0;
+            double rt = 0.0;
+            bool accepted = false, stalled = false;
+            while (true) {
+                element_pass<S>(a, u, px, lam, up, el, inv_dt);
+                __syncthreads();
+                double v3[1] = {node_pass(a, el, cur, Rt)};
+                block_sum<double, 1>(v3, lds_d, ph_d);
+                rt = sqrt(v3[0]);
+                if (rt <= (1.0 - 1e-4 * lam) * rn) { accepted = true; break; }
+                lam *= 0.5;
+                if (lam < 0x1p-20) { stalled = true; break; }
+            }
+            if (stalled) {
+                if (rn <= 1e3 * target) { ++it; break; }
+                status = isfinite(rt) ? PPC_ERR_NEWTON : PPC_ERR_NONFINITE;
+                fail_step = j;
+                break;
+            }
+            if (accepted) {
+                for (int i = threadIdx.x; i < n; i += blockDim.x) u[i] = u[i] + lam * (double)px[i];
+                double* tmp = R;
+                R = Rt;
+                Rt = tmp;
+                rn = rt;
+                __syncthreads();
+            }
+        }
+        newton_total += it;
+        newton_max = it > newton_max ? it : newton_max;
+    }
+
+    double* Fo = a.F + (long)((c + 1) % a.N) * n;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) Fo[i] = u[i];
+    if (threadIdx.x == 0) {
+        int* cnt = a.count + 8 * c;
+        cnt[C_STATUS] = status;
+        cnt[C_NEWTON] = newton_total;
+        cnt[C_LIN] = lin_total;
+        cnt[C_NEWTON_MAX] = newton_max;
+        cnt[C_LIN_MAX] = lin_max;
+        cnt[C_CAPPED] = capped;
+        cnt[C_FAILSTEP] = fail_step;
+    }
+}
+
+void launch_fine_sweep(ppc_problem* pr, const ppc_params* p, const double* U, double* F,
+                       hipStream_t s) {
+    const DeviceMesh& d = pr->mesh;
+    Workspace& w = pr->ws;
+    FineArgs a{};
+    a.n = d.n_free;
+    a.ne = d.n_tri;
+    a.nnz = d.nnz;
+    a.N = p->N;
+    a.m = p->m;
+    a.T = p->T;
+    a.dt = p->T / (double)(p->N * p->m);
+    a.fnorm = d.fnorm;
+    a.tol_newton = p->tol_newton;
+    a.tol_lin = p->tol_lin;
+    a.max_newton = p->max_newton;
+    a.max_lin = p->max_lin;
+    a.rowptr = d.rowptr;
+    a.colidx = d.colidx;
+    a.diag = d.diag;
+    a.slot_ptr = d.slot_ptr;
+    a.slot_src = d.slot_src;
+    a.node_ptr = d.node_ptr;
+    a.node_src = d.node_src;
+    a.efree = d.efree;
+    a.mat = d.mat;
+    a.area = d.area;
+    a.k0 = d.k0;
+    a.sigma = d.sigma;
+    a.mval = d.mval;
+    a.fload = d.fload;
+    a.lawtab = pr->lawtab;
+    a.wavtab = pr->wavtab;
+    a.n_h = pr->wave.n_h;
+    a.f0 = pr->wave.f0;
+    a.U = U;
+    a.F = F;
+    a.vec = w.fvec;
+    a.pcg = w.fpcg;
+    a.jac = w.fjac;
+    a.elem = w.felem;
+    a.count = w.fcount;
+    a.n_pad = (long)w.n_pad;
+    a.nnz_pad = (long)w.nnz_pad;
+    a.ne_pad = (long)w.ne_pad;
+    const int block = p->block > 0 ? p->block : kFineBlock;
+    if (p->precision == 0)
+        hipLaunchKernelGGL(k_fine_sweep<double>, dim3(p->N), dim3(block), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_fine_sweep<float>, dim3(p->N), dim3(block), 0, s, a);
+    PPC_HIP(hipGetLastError());
+}
+
+}  // namespace ppc

@@ -1,0 +1,166 @@
+// Internal declarations of the PP-PC library (not part of the C-ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/ppcmh.h"
+
+namespace ppc {
+
+constexpr int kMaxHarmonicTerms = 16;   // terms of the excitation waveform i(t)
+constexpr int kMaxMaterials = 64;   // validated bound of the material table
+constexpr int kFineBlock = 1024;        // default fine-kernel workgroup
+constexpr int kCocgBlock = 1024;
+constexpr int kRowGroup = 8;            // lanes per CSR row in the vector SpMV
+
+// ----------------------------------------------------------------------------------
+// error plumbing: every internal failure throws ppc::Error, caught at the C-ABI
+// ----------------------------------------------------------------------------------
+struct Error {
+    int code;
+    std::string msg;
+};
+
+[[noreturn]] void fail(int code, const std::string& msg);
+void hip_check(hipError_t e, const char* what);
+#define PPC_HIP(call) ::ppc::hip_check((call), #call)
+
+// Waveform of the imposed current, passed by value to kernels.
+struct Wave {
+    double f0;
+    int n_h;
+    int order[kMaxHarmonicTerms];
+    double amp[kMaxHarmonicTerms];
+    double phase[kMaxHarmonicTerms];
+};
+
+// Material laws, passed by value to kernels.
+struct Laws {
+    int n_mat;
+    int law[kMaxMaterials];
+    double nu[kMaxMaterials], k1[kMaxMaterials], k2[kMaxMaterials], k3[kMaxMaterials];
+};
+
+// Device-resident problem: pattern, maps and element geometry.  Element arrays are
+// stored as planes (structure of arrays) of length n_tri.
+struct DeviceMesh {
+    int n_nodes = 0, n_tri = 0, n_free = 0, nnz = 0;
+    int max_row = 0;           // longest CSR row
+    // CSR pattern of the free block
+    int* rowptr = nullptr;     // [n_free + 1]
+    int* colidx = nullptr;     // [nnz]
+    int* diag = nullptr;       // [n_free] slot of the diagonal entry
+    // slot -> element contributions, each coded e*9 + a*3 + b
+    int* slot_ptr = nullptr;   // [nnz + 1]
+    int* slot_src = nullptr;   // [n_contrib]
+    // free node -> incident (element, local vertex), coded e*3 + a
+    int* node_ptr = nullptr;   // [n_free + 1]
+    int* node_src = nullptr;   // [3 * n_tri] (only free vertices)
+    int* efree = nullptr;      // [3][n_tri] free index of each vertex, -1 on Dirichlet
+    int* free_node = nullptr;  // [n_free] mesh node of each free index
+    int* mat = nullptr;        // [n_tri]
+    double* xy = nullptr;      // [2 * n_nodes]
+    int* tri = nullptr;        // [3 * n_tri]
+    // geometry (set-up kernel)
+    double* area = nullptr;    // [n_tri]
+    double* k0 = nullptr;      // [6][n_tri]: K0 entries 00 01 02 11 12 22
+    double* gx = nullptr;      // [3][n_tri] d(phi_a)/dx
+    double* gy = nullptr;      // [3][n_tri] d(phi_a)/dy
+    double* sigma = nullptr;   // [n_tri]
+    double* js = nullptr;      // [n_tri]
+    double* mval = nullptr;    // [nnz] conductivity mass M
+    double* mdiag = nullptr;   // [n_free]
+    double* fload = nullptr;   // [n_free] load per ampere F
+    double fnorm = 0.0;        // ||F||_2
+    bool nonlinear = false;    // any element with a Brauer law
+    int n_contrib = 0;
+};
+
+void mesh_free(DeviceMesh& d);
+
+struct Workspace {
+    int N = -1, precision = -1;
+    // fine sweep
+    double* fvec = nullptr;    // [N][kFineVec][n_pad] FP64 Newton vectors
+    void* fpcg = nullptr;      // [N][kPcgVec][n_pad] PCG vectors (FP64 or FP32)
+    void* fjac = nullptr;      // [N][nnz_pad] Jacobian values
+    double* felem = nullptr;   // [N][8][ne_pad] element scratch
+    int* fcount = nullptr;     // [N][8] counters per chain
+    // PP-PC state (free layout [N][n_free])
+    double* U = nullptr;
+    double* F = nullptr;
+    double* J = nullptr;
+    double* R = nullptr;
+    // coarse
+    double* kbar = nullptr;    // [nnz]
+    double* nubar = nullptr;   // [3][n_tri]
+    double2* rhat = nullptr;   // [2][H][n_free]: right-hand sides, then solutions
+    double2* cwork = nullptr;  // [H][4][n_pad] COCG vectors r p q dinv
+    double2* sig = nullptr;    // [H] shifts sigma_p
+    int* ccount = nullptr;     // [H][4]
+    double2* twiddle = nullptr;// [N]
+    double* partial = nullptr; // reduction partials
+    double* scal = nullptr;    // small scalars
+    double* host_scal = nullptr; // pinned host mirror
+    size_t n_pad = 0, nnz_pad = 0, ne_pad = 0;
+};
+
+void workspace_free(Workspace& w);
+
+}  // namespace ppc
+
+struct ppc_handle {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    hipEvent_t ev[8] = {};
+    std::string last_error;
+    int n_problems = 0;
+};
+
+struct ppc_problem {
+    ppc_handle* h = nullptr;
+    ppc::DeviceMesh mesh;
+    ppc::Wave wave{};
+    ppc::Laws laws{};
+    ppc::Workspace ws;
+    std::vector<int> free_of_node;   // host map node -> free index (-1 Dirichlet)
+    std::vector<int> nl_elem;        // host list of Brauer elements
+    double* lawtab = nullptr;        // device [n_mat][5]: law, nu, k1, k2, k3
+    double* wavtab = nullptr;        // device [n_h][3]: order, amp, phase
+};
+
+namespace ppc {
+
+constexpr int kFineVec = 4;   // u, uprev, R, du(FP64 copy)
+constexpr int kPcgVec = 5;    // r, p, q, x, dinv
+
+// set-up (setup.hip)
+void build_problem(ppc_problem* pr, const ppc_mesh* mesh, const ppc_material* mat,
+                   const ppc_excitation* exc, hipStream_t s);
+int validate_problem(const ppc_mesh* mesh, const ppc_material* mat, const ppc_excitation* exc,
+                     std::string& msg);
+int validate_params(const ppc_params* p, std::string& msg);
+
+// workspace sizing (api.hip)
+void ensure_workspace(ppc_problem* pr, const ppc_params* p);
+
+// fine sweep (fine.hip): F[n mod N] = F_n(U[n-1]) for all chains, one launch
+void launch_fine_sweep(ppc_problem* pr, const ppc_params* p, const double* U, double* F,
+                       hipStream_t s);
+
+// coarse correction pieces (coarse.hip)
+void launch_jumps(ppc_problem* pr, int N, const double* U, const double* F, double* J,
+                  double* out3, hipStream_t s);
+void launch_coarse(ppc_problem* pr, const ppc_params* p, const double* U, const double* J,
+                   double* dU, bool accumulate, bool excitation_rhs, hipStream_t s);
+void launch_to_nodal(const ppc_problem* pr, int N, const double* Ufree, double* Unodal,
+                     hipStream_t s);
+void launch_to_free(const ppc_problem* pr, int N, const double* Unodal, double* Ufree,
+                    hipStream_t s);
+void launch_max_b(ppc_problem* pr, int N, const double* U, double* out, hipStream_t s);
+
+}  // namespace ppc

@@ -1,0 +1,225 @@
+"""Python binding of the PP-PC library: argument marshalling over the C-ABI.
+
+Every step of the method runs in the HIP library; this module only converts arrays,
+passes device pointers of torch CUDA tensors and the current torch stream, and turns
+status codes into exceptions.  There is no CPU fallback: without the built library
+every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+from ctypes import byref, c_char_p, c_int32, c_void_p
+
+import numpy as np
+
+from . import _native as nat
+
+
+class PPCError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"[{nat.STATUS_NAMES.get(code, code)}] {msg}")
+        self.code = code
+
+
+def lib():
+    return nat.load()
+
+
+def _err(h, code):
+    msg = lib().ppc_last_error(h)
+    return PPCError(code, msg.decode() if msg else "")
+
+
+def params(**kw) -> nat.Params:
+    """ppc_params_default() with keyword overrides (field names of ppc_params)."""
+    p = nat.Params()
+    lib().ppc_params_default(byref(p))
+    names = {f for f, _ in nat.Params._fields_}
+    for k, v in kw.items():
+        if k not in names:
+            raise KeyError(f"unknown parameter {k}")
+        setattr(p, k, v)
+    return p
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _pd(a):
+    return a.ctypes.data_as(nat.PD)
+
+
+def _pi(a):
+    return a.ctypes.data_as(nat.PI)
+
+
+class _Marshalled:
+    """C structs for a problem description, holding the arrays alive."""
+
+    def __init__(self, prob):
+        self.xy = _f64(prob.xy).reshape(-1)
+        self.tri = _i32(prob.tri).reshape(-1)
+        self.dir = _i32(prob.dirichlet)
+        self.sigma = _f64(prob.sigma)
+        self.mat_id = _i32(prob.mat_id)
+        self.js = _f64(prob.js)
+        self.order = _i32(prob.orders)
+        self.amp = _f64(prob.amps)
+        self.phase = _f64(prob.phases)
+        models = np.asarray(prob.mat_model)
+        par = np.asarray(prob.mat_par, dtype=np.float64).reshape(len(models), 4)
+        self.laws = (nat.Law * len(models))()
+        for k in range(len(models)):
+            self.laws[k].law = int(models[k])
+            self.laws[k].nu, self.laws[k].k1, self.laws[k].k2, self.laws[k].k3 = (float(x) for x in par[k])
+        self.mesh = nat.Mesh(len(self.xy) // 2, _pd(self.xy), len(self.tri) // 3, _pi(self.tri),
+                             len(self.dir), _pi(self.dir))
+        self.mat = nat.Material(_pd(self.sigma), _pi(self.mat_id), len(models), self.laws)
+        self.exc = nat.Excitation(_pd(self.js), float(prob.f0), len(self.order), _pi(self.order),
+                                  _pd(self.amp), _pd(self.phase))
+
+
+def validate(prob):
+    """Host-only check of a problem description: returns (code, message)."""
+    m = _Marshalled(prob)
+    buf = ctypes.create_string_buffer(512)
+    rc = lib().ppc_validate(byref(m.mesh), byref(m.mat), byref(m.exc), buf, 512)
+    return rc, buf.value.decode()
+
+
+def validate_params(p):
+    buf = ctypes.create_string_buffer(512)
+    rc = lib().ppc_validate_params(byref(p), buf, 512)
+    return rc, buf.value.decode()
+
+
+class Handle:
+    def __init__(self, device: int = 0):
+        h = c_void_p()
+        rc = lib().ppc_create(int(device), byref(h))
+        if rc != 0:
+            raise _err(None, rc)
+        self.h = h
+        self.device = device
+
+    def close(self):
+        if self.h:
+            lib().ppc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _stream():
+    import torch
+    return c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev_ptr(t, shape):
+    import torch
+    if t.device.type != "cuda" or t.dtype != torch.float64 or not t.is_contiguous():
+        raise ValueError("expected a contiguous float64 CUDA tensor")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"expected shape {tuple(shape)}, got {tuple(t.shape)}")
+    return c_void_p(t.data_ptr())
+
+
+class Problem:
+    """A problem copied to the device (ppc_problem_create)."""
+
+    def __init__(self, handle: Handle, prob):
+        self.handle = handle
+        m = _Marshalled(prob)
+        p = c_void_p()
+        rc = lib().ppc_problem_create(handle.h, byref(m.mesh), byref(m.mat), byref(m.exc), byref(p))
+        if rc != 0:
+            raise _err(handle.h, rc)
+        self.p = p
+        info = [c_int32() for _ in range(4)]
+        lib().ppc_problem_info(p, *(byref(x) for x in info))
+        self.n_free, self.nnz, self.n_tri, self.n_nodes = (x.value for x in info)
+
+    def close(self):
+        if self.p:
+            lib().ppc_problem_destroy(self.p)
+            self.p = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- PP-PC solve ------------------------------------------------------------------------
+    def solve(self, prm, U_init=None, out=None):
+        """Periodic steady state on the device.  Returns (U [N, n_nodes] CUDA float64,
+        eps history (numpy), iterations, stats dict, status)."""
+        import torch
+        shape = (prm.N, self.n_nodes)
+        if out is None:
+            out = torch.empty(shape, dtype=torch.float64, device=f"cuda:{self.handle.device}")
+        resid = np.zeros(prm.max_iters + 1, dtype=np.float64)
+        iters = c_int32()
+        st = nat.Stats()
+        ui = _dev_ptr(U_init, shape) if U_init is not None else c_void_p()
+        rc = lib().ppc_solve_device(self.handle.h, self.p, byref(prm), ui, _dev_ptr(out, shape),
+                                    _pd(resid), byref(iters), byref(st), _stream())
+        if rc < 0:
+            raise _err(self.handle.h, rc)
+        k = iters.value
+        return out, resid[: k + 1].copy(), k, st.as_dict(), rc
+
+    def solve_host(self, prm, U_init=None):
+        """ppc_solve with host arrays: returns (U numpy, eps, iterations, stats, status)."""
+        U = np.zeros((prm.N, self.n_nodes), dtype=np.float64)
+        resid = np.zeros(prm.max_iters + 1, dtype=np.float64)
+        iters = c_int32()
+        st = nat.Stats()
+        ui = _f64(U_init) if U_init is not None else None
+        rc = lib().ppc_solve(self.handle.h, self.p, byref(prm), _pd(ui) if ui is not None else None,
+                             _pd(U), _pd(resid), byref(iters), byref(st))
+        if rc < 0:
+            raise _err(self.handle.h, rc)
+        k = iters.value
+        return U, resid[: k + 1].copy(), k, st.as_dict(), rc
+
+    # -- single pieces ------------------------------------------------------------------------
+    def fine_sweep(self, prm, U):
+        """F[n mod N] = F_n(U[n-1]) for all chains (one launch).  U: CUDA [N, n_nodes]."""
+        import torch
+        shape = (prm.N, self.n_nodes)
+        F = torch.empty(shape, dtype=torch.float64, device=U.device)
+        newton = np.zeros(prm.N, dtype=np.int32)
+        lin = np.zeros(prm.N, dtype=np.int32)
+        rc = lib().ppc_fine_sweep_device(self.handle.h, self.p, byref(prm), _dev_ptr(U, shape),
+                                         _dev_ptr(F, shape), _pi(newton), _pi(lin), _stream())
+        if rc < 0:
+            raise _err(self.handle.h, rc)
+        return F, newton, lin
+
+    def coarse_correction(self, prm, U, J):
+        """dU solving the cyclic coarse system for jumps J.  CUDA [N, n_nodes] each."""
+        import torch
+        shape = (prm.N, self.n_nodes)
+        dU = torch.empty(shape, dtype=torch.float64, device=U.device)
+        cocg = np.zeros(prm.N // 2 + 1, dtype=np.int32)
+        rc = lib().ppc_coarse_correction_device(self.handle.h, self.p, byref(prm), _dev_ptr(U, shape),
+                                                _dev_ptr(J, shape), _dev_ptr(dU, shape), _pi(cocg),
+                                                _stream())
+        if rc < 0:
+            raise _err(self.handle.h, rc)
+        return dU, cocg
+
+
+def problem_params(prob, **kw):
+    """Parameters carrying a workload's period and time grid (T, N, m)."""
+    return params(T=float(prob.T), N=int(prob.N), m=int(prob.m), **kw)

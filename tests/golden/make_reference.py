@@ -1,0 +1,70 @@
+"""Write the stored oracle results used by the GPU parity tests.
+
+Calls only the CPU oracle (``oracle/``) and the seeded input generator
+(``workloads/``); nothing here touches the GPU path.  Run from the repository root:
+
+    python tests/golden/make_reference.py [c2] [c5small] [--procs 8]
+
+Each output ``<name>_oracle.npz`` holds the PP-PC fixed point U (rows n = 0..N-1,
+columns = free nodes in ascending node order), the eps history, the iteration count
+and the generator arguments that define the workload.
+"""
+from __future__ import annotations
+
+import argparse
+import os
+import sys
+import time
+
+os.environ.setdefault("OMP_NUM_THREADS", "1")
+import numpy as np  # noqa: E402
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+from oracle.fe import FE  # noqa: E402
+from oracle import periodic  # noqa: E402
+from workloads import coax  # noqa: E402
+
+CASES = {
+    # name: (generator, kwargs, PP-PC tolerance)
+    "c2": (coax.c2, {}, 1e-12),
+    "c5small": (coax.c5_small, {}, 1e-12),
+}
+
+
+def make(name, procs):
+    gen, kw, tol = CASES[name]
+    prob = gen(**kw)
+    fe = FE(prob)
+    pool = periodic.make_pool(prob, procs) if procs > 1 else None
+    t = time.time()
+    hist_print = []
+
+    def cb(k, U, Fs, eps):
+        hist_print.append(eps)
+        print(f"  [{name}] k={k} eps={eps:.3e} t={time.time() - t:.1f}s", flush=True)
+
+    try:
+        U, hist, k = periodic.ppc(fe, tol=tol, pool=pool, callback=cb)
+    finally:
+        if pool is not None:
+            pool.close()
+            pool.join()
+    out = os.path.join(HERE, f"{name}_oracle.npz")
+    np.savez_compressed(out, U=U, hist=hist, iterations=k, tol=tol,
+                        free=fe.free.astype(np.int32), generator=name)
+    print(f"wrote {out}: iterations={k} eps={hist[-1]:.3e} in {time.time() - t:.1f}s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("cases", nargs="*", default=list(CASES))
+    ap.add_argument("--procs", type=int, default=min(8, os.cpu_count() or 1))
+    a = ap.parse_args()
+    for c in a.cases:
+        make(c, a.procs)
+
+
+if __name__ == "__main__":
+    main()

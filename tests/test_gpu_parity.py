@@ -1,0 +1,130 @@
+"""GPU parity: the HIP path through the C-ABI against the FP64 CPU oracle.
+
+Each test compares element by element on the same seeded inputs; tolerances are
+relative Frobenius errors.  The bar for a converged FP64 periodic steady state is
+1e-10 relative to the oracle.
+"""
+import numpy as np
+import pytest
+
+from workloads import coax
+from tests.gpu_common import banner, free_rows, handle, load_golden, rel
+
+pytestmark = pytest.mark.gpu
+
+
+def _problem(prob):
+    import paper_1905_13076_amd as P
+    return P.Problem(handle(), prob)
+
+
+def _nodal(fe, Ufree):
+    return fe.full(Ufree)
+
+
+def test_c1_linear_fp64_matches_oracle():
+    """C1 (linear coax, N=10 x 20, FP64): GPU PP-PC vs the exact DFT solve of the
+    cyclic fine system and vs the oracle's own PP-PC."""
+    import paper_1905_13076_amd as P
+    from oracle.fe import FE
+    from oracle import periodic
+    prob = coax.c1()
+    fe = FE(prob)
+    UL, _ = periodic.route_l(fe)
+    Uo, hist_o, k_o = periodic.ppc(fe, tol=1e-12)
+    banner("c1 solve fp64")
+    pr = _problem(prob)
+    U, eps, k, st, rc = pr.solve(P.problem_params(prob))
+    assert rc == 0, st
+    Ug = free_rows(U.cpu().numpy(), fe.free)
+    e_l, e_p = rel(Ug, UL), rel(Ug, Uo)
+    banner(f"c1 iters={k} (oracle {k_o}) rel_vs_routeL={e_l:.2e} rel_vs_ppc={e_p:.2e} stats={st}")
+    assert e_l <= 1e-10 and e_p <= 1e-10
+    # Dirichlet ring is exactly zero
+    assert np.all(U.cpu().numpy()[:, prob.dirichlet] == 0.0)
+    # same iteration history as the oracle's PP-PC (same algorithm, same rounding level)
+    assert abs(k - k_o) <= 1
+    # (entries near the rounding floor differ in the last digits: absolute floor 1e-14)
+    L = min(len(eps), len(hist_o))
+    np.testing.assert_allclose(eps[:L], hist_o[:L], rtol=1e-6, atol=1e-14)
+
+
+def test_c1_fine_sweep_matches_oracle():
+    """One fine sweep (all chains, one launch) from the coarse initial iterate."""
+    import torch
+    import paper_1905_13076_amd as P
+    from oracle.fe import FE
+    from oracle import periodic
+    prob = coax.c1()
+    fe = FE(prob)
+    U0 = periodic.initial_iterate(fe)
+    Fo = periodic.fine_sweep(fe, U0)
+    banner("c1 fine sweep")
+    pr = _problem(prob)
+    Ud = torch.tensor(_nodal(fe, U0), dtype=torch.float64, device="cuda")
+    F, newton, lin = pr.fine_sweep(P.problem_params(prob), Ud)
+    Fg = free_rows(F.cpu().numpy(), fe.free)
+    e = rel(Fg, Fo)
+    banner(f"c1 fine sweep rel={e:.2e} newton={newton.tolist()} lin={lin.tolist()}")
+    assert e <= 1e-11
+    for n in range(prob.N):
+        assert rel(Fg[n], Fo[n]) <= 1e-11
+
+
+def test_c1_coarse_correction_matches_oracle():
+    """Coarse correction (linearise, RHS, DFT, COCG per harmonic, inverse DFT) against
+    the oracle's direct per-harmonic solves."""
+    import torch
+    import paper_1905_13076_amd as P
+    from oracle.fe import FE
+    from oracle import periodic
+    prob = coax.c1()
+    fe = FE(prob)
+    U0 = periodic.initial_iterate(fe)
+    J = periodic.fine_sweep(fe, U0) - U0
+    dUo = periodic.coarse_correction(fe, U0, J)
+    banner("c1 coarse correction")
+    pr = _problem(prob)
+    prm = P.problem_params(prob, tol_cocg=1e-13)
+    dU, cocg = pr.coarse_correction(prm, torch.tensor(_nodal(fe, U0), device="cuda"),
+                                    torch.tensor(_nodal(fe, J), device="cuda"))
+    e = rel(free_rows(dU.cpu().numpy(), fe.free), dUo)
+    banner(f"c1 coarse rel={e:.2e} cocg={cocg.tolist()}")
+    assert e <= 1e-10
+
+
+@pytest.mark.parametrize("start", ["zero", "periodic"])
+def test_nonlinear_fine_sweep_matches_oracle(start):
+    """Brauer steel sheath on the C1 mesh: fine sweep from U = 0 (transient, saturating)
+    and from the oracle's periodic solution."""
+    import torch
+    import paper_1905_13076_amd as P
+    from oracle.fe import FE
+    from oracle import periodic
+    prob = coax.c5_small()
+    fe = FE(prob)
+    U0 = np.zeros((prob.N, fe.n)) if start == "zero" else load_golden("c5small")["U"]
+    Fo = periodic.fine_sweep(fe, U0)
+    banner(f"c5small fine sweep from {start}")
+    pr = _problem(prob)
+    F, newton, lin = pr.fine_sweep(P.problem_params(prob), torch.tensor(_nodal(fe, U0), device="cuda"))
+    e = rel(free_rows(F.cpu().numpy(), fe.free), Fo)
+    banner(f"c5small fine sweep ({start}) rel={e:.2e} newton={newton.tolist()}")
+    assert e <= 1e-10
+
+
+def test_c5small_nonlinear_fp64_matches_oracle():
+    """Nonlinear PP-PC (Brauer sheath, C1 mesh, N=10 x 20, FP64) vs the stored oracle
+    fixed point."""
+    import paper_1905_13076_amd as P
+    from oracle.fe import FE
+    prob = coax.c5_small()
+    fe = FE(prob)
+    g = load_golden("c5small")
+    banner("c5small solve fp64")
+    pr = _problem(prob)
+    U, eps, k, st, rc = pr.solve(P.problem_params(prob))
+    assert rc == 0, st
+    e = rel(free_rows(U.cpu().numpy(), fe.free), g["U"])
+    banner(f"c5small iters={k} (oracle {int(g['iterations'])}) rel={e:.2e} maxB={st['max_b_steel']:.3f}")
+    assert e <= 1e-10
