@@ -1,0 +1,191 @@
+"""Pins of the oracle's periodic solvers (Sections 2-3) by brute force, algebraic
+identities of the paper and agreement of independent routes."""
+import math
+
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+from oracle import periodic
+from oracle.fe import FE
+from oracle.timestep import fine_propagate
+from workloads import coax
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _tiny_nl(**kw):
+    args = dict(nr=4, ntheta=8, N=6, m=3, nonlinear=True, amp=300.0)
+    args.update(kw)
+    return FE(coax.tiny(**args))
+
+
+def test_dft_block_diagonalises_block_cyclic_G():
+    """Eq. (13): the per-harmonic solves of harmonic_solve equal a direct solve with the
+    explicit block-cyclic G of eq. (9) (Q on the diagonal, -C below and top-right)."""
+    fe = _tiny_nl()
+    N, T = fe.prob.N, fe.prob.T
+    rng = np.random.default_rng(1)
+    U = 2e-3 * rng.standard_normal((N, fe.n))
+    Kbar = periodic.coarse_stiffness(fe, U)
+    Rr = rng.standard_normal((N, fe.n))
+    X1 = periodic.harmonic_solve(fe, Kbar, Rr, T)
+    G = periodic.block_cyclic_G(fe, Kbar, N, T)
+    X2 = spla.spsolve(G.tocsc(), Rr.ravel()).reshape(N, fe.n)
+    assert rel(X1, X2) <= 1e-12
+
+
+def _coarse_step(fe, Kbar, n, u):
+    """Implicit-Euler coarse propagator of eq. (8): Q G = C u + f(T_n)."""
+    N, T = fe.prob.N, fe.prob.T
+    C = fe.M / (T / N)
+    f = periodic.excitation_rows(fe, N, T)[n % N]
+    return spla.spsolve((C + Kbar).tocsc(), C @ u + f)
+
+
+def test_correction_form_equals_literal_eq9():
+    """Linear case: U + coarse_correction(J) equals the solution of G U^{k+1} = r^k with
+    b^k from eq. (7) and r_n = Q b_n + f(T_n) from eq. (10)."""
+    fe = FE(coax.tiny(nr=4, ntheta=8, N=6, m=3))
+    N, T = fe.prob.N, fe.prob.T
+    rng = np.random.default_rng(2)
+    U = 1e-7 * rng.standard_normal((N, fe.n))
+    Fs = periodic.fine_sweep(fe, U)
+    K = periodic.coarse_stiffness(fe, U)
+    Q = fe.M / (T / N) + K
+    fr = periodic.excitation_rows(fe, N, T)
+    r = np.zeros_like(U)
+    for n in range(1, N + 1):                      # row n mod N pairs with subinterval n
+        b = Fs[n % N] - _coarse_step(fe, K, n, U[n - 1])
+        r[n % N] = Q @ b + fr[n % N]
+    G = periodic.block_cyclic_G(fe, K, N, T)
+    U_lit = spla.spsolve(G.tocsc(), r.ravel()).reshape(N, fe.n)
+    U_cor = U + periodic.coarse_correction(fe, U, Fs - U)
+    assert rel(U_cor, U_lit) <= 1e-12
+    # the identity behind it: r^k = G U^k + Q J^k
+    GU = (G @ U.ravel()).reshape(N, fe.n)
+    assert rel(GU + (Q @ (Fs - U).T).T, r) <= 1e-12
+
+
+def test_coarse_equals_fine_converges_in_one_iteration():
+    """m = 1 and linear: the fine propagator is the coarse one, so one correction with the
+    exact symbol reaches the periodic solution."""
+    fe = FE(coax.tiny(nr=5, ntheta=10, N=8, m=1))
+    U, hist, k = periodic.ppc(fe, tol=1e-13)
+    assert k <= 1 and hist[-1] <= 1e-13
+    UL, _ = periodic.route_l(fe)
+    assert rel(U, UL) <= 1e-12
+
+
+def test_literal_rhs_with_iw_shift_has_wrong_fixed_point():
+    """Negative test: iterating the literal eqs. (9)-(10) but with the harmonic-balance
+    shift i w_p in place of the implicit-Euler symbol does not reach the fine periodic
+    solution, while the correction form with the same shift does."""
+    fe = FE(coax.tiny(nr=5, ntheta=10, N=8, m=4))
+    N, T = fe.prob.N, fe.prob.T
+    UL, _ = periodic.route_l(fe)
+    K = periodic.coarse_stiffness(fe, UL)
+    Q = fe.M / (T / N) + K
+    fr = periodic.excitation_rows(fe, N, T)
+    sig = periodic.shifts(N, T, "iw")
+    U = np.zeros_like(UL)
+    for _ in range(60):
+        Fs = periodic.fine_sweep(fe, U)
+        r = np.zeros_like(U)
+        for n in range(1, N + 1):
+            r[n % N] = Q @ (Fs[n % N] - _coarse_step(fe, K, n, U[n - 1])) + fr[n % N]
+        Rh = np.fft.rfft(r, axis=0)
+        Xh = np.array([spla.spsolve((K + s * fe.M).astype(complex).tocsc(), Rh[p]) for p, s in enumerate(sig)])
+        U = np.fft.irfft(Xh, n=N, axis=0)
+    assert rel(U, UL) > 1e-4
+    Uc, _, _ = periodic.ppc(fe, tol=1e-12, shift="iw")
+    assert rel(Uc, UL) <= 1e-10
+
+
+def test_initial_value_parareal_terminates_after_N_iterations():
+    """Classical Parareal with U_0 fixed reproduces the sequential fine solution exactly
+    after N iterations (the finite-termination property behind eq. (4))."""
+    fe = _tiny_nl(N=5, m=3, amp=20.0)
+    N, T, m = fe.prob.N, fe.prob.T, fe.prob.m
+    rng = np.random.default_rng(3)
+    u0 = 1e-4 * rng.standard_normal(fe.n)
+    its = periodic.ivp_parareal(fe, u0, N)
+    seq = [u0]
+    dt = T / (N * m)
+    for n in range(1, N + 1):
+        seq.append(fine_propagate(fe, seq[-1], (n - 1) * (T / N), m, dt))
+    seq = np.array(seq)
+    assert rel(its[N], seq) <= 1e-12
+    assert rel(its[N - 2], seq) > 1e-10          # not exact before the last iterations
+
+
+def test_route_l_equals_cyclic_direct_solve():
+    fe = FE(coax.tiny(nr=4, ntheta=8, N=4, m=3))
+    UL, _ = periodic.route_l(fe)
+    UD = periodic.cyclic_fine_direct(fe)
+    assert rel(UL, UD) <= 1e-12
+
+
+def test_c1_routes_agree():
+    """C1: exact DFT route, sequential periods and PP-PC give one periodic solution."""
+    fe = FE(coax.c1())
+    UL, _ = periodic.route_l(fe)
+    US, periods = periodic.route_s(fe, tol=1e-14)
+    UP, hist, k = periodic.ppc(fe, tol=1e-12)
+    assert rel(US, UL) <= 1e-12
+    assert rel(UP, UL) <= 1e-12
+    assert k <= 10 and np.all(np.diff(np.log(hist)) < 0)   # monotone contraction
+
+
+def test_energy_identity_of_the_periodic_linear_solution():
+    """Multiply the periodic implicit-Euler equations by du_j and sum over a period:
+    sum f_j.du_j = sum du_j.M du_j / dt + 1/2 sum du_j.K du_j (the stored energy
+    telescopes)."""
+    fe = FE(coax.c1())
+    _, u = periodic.route_l(fe)
+    prob = fe.prob
+    L = prob.N * prob.m
+    dt = prob.T / L
+    K = fe.K_matrix(np.full(prob.n_tri, coax.NU0))
+    du = u - np.roll(u, 1, axis=0)                 # du_j = u_j - u_{j-1}, cyclic
+    t = np.arange(L) * dt
+    t[0] = prob.T
+    f = np.outer(prob.current(t), fe.F)
+    lhs = np.sum(f * du)
+    rhs = np.sum(du * (fe.M @ du.T).T) / dt + 0.5 * np.sum(du * (K @ du.T).T)
+    assert abs(lhs - rhs) <= 1e-10 * abs(lhs)
+
+
+def test_nonlinear_routes_and_variants_share_the_fixed_point():
+    """Nonlinear (saturating Brauer sheath): sequential periods and PP-PC from U^0 = 0
+    with the exact shift, the harmonic-balance shift and the chord linearisation all
+    reach one periodic solution; only iteration counts differ."""
+    fe = _tiny_nl(nr=6, ntheta=12, N=8, m=5, amp=400.0)
+    US, _ = periodic.route_s(fe, tol=1e-14)
+    _, _, b2, _, _ = fe.element_state(US[2])
+    assert math.sqrt(b2.max()) > 1.0
+    runs = {
+        "zero": periodic.ppc(fe, tol=1e-12, init="zero"),
+        "iw": periodic.ppc(fe, tol=1e-12, init="zero", shift="iw"),
+        "chord": periodic.ppc(fe, tol=1e-12, init="zero", lin="chord"),
+    }
+    for name, (U, hist, k) in runs.items():
+        assert rel(U, US) <= 1e-10, name
+
+
+def test_ppic_reaches_the_same_solution_more_slowly():
+    """PP-IC (eq. (5)) converges to the PP-PC fixed point but needs more iterations."""
+    fe = FE(coax.tiny(nr=5, ntheta=10, N=8, m=4))
+    Up, _, kp = periodic.ppc(fe, tol=1e-11)
+    Ui, _, ki = periodic.ppic(fe, tol=1e-11)
+    assert rel(Ui, Up) <= 1e-9
+    assert ki > kp
+
+
+def test_epsilon_definition():
+    U = np.ones((2, 3))
+    assert periodic.periodicity_residual(U, 0.5 * U) == pytest.approx(0.5)
+    assert periodic.periodicity_residual(0 * U, U) == float("inf")
+    assert periodic.periodicity_residual(0 * U, 0 * U) == 0.0
