@@ -1,0 +1,206 @@
+#!/usr/bin/env python3
+"""Throughput of the PP-PC periodic steady-state solver on one MI355X.
+
+One step = one complete periodic steady state: PP-PC from its initial iterate until
+eps = ||J||_F/||U||_F <= tol, every fine sweep, jump, linearisation, DFT, harmonic COCG
+solve and inverse DFT on the GPU, with the problem already resident in HBM.  The
+workload is the nonlinear coax (nr = 60 x ntheta = 120, 7,081 free nodes, steel
+sheath with a Brauer B-H law, N = 40 subintervals x 50 implicit-Euler steps,
+21 harmonic systems, FP64) with synthetic seeded inputs.
+
+Prints one JSON line: steady states per second, the roofline of the dominant kernel
+(the fine sweep) from its measured launch durations and algorithmic bytes, the error
+against the stored FP64 oracle fixed point, and the CPU oracle timed on a bounded
+sample as a baseline.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp64|mixed]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c5small"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--tol", type=float, default=1e-8, help="PP-PC stopping tolerance on eps")
+    ap.add_argument("--cpu-baseline", dest="cpu", action="store_true", default=True)
+    ap.add_argument("--no-cpu-baseline", dest="cpu", action="store_false")
+    ap.add_argument("--cpu-procs", type=int, default=16)
+    return ap.parse_args()
+
+
+def workload(name):
+    from workloads import coax
+    return {"c1": coax.c1, "c2": coax.c2, "c5small": coax.c5_small}[name]()
+
+
+def load_reference(name):
+    import numpy as np
+    path = os.path.join(ROOT, "tests", "golden", f"{name}_oracle.npz")
+    if not os.path.exists(path):
+        return None
+    with np.load(path, allow_pickle=False) as z:
+        return {"U": z["U"], "iterations": int(z["iterations"]), "free": z["free"]}
+
+
+def cpu_baseline(prob, ref, procs):
+    """The oracle (scipy direct solves, FP64) on the host cores, on a bounded sample:
+    one round of `cores` fine chains run in parallel (one per worker process, started
+    from the oracle fixed point) and one coarse correction; extrapolated to the
+    oracle's own count of sweeps and corrections for one steady state."""
+    import numpy as np
+    from oracle import periodic
+    from oracle.fe import FE
+    os.environ.setdefault("OMP_NUM_THREADS", "1")
+    cores = max(1, min(procs, len(os.sched_getaffinity(0)), prob.N))
+    fe = FE(prob)
+    U = ref["U"] if ref is not None else np.zeros((prob.N, fe.n))
+    iters = ref["iterations"] if ref is not None else None
+    dt = periodic.fine_dt(prob)
+    args = [((n - 1) * (prob.T / prob.N), U[n - 1], prob.m, dt, 1e-13) for n in range(1, cores + 1)]
+    pool = periodic.make_pool(prob, cores)
+    try:
+        pool.starmap(periodic._chain_worker, args[:1])          # warm the workers' imports
+        t0 = time.perf_counter()
+        outs = pool.starmap(periodic._chain_worker, args)
+        t_round = time.perf_counter() - t0
+    finally:
+        pool.close()
+        pool.join()
+    J = np.zeros_like(U)
+    for n in range(1, cores + 1):
+        J[n % prob.N] = outs[n - 1] - U[n % prob.N]
+    t0 = time.perf_counter()
+    periodic.coarse_correction(fe, U, J)
+    t_coarse = time.perf_counter() - t0
+    rounds = math.ceil(prob.N / cores)
+    sweeps = (iters + 1) if iters is not None else None
+    t_state = sweeps * rounds * t_round + iters * t_coarse if iters is not None else None
+    return {
+        "value": (1.0 / t_state) if t_state else None,
+        "unit": "steady states/s",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": (f"{cores} of {prob.N} fine chains ({prob.m} steps each, one per process) "
+                   f"in {t_round:.2f} s + 1 coarse correction in {t_coarse:.2f} s; extrapolated to "
+                   f"{sweeps} sweeps x {rounds} rounds + {iters} corrections = {t_state:.1f} s per steady state"),
+    }
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU: the path has no collectives; "
+                                   "run with --gpus 1"}))
+        return 2
+    prob = workload(a.workload)
+    ref = load_reference(a.workload)
+    cpu = None
+    if a.cpu and ref is not None:
+        # before any GPU initialisation: the oracle's worker pool forks this process
+        cpu = cpu_baseline(prob, ref, a.cpu_procs)
+    import numpy as np
+    import torch
+    import paper_1905_13076_amd as P
+    from paper_1905_13076_amd.traffic import fine_sweep_bytes
+
+    torch.cuda.set_device(0)
+    h = P.Handle(0)
+    t0 = time.perf_counter()
+    pr = P.Problem(h, prob)
+    setup_s = time.perf_counter() - t0
+    prec = 0 if a.precision == "fp64" else 1
+    prm = P.problem_params(prob, tol_ppc=a.tol, precision=prec,
+                           **({"tol_lin": 1e-4} if prec == 1 else {}))
+    out = torch.empty((prob.N, pr.n_nodes), dtype=torch.float64, device="cuda")
+    for _ in range(a.warmup):
+        pr.solve(prm, out=out)
+    torch.cuda.synchronize()
+    stats = []
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        U, eps, k, st, rc = pr.solve(prm, out=out)
+        stats.append(st)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    if rc != 0:
+        print(json.dumps({"error": f"solve status {rc}", "stats": st}))
+        return 1
+    # error against the stored FP64 oracle fixed point
+    err = None
+    if ref is not None:
+        Ug = U.cpu().numpy()[:, ref["free"]]
+        err = float(np.linalg.norm(Ug - ref["U"]) / np.linalg.norm(ref["U"]))
+    fine_ms = sum(s["fine_ms"] for s in stats)
+    launches = sum(s["fine_launches"] for s in stats)
+    tot = {k2: sum(s[k2] for s in stats) for k2 in ("lin_total", "resid_total", "newton_total",
+                                                     "steps_total", "fine_launches")}
+    tot.update(n_free=st["n_free"], nnz=st["nnz"], n_tri=st["n_tri"])
+    bytes_launch = fine_sweep_bytes(tot, prob.N, prec) / launches
+    launch_s = fine_ms / launches / 1e3
+    achieved = bytes_launch / launch_s / 1e9
+    value = a.steps / wall
+    line = {
+        "metric": "periodic steady states/s at 1e-6 rel. err vs FP64 oracle; achieved HBM GB/s",
+        "value": value,
+        "unit": "steady states/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": 1e3 * wall / a.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == 0 else "f32+f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{prob.name}: nr={prob.meta['nr']} x ntheta={prob.meta['ntheta']} "
+                        f"({st['n_free']} free nodes, {st['nnz']} nnz), N={prob.N} x m={prob.m}, "
+                        f"{prob.N // 2 + 1} harmonics, amplitude {prob.amps[0]:.1f} A",
+            "precision": a.precision,
+            "tol_ppc": a.tol,
+            "iterations": k,
+            "err_vs_oracle": err,
+            "max_b_steel_T": st["max_b_steel"],
+            "newton_per_step": tot["newton_total"] / max(1, tot["steps_total"]),
+            "pcg_per_newton": tot["lin_total"] / max(1, tot["newton_total"]),
+            "cocg_total_per_state": sum(s["cocg_total"] for s in stats) / a.steps,
+            "fine_ms_per_state": fine_ms / a.steps,
+            "coarse_ms_per_state": sum(s["coarse_ms"] for s in stats) / a.steps,
+            "setup_s": setup_s,
+        },
+        "roofline": {
+            "kernel": "k_fine_sweep",
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "bytes_per_launch": bytes_launch,
+            "launch_ms": launch_s * 1e3,
+            "launches": launches,
+        },
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

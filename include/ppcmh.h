@@ -134,6 +134,8 @@ typedef struct {
     double eps;                  /* last ||J||_F / ||U||_F */
     double max_b_steel;          /* max |B| over nonlinear elements at the returned U (T) */
     int32_t n_free, nnz, n_tri, reserved_i;
+    int64_t resid_total;         /* residual evaluations (element + node passes) */
+    int64_t steps_total;         /* implicit-Euler steps taken over every chain */
 } ppc_stats;
 
 /* ABI version (PPC_ABI_VERSION). */

@@ -60,7 +60,8 @@ class Stats(ctypes.Structure):
                 ("cocg_max", c_int32), ("lin_capped", c_int32), ("fine_ms", c_double),
                 ("coarse_ms", c_double), ("total_ms", c_double), ("jump", c_double),
                 ("eps", c_double), ("max_b_steel", c_double), ("n_free", c_int32),
-                ("nnz", c_int32), ("n_tri", c_int32), ("reserved_i", c_int32)]
+                ("nnz", c_int32), ("n_tri", c_int32), ("reserved_i", c_int32),
+                ("resid_total", c_int64), ("steps_total", c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved_i"}

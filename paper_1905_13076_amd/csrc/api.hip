@@ -134,7 +134,7 @@ namespace {
 
 struct SweepCounts {
     int status = 0;
-    int64_t newton = 0, lin = 0;
+    int64_t newton = 0, lin = 0, resid = 0;
     int newton_max = 0, lin_max = 0, capped = 0;
     int fail_chain = -1, fail_step = -1;
 };
@@ -157,6 +157,7 @@ SweepCounts read_chain_counts(ppc_problem* pr, int N, hipStream_t s, int32_t* ne
         r.newton_max = std::max(r.newton_max, q[3]);
         r.lin_max = std::max(r.lin_max, q[4]);
         r.capped += q[5];
+        r.resid += q[7];
         if (newton_out) newton_out[k] = q[1];
         if (lin_out) lin_out[k] = q[2];
     }
@@ -245,6 +246,8 @@ int solve_device(ppc_handle* h, ppc_problem* pr, const ppc_params* p, const doub
         S.newton_max = std::max(S.newton_max, c.newton_max);
         S.lin_max = std::max(S.lin_max, c.lin_max);
         S.lin_capped += c.capped;
+        S.resid_total += c.resid;
+        S.steps_total += (int64_t)N * p->m;
         check_sweep(c);
         const double jj = w.host_scal[0], uu = w.host_scal[1], j0 = w.host_scal[2];
         const double eps = uu > 0.0 ? std::sqrt(jj) / std::sqrt(uu) : (jj == 0.0 ? 0.0 : INFINITY);

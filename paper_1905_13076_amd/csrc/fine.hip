@@ -101,7 +101,7 @@ enum { E_F0 = 0, E_W0 = 3, E_NU = 6, E_SF = 7 };
 enum { V_U = 0, V_UP = 1, V_R = 2, V_RT = 3 };
 enum { P_R = 0, P_P = 1, P_Q = 2, P_X = 3, P_D = 4 };
 enum { C_STATUS = 0, C_NEWTON = 1, C_LIN = 2, C_NEWTON_MAX = 3, C_LIN_MAX = 4, C_CAPPED = 5,
-       C_FAILSTEP = 6 };
+       C_FAILSTEP = 6, C_RESID = 7 };
 
 // Element pass at ut = u + lam du (du may be null): w = K0 ut, b2 = ut.w/A, nu, nu',
 // and the element force nu w_a + (M_e (ut - u_prev))_a / dt.
@@ -266,7 +266,7 @@ __global__ __launch_bounds__(1024) void k_fine_sweep(FineArgs a) {
     const double t0 = (double)c * (a.T / a.N);
     const double inv_dt = 1.0 / a.dt;
     int status = 0, fail_step = -1;
-    int newton_total = 0, lin_total = 0, newton_max = 0, lin_max = 0, capped = 0;
+    int newton_total = 0, lin_total = 0, newton_max = 0, lin_max = 0, capped = 0, resid_evals = 0;
 
     for (int j = 1; j <= a.m && status == 0; ++j) {
         const double t = t0 + j * a.dt;
@@ -279,6 +279,7 @@ __global__ __launch_bounds__(1024) void k_fine_sweep(FineArgs a) {
         const double target = a.tol_newton * scale;
 
         element_pass<double>(a, u, nullptr, 0.0, up, el, inv_dt);
+        ++resid_evals;
         __syncthreads();
         double v2[1] = {node_pass(a, el, cur, R)};
         block_sum<double, 1>(v2, lds_d, ph_d);
@@ -350,6 +351,7 @@ __global__ __launch_bounds__(1024) void k_fine_sweep(FineArgs a) {
             bool accepted = false, stalled = false;
             while (true) {
                 element_pass<S>(a, u, px, lam, up, el, inv_dt);
+                ++resid_evals;
                 __syncthreads();
                 double v3[1] = {node_pass(a, el, cur, Rt)};
                 block_sum<double, 1>(v3, lds_d, ph_d);
@@ -388,6 +390,7 @@ __global__ __launch_bounds__(1024) void k_fine_sweep(FineArgs a) {
         cnt[C_LIN_MAX] = lin_max;
         cnt[C_CAPPED] = capped;
         cnt[C_FAILSTEP] = fail_step;
+        cnt[C_RESID] = resid_evals;
     }
 }
 

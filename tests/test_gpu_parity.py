@@ -128,3 +128,24 @@ def test_c5small_nonlinear_fp64_matches_oracle():
     e = rel(free_rows(U.cpu().numpy(), fe.free), g["U"])
     banner(f"c5small iters={k} (oracle {int(g['iterations'])}) rel={e:.2e} maxB={st['max_b_steel']:.3f}")
     assert e <= 1e-10
+
+
+def test_c2_nonlinear_fp64_matches_oracle():
+    """C2, the benchmark workload (nr = 60 x ntheta = 120, steel sheath, N = 40 x 50,
+    21 harmonics, FP64), in the launch configuration bench.py times: full PP-PC on the GPU
+    vs the stored oracle fixed point (written by tests/golden/make_reference.py)."""
+    import paper_1905_13076_amd as P
+    from oracle.fe import FE
+    prob = coax.c2()
+    fe = FE(prob)
+    g = load_golden("c2")
+    banner("c2 solve fp64")
+    pr = _problem(prob)
+    U, eps, k, st, rc = pr.solve(P.problem_params(prob))
+    assert rc == 0, st
+    e = rel(free_rows(U.cpu().numpy(), fe.free), g["U"])
+    banner(f"c2 iters={k} (oracle {int(g['iterations'])}) rel={e:.2e} maxB={st['max_b_steel']:.3f} "
+           f"fine_ms={st['fine_ms']:.1f} coarse_ms={st['coarse_ms']:.1f} lin={st['lin_total']} "
+           f"newton={st['newton_total']} cocg={st['cocg_total']}")
+    assert e <= 1e-10
+    assert st["max_b_steel"] > 1.5            # the sheath saturates in the steady state
