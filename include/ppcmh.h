@@ -110,7 +110,9 @@ typedef struct {
     int32_t max_lin;        /* PCG iteration cap per Newton step */
     double tol_cocg;        /* COCG: ||r|| <= tol_cocg ||b|| per harmonic */
     int32_t max_cocg;       /* COCG iteration cap */
-    int32_t block;          /* fine-kernel workgroup size (0: library choice) */
+    int32_t block;          /* fine-kernel path: 0 = library choice (register rows for small
+                               meshes, else LDS-resident p / diagonal); 1024 = force the
+                               workgroup-memory PCG path */
     int32_t reserved[7];
 } ppc_params;
 

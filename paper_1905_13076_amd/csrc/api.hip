@@ -106,9 +106,10 @@ void ensure_workspace(ppc_problem* pr, const ppc_params* p) {
     w.n_pad = pad64(d.n_free);
     w.nnz_pad = pad64(d.nnz);
     w.ne_pad = pad64(d.n_tri);
+    w.vals_pad = pad64(d.n_vals);
     w.fvec = dalloc<double>(N * kFineVec * w.n_pad);
     w.fpcg = dalloc<double>(N * kPcgVec * w.n_pad);     // sized for FP64, also used as FP32
-    w.fjac = dalloc<double>(N * w.nnz_pad);
+    w.fjac = dalloc<double>(N * w.vals_pad);
     w.felem = dalloc<double>(N * 8 * w.ne_pad);
     w.fcount = dalloc<int>(N * 8);
     w.U = dalloc<double>(N * d.n_free);

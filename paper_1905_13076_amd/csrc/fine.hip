@@ -52,7 +52,16 @@ struct FineArgs {
     void* jac;              // [N][nnz_pad] of S
     double* elem;           // [N][8][ne_pad]
     int* count;             // [N][8]
-    long n_pad, nnz_pad, ne_pad;
+    long n_pad, vals_pad, ne_pad;
+    // ELL pattern of the fine-sweep SpMV
+    int W, ntail, nvals;
+    long ell_pad;
+    const int* ecol;
+    const int* vslot;
+    const int* dpos;
+    const int* tail_row;
+    const int* tail_ptr;
+    const int* tail_col;
 };
 
 // Imposed current i(t) = sum_h amp_h sin(2 pi order_h f0 t + phase_h).
@@ -167,56 +176,226 @@ __device__ inline double node_pass(const FineArgs& a, const double* __restrict__
     return part;
 }
 
-// Jacobian values by slot gather, then the Jacobi inverse diagonal.
+// Jacobian values in ELL order: position v takes CSR slot vslot[v] (padding: 0), the
+// slot summing M_s/dt and every element contribution nu K0_ab + (2nu'/A) w_a w_b.
 template <typename S>
 __device__ inline void assemble(const FineArgs& a, const double* __restrict__ el, double inv_dt,
-                                S* __restrict__ jv, S* __restrict__ dinv) {
+                                S* __restrict__ jv) {
     const long P = a.ne_pad;
     const int ne = a.ne;
-    for (int s = threadIdx.x; s < a.nnz; s += blockDim.x) {
-        double acc = a.mval[s] * inv_dt;
-        for (int k = a.slot_ptr[s]; k < a.slot_ptr[s + 1]; ++k) {
-            const int code = a.slot_src[k];
-            const int e = code / 9, ab = code - 9 * e;
-            const int qa = ab / 3, qb = ab - 3 * qa;
-            const int lo = qa < qb ? qa : qb, hi = qa < qb ? qb : qa;
-            const int kidx = lo == 0 ? hi : (lo == 1 ? 2 + hi : 5);
-            acc += el[E_NU * P + e] * a.k0[kidx * ne + e] +
-                   el[E_SF * P + e] * el[(E_W0 + qa) * P + e] * el[(E_W0 + qb) * P + e];
+    for (int v = threadIdx.x; v < a.nvals; v += blockDim.x) {
+        const int s = a.vslot[v];
+        double acc = 0.0;
+        if (s >= 0) {
+            acc = a.mval[s] * inv_dt;
+            for (int k = a.slot_ptr[s]; k < a.slot_ptr[s + 1]; ++k) {
+                const int code = a.slot_src[k];
+                const int e = code / 9, ab = code - 9 * e;
+                const int qa = ab / 3, qb = ab - 3 * qa;
+                const int lo = qa < qb ? qa : qb, hi = qa < qb ? qb : qa;
+                const int kidx = lo == 0 ? hi : (lo == 1 ? 2 + hi : 5);
+                acc += el[E_NU * P + e] * a.k0[kidx * ne + e] +
+                       el[E_SF * P + e] * el[(E_W0 + qa) * P + e] * el[(E_W0 + qb) * P + e];
+            }
         }
-        jv[s] = (S)acc;
+        jv[v] = (S)acc;
     }
-    __syncthreads();
-    for (int i = threadIdx.x; i < a.n; i += blockDim.x) dinv[i] = (S)1 / jv[a.diag[i]];
 }
 
-// q = J p on kRowGroup lanes per row; returns this lane's partial of p.q
-template <typename S>
-__device__ inline S spmv_dot(int n, const int* __restrict__ rowptr, const int* __restrict__ colidx,
-                             const S* __restrict__ val, const S* __restrict__ p, S* __restrict__ q) {
-    constexpr int G = kRowGroup;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    const int sub = lane % G, grp = lane / G;
-    constexpr int RPW = 64 / G;
-    S part = 0;
-    for (int base = wave * RPW; base < n; base += nw * RPW) {
-        const int i = base + grp;
-        S acc = 0;
-        if (i < n) {
-            const int k1 = rowptr[i + 1];
-            for (int k = rowptr[i] + sub; k < k1; k += G) acc += val[k] * p[colidx[k]];
-        }
+// Row-sum of one tail (long) row by a whole wave; returns the sum on every lane.
+template <typename S, typename PV>
+__device__ inline S tail_row_sum(const FineArgs& a, const S* __restrict__ jv, PV p, int t, int lane) {
+    const long base = (long)a.W * a.ell_pad;
+    S acc = 0;
+    const int j1 = a.tail_ptr[t + 1];
+    for (int j = a.tail_ptr[t] + lane; j < j1; j += 64) acc += jv[base + j] * p[a.tail_col[j]];
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    return acc;
+}
+
+// Jacobi-PCG on J x = -R with the rows of each thread (i = tid + k B, k < R) held in
+// registers; p and the inverse diagonal live in LDS so the SpMV gathers never leave
+// the CU; only the ELL values and columns stream from memory.  Returns the iteration
+// count; x is written to xout.
+template <typename S, int R>
+__device__ int pcg_regs(const FineArgs& a, const S* __restrict__ jv, S* __restrict__ p_l,
+                        const S* __restrict__ d_l, S* __restrict__ tq_l, const double* __restrict__ Rres,
+                        S* __restrict__ xout, double tgt, S* lds_s, int& ph) {
+    const int B = blockDim.x, tid = threadIdx.x, n = a.n;
+    const int lane = tid & 63, wave = tid >> 6, nw = B >> 6;
+    const long NP = a.ell_pad;
+    const int W = a.W;
+    S x[R], r[R], p[R], q[R];
+    unsigned tailmask = 0;
+    S loc[2] = {0, 0};
 #pragma unroll
-        for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-        if (i < n && sub == 0) {
-            q[i] = acc;
-            part += p[i] * acc;
+    for (int k = 0; k < R; ++k) {
+        const int i = tid + k * B;
+        x[k] = 0;
+        r[k] = 0;
+        p[k] = 0;
+        q[k] = 0;
+        if (i < n) {
+            const S rv = (S)(-Rres[i]);
+            const S z = d_l[i] * rv;
+            r[k] = rv;
+            p[k] = z;
+            p_l[i] = z;
+            loc[0] += rv * z;
+            loc[1] += rv * rv;
+            if (a.ecol[i] < 0) tailmask |= 1u << k;
         }
     }
-    return part;
+    block_sum<S, 2>(loc, lds_s, ph);
+    S rz = loc[0];
+    double rr = (double)loc[1];
+    int it = 0;
+    while (rr > tgt * tgt && it < a.max_lin) {
+        S dot[1] = {0};
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const int i = tid + k * B;
+            if (i < n && !((tailmask >> k) & 1u)) {
+                S acc = 0;
+                for (int w = 0; w < W; ++w) acc += jv[w * NP + i] * p_l[a.ecol[w * NP + i]];
+                q[k] = acc;
+                dot[0] += p[k] * acc;
+            }
+        }
+        for (int t = wave; t < a.ntail; t += nw) {
+            const S acc = tail_row_sum<S>(a, jv, p_l, t, lane);
+            if (lane == 0) {
+                tq_l[t] = acc;
+                dot[0] += p_l[a.tail_row[t]] * acc;
+            }
+        }
+        block_sum<S, 1>(dot, lds_s, ph);
+        const S pq = dot[0];
+        if (!(pq > (S)0)) break;                 // loss of positivity: Newton decides
+        const S alpha = rz / pq;
+        S l2[2] = {0, 0};
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const int i = tid + k * B;
+            if (i < n) {
+                if ((tailmask >> k) & 1u) q[k] = tq_l[a.ecol[NP + i]];
+                x[k] += alpha * p[k];
+                r[k] -= alpha * q[k];
+                const S z = d_l[i] * r[k];
+                l2[0] += r[k] * z;
+                l2[1] += r[k] * r[k];
+            }
+        }
+        block_sum<S, 2>(l2, lds_s, ph);
+        ++it;
+        rr = (double)l2[1];
+        if (rr <= tgt * tgt) break;
+        const S beta = l2[0] / rz;
+        rz = l2[0];
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const int i = tid + k * B;
+            if (i < n) {
+                p[k] = d_l[i] * r[k] + beta * p[k];
+                p_l[i] = p[k];
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int i = tid + k * B;
+        if (i < n) xout[i] = x[k];
+    }
+    return it;
 }
 
-// ||M x||^2 partial, same lane-group layout (used for the step's residual scale)
+// Same algorithm with the vectors in memory: r, q, x in global memory; p in LDS when
+// LP >= 1 (the SpMV gathers then stay on the CU), the inverse diagonal in LDS when
+// LP == 2.  pl / dl are the LDS arrays (unused otherwise).
+template <typename S, int LP>
+__device__ int pcg_mem(const FineArgs& a, const S* __restrict__ jv, S* __restrict__ pv,
+                       S* __restrict__ pl, S* __restrict__ dl, const double* __restrict__ Rres,
+                       double tgt, S* lds_s, int& ph) {
+    const int B = blockDim.x, tid = threadIdx.x, n = a.n;
+    const int lane = tid & 63, wave = tid >> 6, nw = B >> 6;
+    const long NP = a.ell_pad;
+    const long VP = a.n_pad;
+    const int W = a.W;
+    S* pr = pv + P_R * VP;
+    S* pp = LP >= 1 ? pl : pv + P_P * VP;
+    S* pq = pv + P_Q * VP;
+    S* px = pv + P_X * VP;
+    const S* pd = LP == 2 ? dl : pv + P_D * VP;
+    S loc[2] = {0, 0};
+    for (int i = tid; i < n; i += B) {
+        const S rv = (S)(-Rres[i]);
+        const S z = pd[i] * rv;
+        pr[i] = rv;
+        pp[i] = z;
+        px[i] = 0;
+        loc[0] += rv * z;
+        loc[1] += rv * rv;
+    }
+    block_sum<S, 2>(loc, lds_s, ph);
+    S rz = loc[0];
+    double rr = (double)loc[1];
+    int it = 0;
+    while (rr > tgt * tgt && it < a.max_lin) {
+        S dot[1] = {0};
+#pragma unroll 2
+        for (int i = tid; i < n; i += B) {
+            int col[kEllMaxWidth];
+            S val[kEllMaxWidth];
+#pragma unroll
+            for (int w = 0; w < kEllMaxWidth; ++w) {
+                col[w] = w < W ? a.ecol[w * NP + i] : 0;
+                val[w] = w < W ? jv[w * NP + i] : (S)0;
+            }
+            if (col[0] >= 0) {
+                S acc = 0;
+#pragma unroll
+                for (int w = 0; w < kEllMaxWidth; ++w)
+                    if (w < W) acc += val[w] * pp[col[w]];
+                pq[i] = acc;
+                dot[0] += pp[i] * acc;
+            }
+        }
+        for (int t = wave; t < a.ntail; t += nw) {
+            const S acc = tail_row_sum<S>(a, jv, pp, t, lane);
+            if (lane == 0) {
+                const int row = a.tail_row[t];
+                pq[row] = acc;
+                dot[0] += pp[row] * acc;
+            }
+        }
+        block_sum<S, 1>(dot, lds_s, ph);
+        const S pqv = dot[0];
+        if (!(pqv > (S)0)) break;
+        const S alpha = rz / pqv;
+        S l2[2] = {0, 0};
+#pragma unroll 2
+        for (int i = tid; i < n; i += B) {
+            px[i] += alpha * pp[i];
+            const S rv = pr[i] - alpha * pq[i];
+            pr[i] = rv;
+            l2[0] += rv * (pd[i] * rv);
+            l2[1] += rv * rv;
+        }
+        block_sum<S, 2>(l2, lds_s, ph);
+        ++it;
+        rr = (double)l2[1];
+        if (rr <= tgt * tgt) break;
+        const S beta = l2[0] / rz;
+        rz = l2[0];
+#pragma unroll 2
+        for (int i = tid; i < n; i += B) pp[i] = pd[i] * pr[i] + beta * pp[i];
+        __syncthreads();
+    }
+    return it;
+}
+
+// ||M x||^2 partial, CSR with kRowGroup lanes per row (once per time step)
 __device__ inline double mass_norm2(const FineArgs& a, const double* __restrict__ x) {
     constexpr int G = kRowGroup;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
@@ -237,8 +416,11 @@ __device__ inline double mass_norm2(const FineArgs& a, const double* __restrict_
     return part;
 }
 
-template <typename S>
-__global__ __launch_bounds__(1024) void k_fine_sweep(FineArgs a) {
+// R > 0: PCG rows in registers, p / diagonal / tail sums in dynamic LDS;
+// R == 0: PCG vectors in memory, with p (LP >= 1) and the diagonal (LP == 2) in LDS.
+template <typename S, int R, int BLOCK, int LP>
+__global__ __launch_bounds__(BLOCK) void k_fine_sweep(FineArgs a) {
+    extern __shared__ unsigned char dyn_lds[];
     __shared__ double lds_d[2 * 16 * 4];
     __shared__ S lds_s[2 * 16 * 4];
     int ph_d = 0, ph_s = 0;
@@ -248,16 +430,16 @@ __global__ __launch_bounds__(1024) void k_fine_sweep(FineArgs a) {
     double* vec = a.vec + (long)c * kFineVec * NP;
     double* u = vec + V_U * NP;
     double* up = vec + V_UP * NP;
-    double* R = vec + V_R * NP;
+    double* R_ = vec + V_R * NP;
     double* Rt = vec + V_RT * NP;
     S* pv = reinterpret_cast<S*>(a.pcg) + (long)c * kPcgVec * NP;
-    S* pr = pv + P_R * NP;
-    S* pp = pv + P_P * NP;
-    S* pq = pv + P_Q * NP;
     S* px = pv + P_X * NP;
-    S* pd = pv + P_D * NP;
-    S* jv = reinterpret_cast<S*>(a.jac) + (long)c * a.nnz_pad;
+    S* jv = reinterpret_cast<S*>(a.jac) + (long)c * a.vals_pad;
     double* el = a.elem + (long)c * 8 * a.ne_pad;
+    S* p_l = reinterpret_cast<S*>(dyn_lds);
+    S* d_l = p_l + NP;
+    S* tq_l = d_l + NP;
+    S* dinv = (R > 0 || LP == 2) ? d_l : pv + P_D * NP;
 
     const double* U0 = a.U + (long)c * n;
     for (int i = threadIdx.x; i < n; i += blockDim.x) u[i] = U0[i];
@@ -281,7 +463,7 @@ __global__ __launch_bounds__(1024) void k_fine_sweep(FineArgs a) {
         element_pass<double>(a, u, nullptr, 0.0, up, el, inv_dt);
         ++resid_evals;
         __syncthreads();
-        double v2[1] = {node_pass(a, el, cur, R)};
+        double v2[1] = {node_pass(a, el, cur, R_)};
         block_sum<double, 1>(v2, lds_d, ph_d);
         double rn = sqrt(v2[0]);
         if (!isfinite(rn)) { status = PPC_ERR_NONFINITE; fail_step = j; break; }
@@ -290,45 +472,17 @@ __global__ __launch_bounds__(1024) void k_fine_sweep(FineArgs a) {
         for (;; ++it) {
             if (rn <= target) break;
             if (it == a.max_newton) { status = PPC_ERR_NEWTON; fail_step = j; break; }
-            assemble<S>(a, el, inv_dt, jv, pd);
+            assemble<S>(a, el, inv_dt, jv);
             __syncthreads();
-            // ---- Jacobi-PCG on J x = -R, x0 = 0 -------------------------------------------
-            S loc[2] = {0, 0};
-            for (int i = threadIdx.x; i < n; i += blockDim.x) {
-                const S r = (S)(-R[i]);
-                const S z = pd[i] * r;
-                pr[i] = r;
-                pp[i] = z;
-                px[i] = 0;
-                loc[0] += r * z;
-                loc[1] += r * r;
-            }
-            block_sum<S, 2>(loc, lds_s, ph_s);
-            S rz = loc[0];
-            double rr = (double)loc[1];
+            for (int i = threadIdx.x; i < n; i += blockDim.x) dinv[i] = (S)1 / jv[a.dpos[i]];
+            __syncthreads();
             const double ltarget = fmax(a.tol_lin * rn, 0.5 * target);
-            int k = 0;
-            while (rr > ltarget * ltarget && k < a.max_lin) {
-                S pqv[1] = {spmv_dot<S>(n, a.rowptr, a.colidx, jv, pp, pq)};
-                block_sum<S, 1>(pqv, lds_s, ph_s);
-                if (!(pqv[0] > (S)0)) break;            // loss of positivity: stop, Newton decides
-                const S alpha = rz / pqv[0];
-                S l2[2] = {0, 0};
-                for (int i = threadIdx.x; i < n; i += blockDim.x) {
-                    px[i] += alpha * pp[i];
-                    const S r = pr[i] - alpha * pq[i];
-                    pr[i] = r;
-                    l2[0] += r * (pd[i] * r);
-                    l2[1] += r * r;
-                }
-                block_sum<S, 2>(l2, lds_s, ph_s);
-                const S beta = l2[0] / rz;
-                rz = l2[0];
-                rr = (double)l2[1];
-                for (int i = threadIdx.x; i < n; i += blockDim.x) pp[i] = pd[i] * pr[i] + beta * pp[i];
-                __syncthreads();
-                ++k;
-            }
+            int k;
+            if constexpr (R > 0)
+                k = pcg_regs<S, R>(a, jv, p_l, d_l, tq_l, R_, px, ltarget, lds_s, ph_s);
+            else
+                k = pcg_mem<S, LP>(a, jv, pv, p_l, d_l, R_, ltarget, lds_s, ph_s);
+            __syncthreads();
             lin_total += k;
             lin_max = k > lin_max ? k : lin_max;
             if (k == a.max_lin) ++capped;
@@ -368,8 +522,8 @@ __global__ __launch_bounds__(1024) void k_fine_sweep(FineArgs a) {
             }
             if (accepted) {
                 for (int i = threadIdx.x; i < n; i += blockDim.x) u[i] = u[i] + lam * (double)px[i];
-                double* tmp = R;
-                R = Rt;
+                double* tmp = R_;
+                R_ = Rt;
                 Rt = tmp;
                 rn = rt;
                 __syncthreads();
@@ -393,6 +547,55 @@ __global__ __launch_bounds__(1024) void k_fine_sweep(FineArgs a) {
         cnt[C_RESID] = resid_evals;
     }
 }
+
+namespace {
+
+constexpr int kRegBlock = 512;     // workgroup of the register-row path (256 VGPRs per lane)
+constexpr size_t kLdsBudget = 160 * 1024 - 4096;
+
+struct FineShape {
+    int R, block, LP;
+    size_t lds;
+};
+
+// Register rows (R in {1, 2, 4}, 512 threads) when the mesh fits; otherwise the memory
+// path with as much of p / the inverse diagonal in LDS as fits.
+FineShape pick_shape(int n, size_t n_pad, int n_tail, size_t elem, int block_req) {
+    const size_t tail = (size_t)std::max(n_tail, 1) * elem;
+    if (block_req != kFineBlock) {
+        for (int R : {1, 2, 4}) {
+            if ((long)R * kRegBlock < n) continue;
+            const size_t lds = 2 * n_pad * elem + tail;
+            if (lds <= kLdsBudget) return {R, kRegBlock, 2, lds};
+        }
+    }
+    if (2 * n_pad * elem <= kLdsBudget) return {0, kFineBlock, 2, 2 * n_pad * elem};
+    if (n_pad * elem <= kLdsBudget) return {0, kFineBlock, 1, n_pad * elem};
+    return {0, kFineBlock, 0, 0};
+}
+
+template <typename S, int R, int BLOCK, int LP>
+void launch_shape(const FineArgs& a, int N, size_t lds, hipStream_t s) {
+    static bool attr_set = false;
+    if (!attr_set) {
+        PPC_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fine_sweep<S, R, BLOCK, LP>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBudget));
+        attr_set = true;
+    }
+    hipLaunchKernelGGL((k_fine_sweep<S, R, BLOCK, LP>), dim3(N), dim3(BLOCK), lds, s, a);
+}
+
+template <typename S>
+void launch_typed(const FineArgs& a, int N, const FineShape& sh, hipStream_t s) {
+    if (sh.R == 1) launch_shape<S, 1, kRegBlock, 2>(a, N, sh.lds, s);
+    else if (sh.R == 2) launch_shape<S, 2, kRegBlock, 2>(a, N, sh.lds, s);
+    else if (sh.R == 4) launch_shape<S, 4, kRegBlock, 2>(a, N, sh.lds, s);
+    else if (sh.LP == 2) launch_shape<S, 0, kFineBlock, 2>(a, N, sh.lds, s);
+    else if (sh.LP == 1) launch_shape<S, 0, kFineBlock, 1>(a, N, sh.lds, s);
+    else launch_shape<S, 0, kFineBlock, 0>(a, N, 0, s);
+}
+
+}  // namespace
 
 void launch_fine_sweep(ppc_problem* pr, const ppc_params* p, const double* U, double* F,
                        hipStream_t s) {
@@ -437,13 +640,24 @@ void launch_fine_sweep(ppc_problem* pr, const ppc_params* p, const double* U, do
     a.elem = w.felem;
     a.count = w.fcount;
     a.n_pad = (long)w.n_pad;
-    a.nnz_pad = (long)w.nnz_pad;
+    a.vals_pad = (long)w.vals_pad;
     a.ne_pad = (long)w.ne_pad;
-    const int block = p->block > 0 ? p->block : kFineBlock;
+    a.W = d.ell_w;
+    a.ntail = d.n_tail;
+    a.nvals = d.n_vals;
+    a.ell_pad = (long)d.ell_pad;
+    a.ecol = d.ecol;
+    a.vslot = d.vslot;
+    a.dpos = d.dpos;
+    a.tail_row = d.tail_row;
+    a.tail_ptr = d.tail_ptr;
+    a.tail_col = d.tail_col;
+    const size_t elem = p->precision == 0 ? sizeof(double) : sizeof(float);
+    const FineShape sh = pick_shape(d.n_free, w.n_pad, d.n_tail, elem, p->block);
     if (p->precision == 0)
-        hipLaunchKernelGGL(k_fine_sweep<double>, dim3(p->N), dim3(block), 0, s, a);
+        launch_typed<double>(a, p->N, sh, s);
     else
-        hipLaunchKernelGGL(k_fine_sweep<float>, dim3(p->N), dim3(block), 0, s, a);
+        launch_typed<float>(a, p->N, sh, s);
     PPC_HIP(hipGetLastError());
 }
 

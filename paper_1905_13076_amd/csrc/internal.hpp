@@ -16,6 +16,7 @@ constexpr int kMaxMaterials = 64;   // validated bound of the material table
 constexpr int kFineBlock = 1024;        // default fine-kernel workgroup
 constexpr int kCocgBlock = 1024;
 constexpr int kRowGroup = 8;            // lanes per CSR row in the vector SpMV
+constexpr int kEllMaxWidth = 8;         // rows longer than this go to the ELL tail
 
 // ----------------------------------------------------------------------------------
 // error plumbing: every internal failure throws ppc::Error, caught at the C-ABI
@@ -76,6 +77,20 @@ struct DeviceMesh {
     double* mdiag = nullptr;   // [n_free]
     double* fload = nullptr;   // [n_free] load per ampere F
     double fnorm = 0.0;        // ||F||_2
+    // ELL copy of the pattern for the fine-sweep SpMV: rows of length <= ell_w are stored
+    // column-major [ell_w][n_pad]; longer rows ("tail" rows) are stored whole in a
+    // separate CSR block whose value positions follow the ELL block.
+    int ell_w = 0;             // ELL width
+    int n_tail = 0;            // rows stored in the tail
+    int tail_nnz = 0;
+    int n_vals = 0;            // value positions: ell_w * n_pad + tail_nnz
+    int* ecol = nullptr;       // [ell_w][n_pad]; tail rows: ecol[0][i] = -1, ecol[1][i] = tail index
+    int* vslot = nullptr;      // [n_vals] CSR slot of each value position (-1: padding)
+    int* dpos = nullptr;       // [n_free] value position of the diagonal
+    int* tail_row = nullptr;   // [n_tail]
+    int* tail_ptr = nullptr;   // [n_tail + 1]
+    int* tail_col = nullptr;   // [tail_nnz]
+    size_t ell_pad = 0;        // n_pad used by the ELL arrays
     bool nonlinear = false;    // any element with a Brauer law
     int n_contrib = 0;
 };
@@ -106,7 +121,7 @@ struct Workspace {
     double* partial = nullptr; // reduction partials
     double* scal = nullptr;    // small scalars
     double* host_scal = nullptr; // pinned host mirror
-    size_t n_pad = 0, nnz_pad = 0, ne_pad = 0;
+    size_t n_pad = 0, nnz_pad = 0, ne_pad = 0, vals_pad = 0;
 };
 
 void workspace_free(Workspace& w);

@@ -333,6 +333,53 @@ void build_problem(ppc_problem* pr, const ppc_mesh* mesh, const ppc_material* ma
         for (size_t k = 0; k < codes.size(); ++k) slot_src[fillp[code_slot[k]]++] = codes[k];
     }
     d.n_contrib = (int)codes.size();
+    // ELL layout for the fine sweep
+    const size_t NP = (n + 63) / 64 * 64;
+    int W = 1;
+    bool has_long = false;
+    for (int i = 0; i < n; ++i) {
+        const int len = rowptr[i + 1] - rowptr[i];
+        if (len <= kEllMaxWidth) W = std::max(W, len);
+        else has_long = true;
+    }
+    if (has_long) W = std::max(W, 2);   // slot 1 of a tail row holds its tail index
+    std::vector<int> ecol((size_t)W * NP, 0), tail_row, tail_ptr(1, 0), tail_col, dpos(n);
+    std::vector<int> vslot((size_t)W * NP, -1);
+    for (int i = 0; i < n; ++i) {
+        const int len = rowptr[i + 1] - rowptr[i];
+        if (len <= W) {
+            for (int k = 0; k < W; ++k) {
+                const size_t v = (size_t)k * NP + i;
+                if (k < len) {
+                    ecol[v] = colidx[rowptr[i] + k];
+                    vslot[v] = rowptr[i] + k;
+                    if (ecol[v] == i) dpos[i] = (int)v;
+                } else {
+                    ecol[v] = i;   // padding: zero value times the row's own entry
+                }
+            }
+        } else {
+            ecol[i] = -1;
+            ecol[NP + i] = (int)tail_row.size();
+            tail_row.push_back(i);
+            for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) tail_col.push_back(colidx[k]);
+            tail_ptr.push_back((int)tail_col.size());
+        }
+    }
+    const size_t tail_base = (size_t)W * NP;
+    for (size_t t = 0; t < tail_row.size(); ++t) {
+        const int i = tail_row[t];
+        for (int k = tail_ptr[t]; k < tail_ptr[t + 1]; ++k) {
+            const int slot = rowptr[i] + (k - tail_ptr[t]);
+            vslot.push_back(slot);
+            if (colidx[slot] == i) dpos[i] = (int)(tail_base + k);
+        }
+    }
+    d.ell_w = W;
+    d.ell_pad = NP;
+    d.n_tail = (int)tail_row.size();
+    d.tail_nnz = (int)tail_col.size();
+    d.n_vals = (int)vslot.size();
     // free node -> incident vertices
     std::vector<int> node_ptr(n + 1, 0);
     for (int e = 0; e < ne; ++e)
@@ -382,13 +429,13 @@ void build_problem(ppc_problem* pr, const ppc_mesh* mesh, const ppc_material* ma
         }
         pr->wavtab = upload(wt, s);
     }
-    Wave& W = pr->wave;
-    W.f0 = exc->f0;
-    W.n_h = exc->n_h;
+    Wave& wave = pr->wave;
+    wave.f0 = exc->f0;
+    wave.n_h = exc->n_h;
     for (int k = 0; k < exc->n_h; ++k) {
-        W.order[k] = exc->order[k];
-        W.amp[k] = exc->amp[k];
-        W.phase[k] = exc->phase[k];
+        wave.order[k] = exc->order[k];
+        wave.amp[k] = exc->amp[k];
+        wave.phase[k] = exc->phase[k];
     }
     // upload
     d.rowptr = upload(rowptr, s);
@@ -399,6 +446,12 @@ void build_problem(ppc_problem* pr, const ppc_mesh* mesh, const ppc_material* ma
     d.node_ptr = upload(node_ptr, s);
     d.node_src = upload(node_src, s);
     d.efree = upload(efree, s);
+    d.ecol = upload(ecol, s);
+    d.vslot = upload(vslot, s);
+    d.dpos = upload(dpos, s);
+    d.tail_row = upload(tail_row, s);
+    d.tail_ptr = upload(tail_ptr, s);
+    d.tail_col = upload(tail_col, s);
     d.free_node = upload(free_node, s);
     d.mat = upload(std::vector<int>(mat->mat_id, mat->mat_id + ne), s);
     d.xy = upload(std::vector<double>(mesh->xy, mesh->xy + 2 * (size_t)nn), s);
@@ -429,7 +482,8 @@ void build_problem(ppc_problem* pr, const ppc_mesh* mesh, const ppc_material* ma
 void mesh_free(DeviceMesh& d) {
     void* ptrs[] = {d.rowptr, d.colidx, d.diag, d.slot_ptr, d.slot_src, d.node_ptr, d.node_src,
                     d.efree, d.free_node, d.mat, d.xy, d.tri, d.area, d.k0, d.gx, d.gy,
-                    d.sigma, d.js, d.mval, d.mdiag, d.fload};
+                    d.sigma, d.js, d.mval, d.mdiag, d.fload, d.ecol, d.vslot, d.dpos,
+                    d.tail_row, d.tail_ptr, d.tail_col};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     d = DeviceMesh{};

@@ -149,3 +149,38 @@ def test_c2_nonlinear_fp64_matches_oracle():
            f"newton={st['newton_total']} cocg={st['cocg_total']}")
     assert e <= 1e-10
     assert st["max_b_steel"] > 1.5            # the sheath saturates in the steady state
+
+
+# fine-sweep kernel paths: (mesh rings, ntheta, precision, forced memory path)
+#   nr=20  (761 free)   -> register rows (R=2, 512 threads) or forced memory path
+#   nr=60  (7,081)      -> memory path, p and inverse diagonal in LDS (FP64)
+#   nr=80  (12,641)     -> memory path, p in LDS only (FP64); p + diagonal (FP32)
+#   nr=100 (19,801)     -> memory path, nothing in LDS (FP64)
+@pytest.mark.parametrize("nr,prec,force", [
+    (20, 0, False), (20, 0, True), (20, 1, False),
+    (60, 0, False), (60, 1, False),
+    (80, 0, False), (80, 1, False),
+    (100, 0, False),
+])
+def test_fine_sweep_kernel_paths_match_oracle(nr, prec, force):
+    """Every PCG path of the fine-sweep kernel, FP64 and mixed (FP32 Jacobian/PCG under
+    the FP64 Newton residual), against the oracle: the Newton residual is FP64 in both
+    forms, so both reach the FP64 answer."""
+    import torch
+    import paper_1905_13076_amd as P
+    from oracle.fe import FE
+    from oracle import periodic
+    prob = coax.c2(nr=nr, ntheta=2 * nr, N=4, m=2)
+    fe = FE(prob)
+    rng = np.random.default_rng(nr)
+    r = np.hypot(prob.xy[fe.free, 0], prob.xy[fe.free, 1])
+    U0 = np.outer(1.0 + 0.1 * rng.standard_normal(prob.N), 1e-4 * (3e-3 - r) / 3e-3)
+    Fo = periodic.fine_sweep(fe, U0)
+    banner(f"fine path nr={nr} prec={prec} force={force}")
+    pr = _problem(prob)
+    prm = P.problem_params(prob, precision=prec, block=1024 if force else 0,
+                           tol_lin=1e-8 if prec == 0 else 1e-4)
+    F, newton, lin = pr.fine_sweep(prm, torch.tensor(_nodal(fe, U0), device="cuda"))
+    e = rel(free_rows(F.cpu().numpy(), fe.free), Fo)
+    banner(f"fine path nr={nr} prec={prec} force={force} rel={e:.2e} newton={newton.tolist()} lin={lin.tolist()}")
+    assert e <= 1e-10
