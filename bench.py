@@ -28,6 +28,26 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+COUNTERS = os.path.join(ROOT, "profiles", "fine_sweep_c2_fp64_counters.md")
+FINE_SRC = os.path.join(ROOT, "paper_1905_13076_amd", "csrc", "fine.hip")
+
+
+def measured_traffic():
+    """HBM bytes per fine-sweep launch from the committed counter summary, if it was
+    taken on the current fine-sweep source (else None)."""
+    import hashlib
+    import re
+    if not os.path.exists(COUNTERS):
+        return None
+    text = open(COUNTERS).read()
+    m = re.search(r"fine.hip sha1: ([0-9a-f]{40})", text)
+    t = re.search(r"traffic_bytes_per_launch: (\d+)", text)
+    g = re.search(r"algorithmic_bytes_per_launch: (\d+)", text)
+    if not (m and t and g):
+        return None
+    if hashlib.sha1(open(FINE_SRC, "rb").read()).hexdigest() != m.group(1):
+        return None
+    return {"bytes": int(t.group(1)), "algorithmic_bytes_same_launch": int(g.group(1))}
 
 
 def parse():
@@ -41,6 +61,9 @@ def parse():
     ap.add_argument("--cpu-baseline", dest="cpu", action="store_true", default=True)
     ap.add_argument("--no-cpu-baseline", dest="cpu", action="store_false")
     ap.add_argument("--cpu-procs", type=int, default=16)
+    ap.add_argument("--probe", choices=["fine"], default=None,
+                    help="counter-collection mode: a 512 MiB device copy of known size (the "
+                         "calibration kernel) and one fine sweep from the oracle fixed point")
     return ap.parse_args()
 
 
@@ -102,6 +125,36 @@ def cpu_baseline(prob, ref, procs):
     }
 
 
+def probe_fine(a, prob, ref):
+    """One device copy of known size, then one warm-up and one measured fine sweep
+    (all N chains, one launch) started from the oracle fixed point."""
+    import numpy as np
+    import torch
+    import paper_1905_13076_amd as P
+    from paper_1905_13076_amd.traffic import fine_sweep_bytes
+    torch.cuda.set_device(0)
+    src = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device="cuda")   # 512 MiB
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    h = P.Handle(0)
+    pr = P.Problem(h, prob)
+    prec = 0 if a.precision == "fp64" else 1
+    prm = P.problem_params(prob, precision=prec, **({"tol_lin": 1e-4} if prec == 1 else {}))
+    U = np.zeros((prob.N, pr.n_nodes))
+    U[:, ref["free"]] = ref["U"]
+    Ud = torch.tensor(U, device="cuda")
+    pr.fine_sweep(prm, Ud)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    F, newton, lin = pr.fine_sweep(prm, Ud)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    print(json.dumps({"probe": "fine", "copy_bytes_each_way": src.numel() * 8, "sweep_ms": dt * 1e3,
+                      "newton_total": int(newton.sum()), "lin_total": int(lin.sum())}), flush=True)
+    return 0
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -110,6 +163,8 @@ def main():
         return 2
     prob = workload(a.workload)
     ref = load_reference(a.workload)
+    if a.probe == "fine":
+        return probe_fine(a, prob, ref)
     cpu = None
     if a.cpu and ref is not None:
         # before any GPU initialisation: the oracle's worker pool forks this process
@@ -155,6 +210,7 @@ def main():
     launch_s = fine_ms / launches / 1e3
     achieved = bytes_launch / launch_s / 1e9
     value = a.steps / wall
+    traffic = measured_traffic() if prec == 0 else None
     line = {
         "metric": "periodic steady states/s at 1e-6 rel. err vs FP64 oracle; achieved HBM GB/s",
         "value": value,
@@ -191,7 +247,11 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": (traffic or {}).get("bytes"),
+            "traffic_source": ("rocprofv3 FETCH_SIZE+WRITE_SIZE (copy-calibrated) of one C2 fine sweep "
+                               "from the oracle fixed point, profiles/fine_sweep_c2_fp64_counters.md; "
+                               f"algorithmic bytes of that launch {traffic['algorithmic_bytes_same_launch']}")
+                              if traffic else None,
             "bytes_per_launch": bytes_launch,
             "launch_ms": launch_s * 1e3,
             "launches": launches,

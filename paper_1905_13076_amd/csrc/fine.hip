@@ -55,6 +55,7 @@ struct FineArgs {
     long n_pad, vals_pad, ne_pad;
     // ELL pattern of the fine-sweep SpMV
     int W, ntail, nvals;
+    int predictor;
     long ell_pad;
     const int* ecol;
     const int* vslot;
@@ -107,7 +108,7 @@ __device__ inline void block_sum(T (&v)[K], T* lds, int& phase) {
 }
 
 enum { E_F0 = 0, E_W0 = 3, E_NU = 6, E_SF = 7 };
-enum { V_U = 0, V_UP = 1, V_R = 2, V_RT = 3 };
+enum { V_U = 0, V_UP = 1, V_R = 2, V_RT = 3, V_UPP = 4 };
 enum { P_R = 0, P_P = 1, P_Q = 2, P_X = 3, P_D = 4 };
 enum { C_STATUS = 0, C_NEWTON = 1, C_LIN = 2, C_NEWTON_MAX = 3, C_LIN_MAX = 4, C_CAPPED = 5,
        C_FAILSTEP = 6, C_RESID = 7 };
@@ -213,33 +214,31 @@ __device__ inline S tail_row_sum(const FineArgs& a, const S* __restrict__ jv, PV
     return acc;
 }
 
-// Jacobi-PCG on J x = -R with the rows of each thread (i = tid + k B, k < R) held in
-// registers; p and the inverse diagonal live in LDS so the SpMV gathers never leave
-// the CU; only the ELL values and columns stream from memory.  Returns the iteration
-// count; x is written to xout.
+// Jacobi-PCG on J x = -R for meshes that fit the CU: the rows of each thread
+// (i = tid + k B, k < R) keep x and q in registers; p, r and the inverse diagonal (FP32:
+// it only shapes the preconditioner) live in LDS, so the SpMV gathers and every vector
+// pass stay on the CU and only the ELL values and columns stream from memory.
 template <typename S, int R>
 __device__ int pcg_regs(const FineArgs& a, const S* __restrict__ jv, S* __restrict__ p_l,
-                        const S* __restrict__ d_l, S* __restrict__ tq_l, const double* __restrict__ Rres,
-                        S* __restrict__ xout, double tgt, S* lds_s, int& ph) {
+                        S* __restrict__ r_l, const float* __restrict__ d_l, S* __restrict__ tq_l,
+                        const double* __restrict__ Rres, S* __restrict__ xout, double tgt,
+                        S* lds_s, int& ph) {
     const int B = blockDim.x, tid = threadIdx.x, n = a.n;
     const int lane = tid & 63, wave = tid >> 6, nw = B >> 6;
     const long NP = a.ell_pad;
     const int W = a.W;
-    S x[R], r[R], p[R], q[R];
+    S x[R], q[R];
     unsigned tailmask = 0;
     S loc[2] = {0, 0};
 #pragma unroll
     for (int k = 0; k < R; ++k) {
         const int i = tid + k * B;
         x[k] = 0;
-        r[k] = 0;
-        p[k] = 0;
         q[k] = 0;
         if (i < n) {
             const S rv = (S)(-Rres[i]);
-            const S z = d_l[i] * rv;
-            r[k] = rv;
-            p[k] = z;
+            const S z = (S)d_l[i] * rv;
+            r_l[i] = rv;
             p_l[i] = z;
             loc[0] += rv * z;
             loc[1] += rv * rv;
@@ -259,7 +258,7 @@ __device__ int pcg_regs(const FineArgs& a, const S* __restrict__ jv, S* __restri
                 S acc = 0;
                 for (int w = 0; w < W; ++w) acc += jv[w * NP + i] * p_l[a.ecol[w * NP + i]];
                 q[k] = acc;
-                dot[0] += p[k] * acc;
+                dot[0] += p_l[i] * acc;
             }
         }
         for (int t = wave; t < a.ntail; t += nw) {
@@ -279,11 +278,12 @@ __device__ int pcg_regs(const FineArgs& a, const S* __restrict__ jv, S* __restri
             const int i = tid + k * B;
             if (i < n) {
                 if ((tailmask >> k) & 1u) q[k] = tq_l[a.ecol[NP + i]];
-                x[k] += alpha * p[k];
-                r[k] -= alpha * q[k];
-                const S z = d_l[i] * r[k];
-                l2[0] += r[k] * z;
-                l2[1] += r[k] * r[k];
+                x[k] += alpha * p_l[i];
+                const S rv = r_l[i] - alpha * q[k];
+                r_l[i] = rv;
+                const S z = (S)d_l[i] * rv;
+                l2[0] += rv * z;
+                l2[1] += rv * rv;
             }
         }
         block_sum<S, 2>(l2, lds_s, ph);
@@ -295,10 +295,7 @@ __device__ int pcg_regs(const FineArgs& a, const S* __restrict__ jv, S* __restri
 #pragma unroll
         for (int k = 0; k < R; ++k) {
             const int i = tid + k * B;
-            if (i < n) {
-                p[k] = d_l[i] * r[k] + beta * p[k];
-                p_l[i] = p[k];
-            }
+            if (i < n) p_l[i] = (S)d_l[i] * r_l[i] + beta * p_l[i];
         }
         __syncthreads();
     }
@@ -432,14 +429,17 @@ __global__ __launch_bounds__(BLOCK) void k_fine_sweep(FineArgs a) {
     double* up = vec + V_UP * NP;
     double* R_ = vec + V_R * NP;
     double* Rt = vec + V_RT * NP;
+    double* upp = vec + V_UPP * NP;
     S* pv = reinterpret_cast<S*>(a.pcg) + (long)c * kPcgVec * NP;
     S* px = pv + P_X * NP;
     S* jv = reinterpret_cast<S*>(a.jac) + (long)c * a.vals_pad;
     double* el = a.elem + (long)c * 8 * a.ne_pad;
     S* p_l = reinterpret_cast<S*>(dyn_lds);
-    S* d_l = p_l + NP;
-    S* tq_l = d_l + NP;
-    S* dinv = (R > 0 || LP == 2) ? d_l : pv + P_D * NP;
+    S* d_l = p_l + NP;                        // memory path: inverse diagonal (LP == 2)
+    S* r_l = p_l + NP;                        // register path: r
+    float* df_l = reinterpret_cast<float*>(r_l + NP);   // register path: FP32 diagonal
+    S* tq_l = reinterpret_cast<S*>(df_l + NP);
+    S* dinv = LP == 2 ? d_l : pv + P_D * NP;
 
     const double* U0 = a.U + (long)c * n;
     for (int i = threadIdx.x; i < n; i += blockDim.x) u[i] = U0[i];
@@ -452,7 +452,13 @@ __global__ __launch_bounds__(BLOCK) void k_fine_sweep(FineArgs a) {
 
     for (int j = 1; j <= a.m && status == 0; ++j) {
         const double t = t0 + j * a.dt;
-        for (int i = threadIdx.x; i < n; i += blockDim.x) up[i] = u[i];
+        // u_{j-1} -> u_prev; Newton starts from the linear extrapolation 2 u_{j-1} - u_{j-2}
+        // (j >= 2), which changes only the iteration count, not the step's solution
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            const double uj = u[i];
+            if (j >= 2 && a.predictor) u[i] = 2.0 * uj - up[i];
+            up[i] = uj;
+        }
         __syncthreads();
         const double cur = current(t, a.f0, a.n_h, a.wavtab);
         double v1[1] = {mass_norm2(a, up)};
@@ -474,12 +480,16 @@ __global__ __launch_bounds__(BLOCK) void k_fine_sweep(FineArgs a) {
             if (it == a.max_newton) { status = PPC_ERR_NEWTON; fail_step = j; break; }
             assemble<S>(a, el, inv_dt, jv);
             __syncthreads();
-            for (int i = threadIdx.x; i < n; i += blockDim.x) dinv[i] = (S)1 / jv[a.dpos[i]];
+            if constexpr (R > 0) {
+                for (int i = threadIdx.x; i < n; i += blockDim.x) df_l[i] = (float)(1.0 / (double)jv[a.dpos[i]]);
+            } else {
+                for (int i = threadIdx.x; i < n; i += blockDim.x) dinv[i] = (S)1 / jv[a.dpos[i]];
+            }
             __syncthreads();
             const double ltarget = fmax(a.tol_lin * rn, 0.5 * target);
             int k;
             if constexpr (R > 0)
-                k = pcg_regs<S, R>(a, jv, p_l, d_l, tq_l, R_, px, ltarget, lds_s, ph_s);
+                k = pcg_regs<S, R>(a, jv, p_l, r_l, df_l, tq_l, R_, px, ltarget, lds_s, ph_s);
             else
                 k = pcg_mem<S, LP>(a, jv, pv, p_l, d_l, R_, ltarget, lds_s, ph_s);
             __syncthreads();
@@ -550,7 +560,6 @@ __global__ __launch_bounds__(BLOCK) void k_fine_sweep(FineArgs a) {
 
 namespace {
 
-constexpr int kRegBlock = 512;     // workgroup of the register-row path (256 VGPRs per lane)
 constexpr size_t kLdsBudget = 160 * 1024 - 4096;
 
 struct FineShape {
@@ -558,15 +567,17 @@ struct FineShape {
     size_t lds;
 };
 
-// Register rows (R in {1, 2, 4}, 512 threads) when the mesh fits; otherwise the memory
-// path with as much of p / the inverse diagonal in LDS as fits.
+// Register rows (R in {1, 2, 4, 8} rows per thread, 1024 threads) when p, r, the FP32
+// diagonal and the tail sums fit in LDS; otherwise the memory path with as much of p /
+// the inverse diagonal in LDS as fits.
 FineShape pick_shape(int n, size_t n_pad, int n_tail, size_t elem, int block_req) {
     const size_t tail = (size_t)std::max(n_tail, 1) * elem;
     if (block_req != kFineBlock) {
-        for (int R : {1, 2, 4}) {
-            if ((long)R * kRegBlock < n) continue;
-            const size_t lds = 2 * n_pad * elem + tail;
-            if (lds <= kLdsBudget) return {R, kRegBlock, 2, lds};
+        for (int R : {1, 2, 4, 8}) {
+            if ((long)R * kFineBlock < n) continue;
+            const size_t lds = 2 * n_pad * elem + n_pad * sizeof(float) + tail;
+            if (lds <= kLdsBudget) return {R, kFineBlock, 0, lds};
+            break;
         }
     }
     if (2 * n_pad * elem <= kLdsBudget) return {0, kFineBlock, 2, 2 * n_pad * elem};
@@ -587,9 +598,10 @@ void launch_shape(const FineArgs& a, int N, size_t lds, hipStream_t s) {
 
 template <typename S>
 void launch_typed(const FineArgs& a, int N, const FineShape& sh, hipStream_t s) {
-    if (sh.R == 1) launch_shape<S, 1, kRegBlock, 2>(a, N, sh.lds, s);
-    else if (sh.R == 2) launch_shape<S, 2, kRegBlock, 2>(a, N, sh.lds, s);
-    else if (sh.R == 4) launch_shape<S, 4, kRegBlock, 2>(a, N, sh.lds, s);
+    if (sh.R == 1) launch_shape<S, 1, kFineBlock, 0>(a, N, sh.lds, s);
+    else if (sh.R == 2) launch_shape<S, 2, kFineBlock, 0>(a, N, sh.lds, s);
+    else if (sh.R == 4) launch_shape<S, 4, kFineBlock, 0>(a, N, sh.lds, s);
+    else if (sh.R == 8) launch_shape<S, 8, kFineBlock, 0>(a, N, sh.lds, s);
     else if (sh.LP == 2) launch_shape<S, 0, kFineBlock, 2>(a, N, sh.lds, s);
     else if (sh.LP == 1) launch_shape<S, 0, kFineBlock, 1>(a, N, sh.lds, s);
     else launch_shape<S, 0, kFineBlock, 0>(a, N, 0, s);
@@ -652,6 +664,7 @@ void launch_fine_sweep(ppc_problem* pr, const ppc_params* p, const double* U, do
     a.tail_row = d.tail_row;
     a.tail_ptr = d.tail_ptr;
     a.tail_col = d.tail_col;
+    a.predictor = p->reserved[0] == 0 ? 1 : 0;
     const size_t elem = p->precision == 0 ? sizeof(double) : sizeof(float);
     const FineShape sh = pick_shape(d.n_free, w.n_pad, d.n_tail, elem, p->block);
     if (p->precision == 0)

@@ -150,7 +150,7 @@ struct ppc_problem {
 
 namespace ppc {
 
-constexpr int kFineVec = 4;   // u, uprev, R, du(FP64 copy)
+constexpr int kFineVec = 5;   // u, u_prev, R, R_trial, u_{j-2}
 constexpr int kPcgVec = 5;    // r, p, q, x, dinv
 
 // set-up (setup.hip)
