@@ -175,10 +175,28 @@ int ppc_destroy(ppc_handle* h);
 int ppc_problem_create(ppc_handle* h, const ppc_mesh* mesh, const ppc_material* mat,
                        const ppc_excitation* exc, ppc_problem** out);
 
+/* Copy n_designs independent problems (e.g. cable designs of uneven size) to the device
+ * as one batched problem.  Each design is validated and set up as by ppc_problem_create.
+ * ppc_solve / ppc_solve_device on a batched problem run PP-PC on every design at once:
+ * the fine sweeps of all active designs share launches and their harmonic solves share
+ * one COCG launch; each design stops at its own eps <= tol_ppc.  Batched layouts:
+ * U_init / U_out are the designs' [N * n_nodes_d] blocks concatenated in design order;
+ * resid_out is [n_designs][max_iters + 1]; iters_out is [n_designs]; stats are summed
+ * (eps: the largest final eps).  ppc_fine_sweep_device and ppc_coarse_correction_device
+ * reject batched problems (PPC_ERR_ARG). */
+int ppc_problem_create_batch(ppc_handle* h, int32_t n_designs, const ppc_mesh* meshes,
+                             const ppc_material* mats, const ppc_excitation* excs,
+                             ppc_problem** out);
+
+/* Designs of a problem (1 for a single one) and, if non-null, each design's node and
+ * free-node counts (host arrays [n_designs]). */
+int ppc_batch_info(const ppc_problem* pr, int32_t* n_designs, int32_t* n_nodes, int32_t* n_free);
+
 /* Free a problem's device memory (null-safe). */
 int ppc_problem_destroy(ppc_problem* pr);
 
-/* Sizes of a problem: free nodes, CSR entries among free nodes, triangles, nodes. */
+/* Sizes of a problem: free nodes, CSR entries among free nodes, triangles, nodes
+ * (summed over the designs of a batched problem). */
 int ppc_problem_info(const ppc_problem* pr, int32_t* n_free, int32_t* nnz, int32_t* n_tri,
                      int32_t* n_nodes);
 

@@ -18,6 +18,9 @@ import scipy.sparse.linalg as spla
 
 NEWTON_TOL = 1e-13
 NEWTON_MAXIT = 50
+# A residual that no longer halves while below FLOOR_CAP * scale sits at the rounding
+# floor of its own evaluation: the step is solved as far as FP64 can resolve it.
+FLOOR_CAP = 1e-9
 
 
 class NewtonFailure(RuntimeError):
@@ -31,10 +34,11 @@ def step_residual(fe, u, u_prev, t, dt):
 def ie_step(fe, u_prev, t, dt, tol=NEWTON_TOL, maxit=NEWTON_MAXIT, stats=None):
     """One implicit-Euler step from u_prev to time t.
 
-    Stops when ||R|| <= tol * (||f(t)|| + ||M u_prev||/dt), or when the Newton
-    correction has reached rounding level (||du|| <= 4 eps ||u||) so that no
-    further progress is representable.  Backtracking: lambda = 1, 1/2, ... 2^-20
-    until ||R(u + lambda du)|| <= (1 - 1e-4 lambda) ||R(u)||."""
+    Stops when ||R|| <= tol * scale, scale = ||f(t)|| + ||M u_prev||/dt; or when the
+    residual has reached the rounding floor of its evaluation: the Newton correction is
+    at rounding level (||du|| <= 4 eps ||u||), or an accepted step fails to halve ||R||
+    while ||R|| <= FLOOR_CAP * scale, or the line search stalls there.  Backtracking:
+    lambda = 1, 1/2, ... 2^-20 until ||R(u + lambda du)|| <= (1 - 1e-4 lambda) ||R(u)||."""
     f_norm = np.linalg.norm(fe.f(t))
     scale = f_norm + np.linalg.norm(fe.M @ u_prev) / dt
     u = u_prev.copy()
@@ -63,10 +67,14 @@ def ie_step(fe, u_prev, t, dt, tol=NEWTON_TOL, maxit=NEWTON_MAXIT, stats=None):
             lam *= 0.5
             if lam < 2.0 ** -20:
                 # no decrease is representable: the iterate sits at rounding level
-                if rn <= 1e3 * tol * scale:
+                if rn <= FLOOR_CAP * scale:
                     return u, it
                 raise NewtonFailure(f"line search failed at t={t}: ||R||={rn:.3e}")
+        floor = rt > 0.5 * rn and rt <= FLOOR_CAP * scale
         u, R, rn = ut, Rt, rt
+        if floor:
+            it += 1
+            break
     if stats is not None:
         stats["newton"] = stats.get("newton", 0) + it
         stats["steps"] = stats.get("steps", 0) + 1

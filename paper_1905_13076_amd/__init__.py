@@ -3,7 +3,8 @@
 Hand-written HIP kernels for gfx950 behind the C-ABI of include/ppcmh.h; this package
 holds the kernels (csrc/), the build script and a thin ctypes binding.
 """
-from .ppc import Handle, PPCError, Problem, lib, params, problem_params, validate, validate_params
+from .ppc import (BatchProblem, Handle, PPCError, Problem, lib, params, problem_params, validate,
+                  validate_params)
 
-__all__ = ["Handle", "PPCError", "Problem", "lib", "params", "problem_params", "validate",
+__all__ = ["BatchProblem", "Handle", "PPCError", "Problem", "lib", "params", "problem_params", "validate",
            "validate_params"]

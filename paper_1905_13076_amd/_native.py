@@ -79,6 +79,9 @@ SIGNATURES = {
     "ppc_problem_create": (c_int, [c_void_p, POINTER(Mesh), POINTER(Material), POINTER(Excitation),
                                    POINTER(c_void_p)]),
     "ppc_problem_destroy": (c_int, [c_void_p]),
+    "ppc_problem_create_batch": (c_int, [c_void_p, c_int32, POINTER(Mesh), POINTER(Material),
+                                         POINTER(Excitation), POINTER(c_void_p)]),
+    "ppc_batch_info": (c_int, [c_void_p, PI, PI, PI]),
     "ppc_problem_info": (c_int, [c_void_p, PI, PI, PI, PI]),
     "ppc_solve": (c_int, [c_void_p, c_void_p, POINTER(Params), PD, PD, PD, PI, POINTER(Stats)]),
     "ppc_solve_device": (c_int, [c_void_p, c_void_p, POINTER(Params), c_void_p, c_void_p, PD, PI,

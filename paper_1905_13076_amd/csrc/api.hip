@@ -284,6 +284,167 @@ int solve_device(ppc_handle* h, ppc_problem* pr, const ppc_params* p, const doub
     return status;
 }
 
+
+// ---------------------------------------------------------------------------------------
+// batched designs: every design runs the same PP-PC iteration; the fine sweeps of all
+// active designs share launches (one per kernel shape), the harmonic solves of all active
+// designs share one COCG launch, and each design stops at its own eps <= tol.
+// ---------------------------------------------------------------------------------------
+struct DevBuf {
+    void* p = nullptr;
+    ~DevBuf() { if (p) (void)hipFree(p); }
+};
+
+int solve_batch_device(ppc_handle* h, ppc_problem* bp, const ppc_params* p, const double* U_init_dev,
+                       double* U_out_dev, double* resid_out, int32_t* iters_out, ppc_stats* st,
+                       hipStream_t s) {
+    PPC_HIP(hipSetDevice(h->device));
+    auto& parts = bp->parts;
+    const int D = (int)parts.size();
+    const int N = p->N, H = N / 2 + 1, R1 = p->max_iters + 1;
+    std::vector<size_t> off(D + 1, 0);
+    for (int d = 0; d < D; ++d) {
+        ensure_workspace(parts[d], p);
+        off[d + 1] = off[d] + (size_t)N * parts[d]->mesh.n_nodes;
+    }
+    ppc_stats S{};
+    for (int d = 0; d < D; ++d) {
+        S.n_free += parts[d]->mesh.n_free;
+        S.nnz += parts[d]->mesh.nnz;
+        S.n_tri += parts[d]->mesh.n_tri;
+    }
+    DevBuf scal, cargs, cwork;
+    PPC_HIP(hipMalloc(&scal.p, sizeof(double) * 3 * D));
+    PPC_HIP(hipMalloc(&cargs.p, sizeof(CocgArgs) * D));
+    PPC_HIP(hipMalloc(&cwork.p, sizeof(int2) * (size_t)D * H));
+    {
+        std::vector<CocgArgs> ca(D);
+        for (int d = 0; d < D; ++d) ca[d] = make_cocg_args(parts[d], p);
+        PPC_HIP(hipMemcpyAsync(cargs.p, ca.data(), sizeof(CocgArgs) * D, hipMemcpyHostToDevice, s));
+        PPC_HIP(hipStreamSynchronize(s));
+    }
+    std::vector<double> hs(3 * (size_t)D);
+    std::vector<int> counts(8 * (size_t)N);
+    std::vector<int> ccount(4 * (size_t)H);
+    std::vector<int2> cw;
+    hipEvent_t* ev = h->ev;
+    PPC_HIP(hipEventRecord(ev[4], s));
+
+    // harmonic solves of the listed designs (excitation: U^0 rows; else correction)
+    auto coarse = [&](const std::vector<int>& list, bool excitation) {
+        if (list.empty()) return;
+        for (int d : list) {
+            Workspace& w = parts[d]->ws;
+            launch_coarse_pre(parts[d], p, excitation ? nullptr : w.U, excitation ? nullptr : w.J, excitation, s);
+        }
+        cw.clear();
+        for (int d : list)
+            for (int q = 0; q < H; ++q) cw.push_back(make_int2(d, q));
+        PPC_HIP(hipMemcpyAsync(cwork.p, cw.data(), sizeof(int2) * cw.size(), hipMemcpyHostToDevice, s));
+        launch_cocg_batch(static_cast<CocgArgs*>(cargs.p), static_cast<int2*>(cwork.p), (int)cw.size(), s);
+        for (int d : list) launch_coarse_post(parts[d], p, parts[d]->ws.U, !excitation, s);
+        for (int d : list) {
+            PPC_HIP(hipMemcpyAsync(ccount.data(), parts[d]->ws.ccount, ccount.size() * sizeof(int),
+                                   hipMemcpyDeviceToHost, s));
+            PPC_HIP(hipStreamSynchronize(s));
+            for (int q = 0; q < H; ++q) {
+                if (ccount[4 * q] != 0)
+                    fail(ccount[4 * q], "design " + std::to_string(d) + ": " +
+                                            (ccount[4 * q] == PPC_ERR_BREAKDOWN ? "COCG breakdown" : "non-finite COCG residual"));
+                S.cocg_total += ccount[4 * q + 1];
+                S.cocg_max = std::max(S.cocg_max, ccount[4 * q + 1]);
+            }
+        }
+        S.coarse_solves++;
+    };
+
+    // initial iterate per design
+    std::vector<int> coarse_init;
+    for (int d = 0; d < D; ++d) {
+        Workspace& w = parts[d]->ws;
+        const long cnt = (long)N * parts[d]->mesh.n_free;
+        if (U_init_dev) {
+            launch_to_free(parts[d], N, U_init_dev + off[d], w.U, s);
+        } else {
+            int mode = p->init_mode;
+            if (mode == 0) mode = parts[d]->mesh.nonlinear ? 2 : 1;
+            if (mode == 2) fill(w.U, cnt, 0.0, s);
+            else coarse_init.push_back(d);
+        }
+    }
+    coarse(coarse_init, true);
+
+    FineBatch fb;
+    fine_batch_prepare(fb, parts, p, s);
+    std::vector<char> active(D, 1);
+    std::vector<int> iters(D, p->max_iters);
+    int status = PPC_OK;
+    int k = 0;
+    for (k = 0; k <= p->max_iters; ++k) {
+        PPC_HIP(hipEventRecord(ev[0], s));
+        fine_batch_launch(fb, active, s);
+        PPC_HIP(hipEventRecord(ev[1], s));
+        S.fine_launches++;
+        for (int d = 0; d < D; ++d)
+            if (active[d]) {
+                Workspace& w = parts[d]->ws;
+                launch_jumps(parts[d], N, w.U, w.F, w.J, static_cast<double*>(scal.p) + 3 * d, s);
+            }
+        PPC_HIP(hipMemcpyAsync(hs.data(), scal.p, sizeof(double) * 3 * D, hipMemcpyDeviceToHost, s));
+        PPC_HIP(hipStreamSynchronize(s));
+        S.fine_ms += elapsed(ev[0], ev[1]);
+        std::vector<int> corr;
+        for (int d = 0; d < D; ++d) {
+            if (!active[d]) continue;
+            PPC_HIP(hipMemcpy(counts.data(), parts[d]->ws.fcount, counts.size() * sizeof(int), hipMemcpyDeviceToHost));
+            for (int c = 0; c < N; ++c) {
+                const int* q = counts.data() + 8 * c;
+                if (q[0] != 0)
+                    fail(q[0], "design " + std::to_string(d) + ", fine chain " + std::to_string(c + 1) +
+                                   " failed at step " + std::to_string(q[6]));
+                S.newton_total += q[1];
+                S.lin_total += q[2];
+                S.newton_max = std::max(S.newton_max, q[3]);
+                S.lin_max = std::max(S.lin_max, q[4]);
+                S.lin_capped += q[5];
+                S.resid_total += q[7];
+            }
+            S.steps_total += (int64_t)N * p->m;
+            const double jj = hs[3 * d], uu = hs[3 * d + 1];
+            if (!std::isfinite(jj)) fail(PPC_ERR_NONFINITE, "design " + std::to_string(d) + ": non-finite jump norm");
+            const double eps = uu > 0.0 ? std::sqrt(jj) / std::sqrt(uu) : (jj == 0.0 ? 0.0 : INFINITY);
+            if (resid_out) resid_out[(size_t)d * R1 + k] = eps;
+            S.eps = std::max(S.eps, eps);
+            if (eps <= p->tol_ppc) {
+                active[d] = 0;
+                iters[d] = k;
+            } else if (k < p->max_iters) {
+                corr.push_back(d);
+            }
+        }
+        if (corr.empty()) break;
+        PPC_HIP(hipEventRecord(ev[2], s));
+        coarse(corr, false);
+        PPC_HIP(hipEventRecord(ev[3], s));
+        PPC_HIP(hipStreamSynchronize(s));
+        S.coarse_ms += elapsed(ev[2], ev[3]);
+    }
+    for (int d = 0; d < D; ++d)
+        if (active[d]) status = PPC_NOT_CONVERGED;
+    S.iterations = 0;
+    for (int d = 0; d < D; ++d) {
+        S.iterations = std::max(S.iterations, iters[d]);
+        if (iters_out) iters_out[d] = iters[d];
+        if (U_out_dev) launch_to_nodal(parts[d], N, parts[d]->ws.U, U_out_dev + off[d], s);
+    }
+    PPC_HIP(hipEventRecord(ev[5], s));
+    PPC_HIP(hipStreamSynchronize(s));
+    S.total_ms = elapsed(ev[4], ev[5]);
+    S.status = status;
+    if (st) *st = S;
+    return status;
+}
+
 }  // namespace
 }  // namespace ppc
 
@@ -401,8 +562,67 @@ int ppc_problem_create(ppc_handle* h, const ppc_mesh* mesh, const ppc_material* 
     });
 }
 
+int ppc_problem_create_batch(ppc_handle* h, int32_t n_designs, const ppc_mesh* meshes,
+                             const ppc_material* mats, const ppc_excitation* excs, ppc_problem** out) {
+    return guarded(h, [&]() -> int {
+        if (!out) fail(PPC_ERR_ARG, "null output pointer");
+        *out = nullptr;
+        if (!h) fail(PPC_ERR_ARG, "null handle");
+        if (n_designs < 1 || !meshes || !mats || !excs) fail(PPC_ERR_ARG, "need n_designs >= 1 and non-null arrays");
+        for (int d = 0; d < n_designs; ++d) {
+            std::string msg;
+            const int rc = validate_problem(&meshes[d], &mats[d], &excs[d], msg);
+            if (rc != PPC_OK) fail(rc, "design " + std::to_string(d) + ": " + msg);
+        }
+        PPC_HIP(hipSetDevice(h->device));
+        auto* bp = new ppc_problem();
+        bp->h = h;
+        bp->batch = true;
+        try {
+            for (int d = 0; d < n_designs; ++d) {
+                auto* q = new ppc_problem();
+                q->h = h;
+                bp->parts.push_back(q);
+                build_problem(q, &meshes[d], &mats[d], &excs[d], h->stream);
+            }
+        } catch (...) {
+            for (auto* q : bp->parts) {
+                q->h = nullptr;
+                ppc_problem_destroy(q);
+            }
+            bp->parts.clear();
+            delete bp;
+            throw;
+        }
+        h->n_problems++;
+        *out = bp;
+        return PPC_OK;
+    });
+}
+
+int ppc_batch_info(const ppc_problem* pr, int32_t* n_designs, int32_t* n_nodes, int32_t* n_free) {
+    if (!pr) return PPC_ERR_ARG;
+    if (!pr->batch) {
+        if (n_designs) *n_designs = 1;
+        if (n_nodes) n_nodes[0] = pr->mesh.n_nodes;
+        if (n_free) n_free[0] = pr->mesh.n_free;
+        return PPC_OK;
+    }
+    if (n_designs) *n_designs = (int32_t)pr->parts.size();
+    for (size_t d = 0; d < pr->parts.size(); ++d) {
+        if (n_nodes) n_nodes[d] = pr->parts[d]->mesh.n_nodes;
+        if (n_free) n_free[d] = pr->parts[d]->mesh.n_free;
+    }
+    return PPC_OK;
+}
+
 int ppc_problem_destroy(ppc_problem* pr) {
     if (!pr) return PPC_OK;
+    for (auto* q : pr->parts) {
+        q->h = nullptr;
+        ppc_problem_destroy(q);
+    }
+    pr->parts.clear();
     if (pr->h) (void)hipSetDevice(pr->h->device);
     workspace_free(pr->ws);
     mesh_free(pr->mesh);
@@ -416,6 +636,20 @@ int ppc_problem_destroy(ppc_problem* pr) {
 int ppc_problem_info(const ppc_problem* pr, int32_t* n_free, int32_t* nnz, int32_t* n_tri,
                      int32_t* n_nodes) {
     if (!pr) return PPC_ERR_ARG;
+    if (pr->batch) {
+        int32_t a = 0, b = 0, c = 0, e = 0;
+        for (auto* q : pr->parts) {
+            a += q->mesh.n_free;
+            b += q->mesh.nnz;
+            c += q->mesh.n_tri;
+            e += q->mesh.n_nodes;
+        }
+        if (n_free) *n_free = a;
+        if (nnz) *nnz = b;
+        if (n_tri) *n_tri = c;
+        if (n_nodes) *n_nodes = e;
+        return PPC_OK;
+    }
     if (n_free) *n_free = pr->mesh.n_free;
     if (nnz) *nnz = pr->mesh.nnz;
     if (n_tri) *n_tri = pr->mesh.n_tri;
@@ -430,6 +664,9 @@ int ppc_solve_device(ppc_handle* h, ppc_problem* pr, const ppc_params* p, const 
         check_handle_problem(h, pr);
         check_params(p);
         if (!U_out_dev) fail(PPC_ERR_ARG, "null U_out");
+        if (pr->batch)
+            return solve_batch_device(h, pr, p, U_init_dev, U_out_dev, resid_out, iters_out, stats,
+                                      pick_stream(h, stream));
         return solve_device(h, pr, p, U_init_dev, U_out_dev, resid_out, iters_out, stats,
                             pick_stream(h, stream));
     });
@@ -442,7 +679,12 @@ int ppc_solve(ppc_handle* h, ppc_problem* pr, const ppc_params* p, const double*
         check_params(p);
         if (!U_out) fail(PPC_ERR_ARG, "null U_out");
         PPC_HIP(hipSetDevice(h->device));
-        const size_t cnt = (size_t)p->N * pr->mesh.n_nodes;
+        size_t nodes = pr->mesh.n_nodes;
+        if (pr->batch) {
+            nodes = 0;
+            for (auto* q : pr->parts) nodes += q->mesh.n_nodes;
+        }
+        const size_t cnt = (size_t)p->N * nodes;
         double* du = dalloc<double>(cnt);
         double* di = nullptr;
         int rc = PPC_OK;
@@ -451,7 +693,8 @@ int ppc_solve(ppc_handle* h, ppc_problem* pr, const ppc_params* p, const double*
                 di = dalloc<double>(cnt);
                 PPC_HIP(hipMemcpyAsync(di, U_init, cnt * sizeof(double), hipMemcpyHostToDevice, h->stream));
             }
-            rc = solve_device(h, pr, p, di, du, resid_out, iters_out, stats, h->stream);
+            rc = pr->batch ? solve_batch_device(h, pr, p, di, du, resid_out, iters_out, stats, h->stream)
+                           : solve_device(h, pr, p, di, du, resid_out, iters_out, stats, h->stream);
             PPC_HIP(hipMemcpyAsync(U_out, du, cnt * sizeof(double), hipMemcpyDeviceToHost, h->stream));
             PPC_HIP(hipStreamSynchronize(h->stream));
         } catch (...) {
@@ -471,6 +714,7 @@ int ppc_fine_sweep_device(ppc_handle* h, ppc_problem* pr, const ppc_params* p, c
         check_handle_problem(h, pr);
         check_params(p);
         if (!U_in_dev || !F_out_dev) fail(PPC_ERR_ARG, "null U_in or F_out");
+        if (pr->batch) fail(PPC_ERR_ARG, "single-design entry point called with a batch problem");
         PPC_HIP(hipSetDevice(h->device));
         hipStream_t s = pick_stream(h, stream);
         ensure_workspace(pr, p);
@@ -490,6 +734,7 @@ int ppc_coarse_correction_device(ppc_handle* h, ppc_problem* pr, const ppc_param
         check_handle_problem(h, pr);
         check_params(p);
         if (!U_dev || !J_dev || !dU_dev) fail(PPC_ERR_ARG, "null U, J or dU");
+        if (pr->batch) fail(PPC_ERR_ARG, "single-design entry point called with a batch problem");
         PPC_HIP(hipSetDevice(h->device));
         hipStream_t s = pick_stream(h, stream);
         ensure_workspace(pr, p);

@@ -207,19 +207,23 @@ __global__ void k_dft(int n, int N, const double* __restrict__ R, const double2*
     Rh[(long)p * n + i] = make_double2(re, im);
 }
 
-// One workgroup per harmonic: (Kbar + sigma_p M) x = b by Jacobi-preconditioned COCG.
-__global__ __launch_bounds__(1024) void k_cocg(int n, int H, const int* __restrict__ rowptr,
-                                               const int* __restrict__ colidx,
-                                               const double* __restrict__ kbar,
-                                               const double* __restrict__ mval,
-                                               const int* __restrict__ diag,
-                                               const double2* __restrict__ sig,
-                                               const double2* __restrict__ B, double2* __restrict__ X,
-                                               double2* __restrict__ work, long n_pad, double tol,
-                                               int max_it, int* __restrict__ count) {
-    __shared__ double lds[2 * 16 * 3];
+// One workgroup per harmonic p: (Kbar + sigma_p M) x = b by Jacobi-preconditioned COCG.
+__device__ __forceinline__ void cocg_body(const CocgArgs& a, const int p, double* lds) {
+    const int n = a.n;
+    const int* __restrict__ rowptr = a.rowptr;
+    const int* __restrict__ colidx = a.colidx;
+    const double* __restrict__ kbar = a.kbar;
+    const double* __restrict__ mval = a.mval;
+    const int* __restrict__ diag = a.diag;
+    const double2* __restrict__ sig = a.sig;
+    const double2* __restrict__ B = a.B;
+    double2* __restrict__ X = a.X;
+    double2* __restrict__ work = a.work;
+    const long n_pad = a.n_pad;
+    const double tol = a.tol;
+    const int max_it = a.max_it;
+    int* __restrict__ count = a.count;
     int ph = 0;
-    const int p = blockIdx.x;
     const double2 sg = sig[p];
     const double2* b = B + (long)p * n;
     double2* x = X + (long)p * n;
@@ -329,6 +333,33 @@ __global__ __launch_bounds__(1024) void k_cocg(int n, int H, const int* __restri
     }
 }
 
+__global__ __launch_bounds__(1024) void k_cocg(CocgArgs a) {
+    __shared__ double lds[2 * 16 * 3];
+    cocg_body(a, blockIdx.x, lds);
+}
+
+// Batched designs: block b solves harmonic work[b].y of design work[b].x.
+__global__ __launch_bounds__(1024) void k_cocg_batch(const CocgArgs* __restrict__ args,
+                                                     const int2* __restrict__ work) {
+    __shared__ double lds[2 * 16 * 3];
+    const int2 wk = work[blockIdx.x];
+    cocg_body(args[wk.x], wk.y, lds);
+}
+
+// sigma_p, p = 0..N/2: exact implicit-Euler symbol (1 - e^{-i w_p dT})/dT or i w_p
+__global__ void k_shifts(int N, double T, int mode, double2* __restrict__ sig) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q > N / 2) return;
+    const double dT = T / N;
+    if (mode == 0) {
+        double sn, cs;
+        sincospi(2.0 * q / N, &sn, &cs);
+        sig[q] = make_double2((1.0 - cs) / dT, sn / dT);
+    } else {
+        sig[q] = make_double2(0.0, 2.0 * M_PI * q / T);
+    }
+}
+
 // dU[s][i] = (1/N) [ Re X_0 + (-1)^s Re X_{N/2} + 2 sum_{p=1}^{N/2-1} Re(X_p e^{+2 pi i p s/N}) ]
 // written to out (accumulate: out += dU)
 __global__ void k_idft(int n, int N, const double2* __restrict__ X, const double2* __restrict__ tw,
@@ -429,8 +460,10 @@ void launch_jumps(ppc_problem* pr, int N, const double* U, const double* F, doub
     PPC_HIP(hipGetLastError());
 }
 
-void launch_coarse(ppc_problem* pr, const ppc_params* p, const double* U, const double* J,
-                   double* dU, bool accumulate, bool excitation_rhs, hipStream_t s) {
+// Linearisation, coarse right-hand side, DFT along time and the shifts: everything of the
+// correction before the harmonic solves.
+void launch_coarse_pre(ppc_problem* pr, const ppc_params* p, const double* U, const double* J,
+                       bool excitation_rhs, hipStream_t s) {
     const DeviceMesh& d = pr->mesh;
     Workspace& w = pr->ws;
     const int n = d.n_free, ne = d.n_tri, N = p->N, H = N / 2 + 1;
@@ -451,23 +484,57 @@ void launch_coarse(ppc_problem* pr, const ppc_params* p, const double* U, const 
                            1.0 / dT, J, w.R);
     hipLaunchKernelGGL(k_twiddle, dim3((N + 255) / 256), dim3(256), 0, s, N, w.twiddle);
     hipLaunchKernelGGL(k_dft, dim3((n + 255) / 256, H), dim3(256), 0, s, n, N, w.R, w.twiddle, w.rhat);
-    // shifts sigma_p on the host: p = 0..N/2
-    std::vector<double2> sig(H);
-    for (int q = 0; q < H; ++q) {
-        if (p->shift_mode == 0) {
-            const double th = 2.0 * M_PI * q / N;
-            sig[q] = make_double2((1.0 - std::cos(th)) / dT, std::sin(th) / dT);
-        } else {
-            sig[q] = make_double2(0.0, 2.0 * M_PI * q / p->T);
-        }
-    }
-    PPC_HIP(hipMemcpyAsync(w.sig, sig.data(), H * sizeof(double2), hipMemcpyHostToDevice, s));
-    double2* X = w.rhat + (long)H * n;   // solution block follows the right-hand sides
-    hipLaunchKernelGGL(k_cocg, dim3(H), dim3(kCocgBlock), 0, s, n, H, d.rowptr, d.colidx, w.kbar, d.mval,
-                       d.diag, w.sig, w.rhat, X, w.cwork, (long)w.n_pad, p->tol_cocg, p->max_cocg,
-                       w.ccount);
+    hipLaunchKernelGGL(k_shifts, dim3((H + 63) / 64), dim3(64), 0, s, N, p->T, p->shift_mode, w.sig);
+    PPC_HIP(hipGetLastError());
+}
+
+CocgArgs make_cocg_args(ppc_problem* pr, const ppc_params* p) {
+    const DeviceMesh& d = pr->mesh;
+    Workspace& w = pr->ws;
+    const int H = p->N / 2 + 1;
+    CocgArgs a{};
+    a.n = d.n_free;
+    a.H = H;
+    a.rowptr = d.rowptr;
+    a.colidx = d.colidx;
+    a.kbar = w.kbar;
+    a.mval = d.mval;
+    a.diag = d.diag;
+    a.sig = w.sig;
+    a.B = w.rhat;
+    a.X = w.rhat + (long)H * d.n_free;   // solution block follows the right-hand sides
+    a.work = w.cwork;
+    a.n_pad = (long)w.n_pad;
+    a.tol = p->tol_cocg;
+    a.max_it = p->max_cocg;
+    a.count = w.ccount;
+    return a;
+}
+
+// Inverse DFT of the harmonic solutions into dU (accumulate: U += dU).
+void launch_coarse_post(ppc_problem* pr, const ppc_params* p, double* dU, bool accumulate,
+                        hipStream_t s) {
+    const DeviceMesh& d = pr->mesh;
+    Workspace& w = pr->ws;
+    const int n = d.n_free, N = p->N, H = N / 2 + 1;
+    const double2* X = w.rhat + (long)H * n;
     hipLaunchKernelGGL(k_idft, dim3((n + 255) / 256, N), dim3(256), 0, s, n, N, X, w.twiddle, dU,
                        accumulate ? 1 : 0);
+    PPC_HIP(hipGetLastError());
+}
+
+void launch_coarse(ppc_problem* pr, const ppc_params* p, const double* U, const double* J,
+                   double* dU, bool accumulate, bool excitation_rhs, hipStream_t s) {
+    launch_coarse_pre(pr, p, U, J, excitation_rhs, s);
+    const CocgArgs a = make_cocg_args(pr, p);
+    hipLaunchKernelGGL(k_cocg, dim3(a.H), dim3(kCocgBlock), 0, s, a);
+    PPC_HIP(hipGetLastError());
+    launch_coarse_post(pr, p, dU, accumulate, s);
+}
+
+void launch_cocg_batch(const CocgArgs* d_args, const int2* d_work, int nblocks, hipStream_t s) {
+    if (nblocks <= 0) return;
+    hipLaunchKernelGGL(k_cocg_batch, dim3(nblocks), dim3(kCocgBlock), 0, s, d_args, d_work);
     PPC_HIP(hipGetLastError());
 }
 

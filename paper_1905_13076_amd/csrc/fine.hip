@@ -22,48 +22,7 @@
 
 namespace ppc {
 
-struct FineArgs {
-    int n, ne, nnz, N, m;
-    double T, dt, fnorm;
-    double tol_newton, tol_lin;
-    int max_newton, max_lin;
-    const int* rowptr;
-    const int* colidx;
-    const int* diag;
-    const int* slot_ptr;
-    const int* slot_src;
-    const int* node_ptr;
-    const int* node_src;
-    const int* efree;
-    const int* mat;
-    const double* area;
-    const double* k0;
-    const double* sigma;
-    const double* mval;
-    const double* fload;
-    const double* lawtab;   // [n_mat][5]: law, nu, k1, k2, k3
-    const double* wavtab;   // [n_h][3]: order, amp, phase
-    int n_h;
-    double f0;
-    const double* U;        // [N][n]
-    double* F;              // [N][n]
-    double* vec;            // [N][kFineVec][n_pad]
-    void* pcg;              // [N][kPcgVec][n_pad] of S
-    void* jac;              // [N][nnz_pad] of S
-    double* elem;           // [N][8][ne_pad]
-    int* count;             // [N][8]
-    long n_pad, vals_pad, ne_pad;
-    // ELL pattern of the fine-sweep SpMV
-    int W, ntail, nvals;
-    int predictor;
-    long ell_pad;
-    const int* ecol;
-    const int* vslot;
-    const int* dpos;
-    const int* tail_row;
-    const int* tail_ptr;
-    const int* tail_col;
-};
+
 
 // Imposed current i(t) = sum_h amp_h sin(2 pi order_h f0 t + phase_h).
 __device__ inline double current(double t, double f0, int n_h, const double* __restrict__ w) {
@@ -108,6 +67,10 @@ __device__ inline void block_sum(T (&v)[K], T* lds, int& phase) {
 }
 
 enum { E_F0 = 0, E_W0 = 3, E_NU = 6, E_SF = 7 };
+
+// Newton accepts a residual that stops halving (or a stalled line search) once it is
+// below kFloorCap * scale: it then sits at the rounding floor of its evaluation.
+constexpr double kFloorCap = 1e-9;
 enum { V_U = 0, V_UP = 1, V_R = 2, V_RT = 3, V_UPP = 4 };
 enum { P_R = 0, P_P = 1, P_Q = 2, P_X = 3, P_D = 4 };
 enum { C_STATUS = 0, C_NEWTON = 1, C_LIN = 2, C_NEWTON_MAX = 3, C_LIN_MAX = 4, C_CAPPED = 5,
@@ -415,13 +378,10 @@ __device__ inline double mass_norm2(const FineArgs& a, const double* __restrict_
 
 // R > 0: PCG rows in registers, p / diagonal / tail sums in dynamic LDS;
 // R == 0: PCG vectors in memory, with p (LP >= 1) and the diagonal (LP == 2) in LDS.
-template <typename S, int R, int BLOCK, int LP>
-__global__ __launch_bounds__(BLOCK) void k_fine_sweep(FineArgs a) {
-    extern __shared__ unsigned char dyn_lds[];
-    __shared__ double lds_d[2 * 16 * 4];
-    __shared__ S lds_s[2 * 16 * 4];
-    int ph_d = 0, ph_s = 0;
-    const int c = blockIdx.x;                 // chain n = c + 1
+template <typename S, int R, int LP>
+__device__ __forceinline__ void fine_chain(const FineArgs& a, const int c, unsigned char* dyn_lds,
+                                           double* lds_d, S* lds_s) {
+    int ph_d = 0, ph_s = 0;                   // chain n = c + 1
     const int n = a.n;
     const long NP = a.n_pad;
     double* vec = a.vec + (long)c * kFineVec * NP;
@@ -525,7 +485,7 @@ __global__ __launch_bounds__(BLOCK) void k_fine_sweep(FineArgs a) {
                 if (lam < 0x1p-20) { stalled = true; break; }
             }
             if (stalled) {
-                if (rn <= 1e3 * target) { ++it; break; }
+                if (rn <= kFloorCap * scale) { ++it; break; }
                 status = isfinite(rt) ? PPC_ERR_NEWTON : PPC_ERR_NONFINITE;
                 fail_step = j;
                 break;
@@ -535,8 +495,12 @@ __global__ __launch_bounds__(BLOCK) void k_fine_sweep(FineArgs a) {
                 double* tmp = R_;
                 R_ = Rt;
                 Rt = tmp;
+                // a step that fails to halve a residual below the floor cap: the residual
+                // sits at the rounding floor of its own evaluation
+                const bool floor = rt > 0.5 * rn && rt <= kFloorCap * scale;
                 rn = rt;
                 __syncthreads();
+                if (floor) { ++it; break; }
             }
         }
         newton_total += it;
@@ -558,14 +522,29 @@ __global__ __launch_bounds__(BLOCK) void k_fine_sweep(FineArgs a) {
     }
 }
 
+template <typename S, int R, int BLOCK, int LP>
+__global__ __launch_bounds__(BLOCK) void k_fine_sweep(FineArgs a) {
+    extern __shared__ unsigned char dyn_lds[];
+    __shared__ double lds_d[2 * 16 * 4];
+    __shared__ S lds_s[2 * 16 * 4];
+    fine_chain<S, R, LP>(a, blockIdx.x, dyn_lds, lds_d, lds_s);
+}
+
+// Batched designs: block b runs chain work[b].y of design work[b].x, whose arguments are
+// args[work[b].x] (a work list over every design of one kernel shape, longest first).
+template <typename S, int R, int BLOCK, int LP>
+__global__ __launch_bounds__(BLOCK) void k_fine_sweep_batch(const FineArgs* __restrict__ args,
+                                                            const int2* __restrict__ work) {
+    extern __shared__ unsigned char dyn_lds[];
+    __shared__ double lds_d[2 * 16 * 4];
+    __shared__ S lds_s[2 * 16 * 4];
+    const int2 wk = work[blockIdx.x];
+    fine_chain<S, R, LP>(args[wk.x], wk.y, dyn_lds, lds_d, lds_s);
+}
+
 namespace {
 
 constexpr size_t kLdsBudget = 160 * 1024 - 4096;
-
-struct FineShape {
-    int R, block, LP;
-    size_t lds;
-};
 
 // Register rows (R in {1, 2, 4, 8} rows per thread, 1024 threads) when p, r, the FP32
 // diagonal and the tail sums fit in LDS; otherwise the memory path with as much of p /
@@ -609,8 +588,7 @@ void launch_typed(const FineArgs& a, int N, const FineShape& sh, hipStream_t s) 
 
 }  // namespace
 
-void launch_fine_sweep(ppc_problem* pr, const ppc_params* p, const double* U, double* F,
-                       hipStream_t s) {
+FineArgs make_fine_args(ppc_problem* pr, const ppc_params* p, const double* U, double* F) {
     const DeviceMesh& d = pr->mesh;
     Workspace& w = pr->ws;
     FineArgs a{};
@@ -665,12 +643,124 @@ void launch_fine_sweep(ppc_problem* pr, const ppc_params* p, const double* U, do
     a.tail_ptr = d.tail_ptr;
     a.tail_col = d.tail_col;
     a.predictor = p->reserved[0] == 0 ? 1 : 0;
+    return a;
+}
+
+FineShape fine_shape(const ppc_problem* pr, const ppc_params* p) {
     const size_t elem = p->precision == 0 ? sizeof(double) : sizeof(float);
-    const FineShape sh = pick_shape(d.n_free, w.n_pad, d.n_tail, elem, p->block);
+    return pick_shape(pr->mesh.n_free, pr->ws.n_pad, pr->mesh.n_tail, elem, p->block);
+}
+
+void launch_fine_sweep(ppc_problem* pr, const ppc_params* p, const double* U, double* F,
+                       hipStream_t s) {
+    const FineArgs a = make_fine_args(pr, p, U, F);
+    const FineShape sh = fine_shape(pr, p);
     if (p->precision == 0)
         launch_typed<double>(a, p->N, sh, s);
     else
         launch_typed<float>(a, p->N, sh, s);
+    PPC_HIP(hipGetLastError());
+}
+
+namespace {
+
+template <typename S, int R, int LP>
+void launch_batch_shape(const FineArgs* args, const int2* work, int nblocks, size_t lds, hipStream_t s) {
+    static bool attr_set = false;
+    if (!attr_set) {
+        PPC_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fine_sweep_batch<S, R, kFineBlock, LP>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBudget));
+        attr_set = true;
+    }
+    hipLaunchKernelGGL((k_fine_sweep_batch<S, R, kFineBlock, LP>), dim3(nblocks), dim3(kFineBlock), lds, s,
+                       args, work);
+}
+
+template <typename S>
+void launch_batch_typed(const FineArgs* args, const int2* work, int nblocks, const FineShape& sh,
+                        hipStream_t s) {
+    if (sh.R == 1) launch_batch_shape<S, 1, 0>(args, work, nblocks, sh.lds, s);
+    else if (sh.R == 2) launch_batch_shape<S, 2, 0>(args, work, nblocks, sh.lds, s);
+    else if (sh.R == 4) launch_batch_shape<S, 4, 0>(args, work, nblocks, sh.lds, s);
+    else if (sh.R == 8) launch_batch_shape<S, 8, 0>(args, work, nblocks, sh.lds, s);
+    else if (sh.LP == 2) launch_batch_shape<S, 0, 2>(args, work, nblocks, sh.lds, s);
+    else if (sh.LP == 1) launch_batch_shape<S, 0, 1>(args, work, nblocks, sh.lds, s);
+    else launch_batch_shape<S, 0, 0>(args, work, nblocks, 0, s);
+}
+
+int shape_key(const FineShape& sh) { return sh.R * 16 + sh.LP; }
+
+}  // namespace
+
+void FineBatch::release() {
+    if (d_args) (void)hipFree(d_args);
+    if (d_work) (void)hipFree(d_work);
+    d_args = nullptr;
+    d_work = nullptr;
+    work_cap = 0;
+}
+
+// Upload one FineArgs per design (U / F are each design's own state arrays).
+void fine_batch_prepare(FineBatch& b, const std::vector<ppc_problem*>& parts, const ppc_params* p,
+                        hipStream_t s) {
+    const int D = (int)parts.size();
+    std::vector<FineArgs> host(D);
+    b.shapes.resize(D);
+    for (int d = 0; d < D; ++d) {
+        host[d] = make_fine_args(parts[d], p, parts[d]->ws.U, parts[d]->ws.F);
+        b.shapes[d] = fine_shape(parts[d], p);
+        b.sizes.push_back(parts[d]->mesh.n_free);
+    }
+    if (b.d_args) (void)hipFree(b.d_args);
+    PPC_HIP(hipMalloc(&b.d_args, sizeof(FineArgs) * D));
+    PPC_HIP(hipMemcpyAsync(b.d_args, host.data(), sizeof(FineArgs) * D, hipMemcpyHostToDevice, s));
+    PPC_HIP(hipStreamSynchronize(s));
+    b.N = p->N;
+    b.precision = p->precision;
+}
+
+// One launch per kernel shape over the chains of the active designs, longest chains first.
+void fine_batch_launch(FineBatch& b, const std::vector<char>& active, hipStream_t s) {
+    const int D = (int)b.shapes.size();
+    std::vector<int> order;
+    for (int d = 0; d < D; ++d)
+        if (active[d]) order.push_back(d);
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return b.sizes[x] > b.sizes[y]; });
+    std::vector<int> keys;
+    for (int d : order) {
+        const int k = shape_key(b.shapes[d]);
+        if (std::find(keys.begin(), keys.end(), k) == keys.end()) keys.push_back(k);
+    }
+    std::vector<int2> work;
+    std::vector<std::pair<size_t, size_t>> spans;
+    std::vector<FineShape> shapes;
+    for (int k : keys) {
+        const size_t start = work.size();
+        FineShape sh{};
+        for (int d : order) {
+            if (shape_key(b.shapes[d]) != k) continue;
+            if (b.shapes[d].lds >= sh.lds) sh = b.shapes[d];
+            for (int c = 0; c < b.N; ++c) work.push_back(make_int2(d, c));
+        }
+        spans.emplace_back(start, work.size() - start);
+        shapes.push_back(sh);
+    }
+    if (work.empty()) return;
+    if (work.size() > b.work_cap) {
+        if (b.d_work) (void)hipFree(b.d_work);
+        PPC_HIP(hipMalloc(&b.d_work, sizeof(int2) * work.size()));
+        b.work_cap = work.size();
+    }
+    b.host_work = work;   // kept alive until the copy is complete
+    PPC_HIP(hipMemcpyAsync(b.d_work, b.host_work.data(), sizeof(int2) * work.size(), hipMemcpyHostToDevice, s));
+    for (size_t g = 0; g < spans.size(); ++g) {
+        const int2* w = b.d_work + spans[g].first;
+        const int nb = (int)spans[g].second;
+        if (b.precision == 0)
+            launch_batch_typed<double>(b.d_args, w, nb, shapes[g], s);
+        else
+            launch_batch_typed<float>(b.d_args, w, nb, shapes[g], s);
+    }
     PPC_HIP(hipGetLastError());
 }
 

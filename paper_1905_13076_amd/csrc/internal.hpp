@@ -146,9 +146,94 @@ struct ppc_problem {
     std::vector<int> nl_elem;        // host list of Brauer elements
     double* lawtab = nullptr;        // device [n_mat][5]: law, nu, k1, k2, k3
     double* wavtab = nullptr;        // device [n_h][3]: order, amp, phase
+    // batched problem: one sub-problem per design (the fields above are unused then)
+    std::vector<ppc_problem*> parts;
+    bool batch = false;
 };
 
 namespace ppc {
+
+// Arguments of one design's fine sweep (device pointers and sizes).
+struct FineArgs {
+    int n, ne, nnz, N, m;
+    double T, dt, fnorm;
+    double tol_newton, tol_lin;
+    int max_newton, max_lin;
+    const int* rowptr;
+    const int* colidx;
+    const int* diag;
+    const int* slot_ptr;
+    const int* slot_src;
+    const int* node_ptr;
+    const int* node_src;
+    const int* efree;
+    const int* mat;
+    const double* area;
+    const double* k0;
+    const double* sigma;
+    const double* mval;
+    const double* fload;
+    const double* lawtab;   // [n_mat][5]: law, nu, k1, k2, k3
+    const double* wavtab;   // [n_h][3]: order, amp, phase
+    int n_h;
+    double f0;
+    const double* U;        // [N][n]
+    double* F;              // [N][n]
+    double* vec;            // [N][kFineVec][n_pad]
+    void* pcg;              // [N][kPcgVec][n_pad] of S
+    void* jac;              // [N][nnz_pad] of S
+    double* elem;           // [N][8][ne_pad]
+    int* count;             // [N][8]
+    long n_pad, vals_pad, ne_pad;
+    // ELL pattern of the fine-sweep SpMV
+    int W, ntail, nvals;
+    int predictor;
+    long ell_pad;
+    const int* ecol;
+    const int* vslot;
+    const int* dpos;
+    const int* tail_row;
+    const int* tail_ptr;
+    const int* tail_col;
+};
+
+// Kernel shape of a design's fine sweep: register rows R (0: memory path), workgroup,
+// LDS residency LP of the memory path, dynamic LDS bytes.
+struct FineShape {
+    int R, block, LP;
+    size_t lds;
+};
+
+// Batched fine sweep over several designs (one descriptor per design on the device).
+struct FineBatch {
+    FineArgs* d_args = nullptr;
+    int2* d_work = nullptr;
+    size_t work_cap = 0;
+    int N = 0, precision = 0;
+    std::vector<FineShape> shapes;
+    std::vector<int> sizes;
+    std::vector<int2> host_work;
+    void release();
+    ~FineBatch() { release(); }
+};
+
+// Arguments of one design's harmonic COCG solves.
+struct CocgArgs {
+    int n, H;
+    const int* rowptr;
+    const int* colidx;
+    const double* kbar;
+    const double* mval;
+    const int* diag;
+    const double2* sig;
+    const double2* B;
+    double2* X;
+    double2* work;
+    long n_pad;
+    double tol;
+    int max_it;
+    int* count;
+};
 
 constexpr int kFineVec = 5;   // u, u_prev, R, R_trial, u_{j-2}
 constexpr int kPcgVec = 5;    // r, p, q, x, dinv
@@ -166,12 +251,21 @@ void ensure_workspace(ppc_problem* pr, const ppc_params* p);
 // fine sweep (fine.hip): F[n mod N] = F_n(U[n-1]) for all chains, one launch
 void launch_fine_sweep(ppc_problem* pr, const ppc_params* p, const double* U, double* F,
                        hipStream_t s);
+void fine_batch_prepare(FineBatch& b, const std::vector<ppc_problem*>& parts, const ppc_params* p,
+                        hipStream_t s);
+void fine_batch_launch(FineBatch& b, const std::vector<char>& active, hipStream_t s);
 
 // coarse correction pieces (coarse.hip)
 void launch_jumps(ppc_problem* pr, int N, const double* U, const double* F, double* J,
                   double* out3, hipStream_t s);
 void launch_coarse(ppc_problem* pr, const ppc_params* p, const double* U, const double* J,
                    double* dU, bool accumulate, bool excitation_rhs, hipStream_t s);
+void launch_coarse_pre(ppc_problem* pr, const ppc_params* p, const double* U, const double* J,
+                       bool excitation_rhs, hipStream_t s);
+CocgArgs make_cocg_args(ppc_problem* pr, const ppc_params* p);
+void launch_cocg_batch(const CocgArgs* d_args, const int2* d_work, int nblocks, hipStream_t s);
+void launch_coarse_post(ppc_problem* pr, const ppc_params* p, double* dU, bool accumulate,
+                        hipStream_t s);
 void launch_to_nodal(const ppc_problem* pr, int N, const double* Ufree, double* Unodal,
                      hipStream_t s);
 void launch_to_free(const ppc_problem* pr, int N, const double* Unodal, double* Ufree,

@@ -220,6 +220,68 @@ class Problem:
         return dU, cocg
 
 
+class BatchProblem:
+    """Several designs copied to the device as one batched problem
+    (ppc_problem_create_batch); solve() runs PP-PC on all of them at once."""
+
+    def __init__(self, handle: Handle, probs):
+        self.handle = handle
+        ms = [_Marshalled(q) for q in probs]
+        self._keep = ms
+        D = len(ms)
+        meshes = (nat.Mesh * D)(*[m.mesh for m in ms])
+        mats = (nat.Material * D)(*[m.mat for m in ms])
+        excs = (nat.Excitation * D)(*[m.exc for m in ms])
+        p = c_void_p()
+        rc = lib().ppc_problem_create_batch(handle.h, D, meshes, mats, excs, byref(p))
+        if rc != 0:
+            raise _err(handle.h, rc)
+        self.p = p
+        nd = c_int32()
+        nn = np.zeros(D, dtype=np.int32)
+        nf = np.zeros(D, dtype=np.int32)
+        lib().ppc_batch_info(p, byref(nd), _pi(nn), _pi(nf))
+        self.n_designs = nd.value
+        self.n_nodes = nn
+        self.n_free = nf
+        self.offsets = np.concatenate([[0], np.cumsum(nn)])
+
+    def close(self):
+        if self.p:
+            lib().ppc_problem_destroy(self.p)
+            self.p = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, prm, U_init=None):
+        """Returns (list of per-design U [N, n_nodes_d] CUDA views, eps [D, k+1] numpy,
+        iterations per design, stats dict, status)."""
+        import torch
+        total = int(self.offsets[-1])
+        flat = torch.empty(prm.N * total, dtype=torch.float64, device=f"cuda:{self.handle.device}")
+        resid = np.zeros((self.n_designs, prm.max_iters + 1), dtype=np.float64)
+        iters = np.zeros(self.n_designs, dtype=np.int32)
+        st = nat.Stats()
+        if U_init is not None:
+            ui = torch.cat([u.reshape(-1) for u in U_init]).contiguous()
+            uip = c_void_p(ui.data_ptr())
+        else:
+            uip = c_void_p()
+        rc = lib().ppc_solve_device(self.handle.h, self.p, byref(prm), uip, c_void_p(flat.data_ptr()),
+                                    _pd(resid), _pi(iters), byref(st), _stream())
+        if rc < 0:
+            raise _err(self.handle.h, rc)
+        Us = []
+        for d in range(self.n_designs):
+            a, b = prm.N * int(self.offsets[d]), prm.N * int(self.offsets[d + 1])
+            Us.append(flat[a:b].view(prm.N, int(self.n_nodes[d])))
+        return Us, resid, iters, st.as_dict(), rc
+
+
 def problem_params(prob, **kw):
     """Parameters carrying a workload's period and time grid (T, N, m)."""
     return params(T=float(prob.T), N=int(prob.N), m=int(prob.m), **kw)
