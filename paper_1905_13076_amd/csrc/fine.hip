@@ -412,12 +412,10 @@ __device__ __forceinline__ void fine_chain(const FineArgs& a, const int c, unsig
 
     for (int j = 1; j <= a.m && status == 0; ++j) {
         const double t = t0 + j * a.dt;
-        // u_{j-1} -> u_prev; Newton starts from the linear extrapolation 2 u_{j-1} - u_{j-2}
-        // (j >= 2), which changes only the iteration count, not the step's solution
+        // u_{j-1} -> u_prev (u_{j-2} kept for the predictor)
         for (int i = threadIdx.x; i < n; i += blockDim.x) {
-            const double uj = u[i];
-            if (j >= 2 && a.predictor) u[i] = 2.0 * uj - up[i];
-            up[i] = uj;
+            upp[i] = up[i];
+            up[i] = u[i];
         }
         __syncthreads();
         const double cur = current(t, a.f0, a.n_h, a.wavtab);
@@ -433,6 +431,30 @@ __device__ __forceinline__ void fine_chain(const FineArgs& a, const int c, unsig
         block_sum<double, 1>(v2, lds_d, ph_d);
         double rn = sqrt(v2[0]);
         if (!isfinite(rn)) { status = PPC_ERR_NONFINITE; fail_step = j; break; }
+        // Newton starts from the linear extrapolation 2 u_{j-1} - u_{j-2} when that has the
+        // smaller residual (it changes only the iteration count, not the step's solution)
+        if (j >= 2 && a.predictor && rn > target) {
+            for (int i = threadIdx.x; i < n; i += blockDim.x) u[i] = 2.0 * up[i] - upp[i];
+            __syncthreads();
+            element_pass<double>(a, u, nullptr, 0.0, up, el, inv_dt);
+            ++resid_evals;
+            __syncthreads();
+            double v4[1] = {node_pass(a, el, cur, Rt)};
+            block_sum<double, 1>(v4, lds_d, ph_d);
+            const double rp = sqrt(v4[0]);
+            if (rp < rn) {
+                double* tmp = R_;
+                R_ = Rt;
+                Rt = tmp;
+                rn = rp;
+            } else {
+                for (int i = threadIdx.x; i < n; i += blockDim.x) u[i] = up[i];
+                __syncthreads();
+                element_pass<double>(a, u, nullptr, 0.0, up, el, inv_dt);
+                ++resid_evals;
+                __syncthreads();
+            }
+        }
 
         int it = 0;
         for (;; ++it) {
