@@ -219,6 +219,26 @@ int ppc_solve_device(ppc_handle* h, ppc_problem* pr, const ppc_params* p,
                      const double* U_init_dev, double* U_out_dev, double* resid_out,
                      int32_t* iters_out, ppc_stats* stats, void* stream);
 
+/* Adjoint gradients of the period-averaged eddy-current loss at a periodic steady state
+ * (the state of eq. (1) that ppc_solve returns).  With the periodic implicit-Euler fine
+ * trajectory u_j, j = 1..L = N m, the loss is
+ *     P = 1/(T dt) sum_j (u_j - u_{j-1})^T M (u_j - u_{j-1})      (W/m, sigma (dA/dt)^2)
+ * and its gradient follows from the periodic adjoint
+ *     J_j lambda_j = (M/dt) lambda_{j+1} + dP/du_j,   lambda_{L+1} = lambda_1,
+ * solved by a backward fine sweep (one launch; each chain replays its forward states
+ * from the checkpoint U_{n-1}) inside a PP-PC iteration whose coarse correction is the
+ * harmonic solve of Section 3 applied to the time-reversed jumps.  The adjoint solves
+ * are FP64 (relative tolerance 1e-12) whatever params->precision says; the adjoint
+ * iteration stops at ||jumps|| / ||Lambda|| <= tol_ppc.
+ *   U_periodic  host, [N * n_nodes]: the converged coarse samples (checkpoints)
+ *   loss        host scalar or null
+ *   dsigma      host [n_tri] or null: dP/dsigma_e (per element)
+ *   dbrauer     host [n_mat * 3] or null: dP/d(k1, k2, k3) per material (0 for linear)
+ *   iters_out   host or null: adjoint coarse corrections applied
+ * Single designs only (PPC_ERR_ARG for a batched problem). */
+int ppc_adjoint(ppc_handle* h, ppc_problem* pr, const ppc_params* p, const double* U_periodic,
+                double* loss, double* dsigma, double* dbrauer, int32_t* iters_out, ppc_stats* stats);
+
 /* One fine sweep (Section 2, eqs. (2)-(3)): F_out[n mod N] = F_n(U_in[n-1]) for
  * n = 1..N, all chains in one launch.  U_in / F_out are DEVICE pointers
  * [N * n_nodes]; newton_out / lin_out are host [N] or null (per-chain Newton and PCG

@@ -86,6 +86,7 @@ SIGNATURES = {
     "ppc_solve": (c_int, [c_void_p, c_void_p, POINTER(Params), PD, PD, PD, PI, POINTER(Stats)]),
     "ppc_solve_device": (c_int, [c_void_p, c_void_p, POINTER(Params), c_void_p, c_void_p, PD, PI,
                                  POINTER(Stats), c_void_p]),
+    "ppc_adjoint": (c_int, [c_void_p, c_void_p, POINTER(Params), PD, PD, PD, PD, PI, POINTER(Stats)]),
     "ppc_fine_sweep_device": (c_int, [c_void_p, c_void_p, POINTER(Params), c_void_p, c_void_p, PI, PI,
                                       c_void_p]),
     "ppc_coarse_correction_device": (c_int, [c_void_p, c_void_p, POINTER(Params), c_void_p, c_void_p,

@@ -445,6 +445,105 @@ int solve_batch_device(ppc_handle* h, ppc_problem* bp, const ppc_params* p, cons
     return status;
 }
 
+
+// ---------------------------------------------------------------------------------------
+// adjoint of the periodic steady state
+// ---------------------------------------------------------------------------------------
+int adjoint_device(ppc_handle* h, ppc_problem* pr, const ppc_params* p, const double* U_host, double* loss,
+                   double* dsigma, double* dbrauer, int32_t* iters_out, ppc_stats* st, hipStream_t s) {
+    PPC_HIP(hipSetDevice(h->device));
+    ensure_workspace(pr, p);
+    Workspace& w = pr->ws;
+    const DeviceMesh& d = pr->mesh;
+    const int N = p->N, m = p->m, n = d.n_free, H = N / 2 + 1;
+    const int n_mat = pr->laws.n_mat;
+    DevBuf traj, lam_all, Lam, FB, JR, dLR, part, out1, dsig, dke, dkm, Unod;
+    PPC_HIP(hipMalloc(&traj.p, sizeof(double) * (size_t)N * (m + 1) * n));
+    PPC_HIP(hipMalloc(&lam_all.p, sizeof(double) * (size_t)N * m * n));
+    PPC_HIP(hipMalloc(&Lam.p, sizeof(double) * (size_t)N * n));
+    PPC_HIP(hipMalloc(&FB.p, sizeof(double) * (size_t)N * n));
+    PPC_HIP(hipMalloc(&JR.p, sizeof(double) * (size_t)N * n));
+    PPC_HIP(hipMalloc(&dLR.p, sizeof(double) * (size_t)N * n));
+    PPC_HIP(hipMalloc(&part.p, sizeof(double) * (size_t)N * m));
+    PPC_HIP(hipMalloc(&out1.p, sizeof(double) * 4));
+    PPC_HIP(hipMalloc(&dsig.p, sizeof(double) * (size_t)d.n_tri));
+    PPC_HIP(hipMalloc(&dke.p, sizeof(double) * 3 * (size_t)d.n_tri));
+    PPC_HIP(hipMalloc(&dkm.p, sizeof(double) * 3 * (size_t)n_mat));
+    PPC_HIP(hipMalloc(&Unod.p, sizeof(double) * (size_t)N * d.n_nodes));
+    double* dtraj = static_cast<double*>(traj.p);
+    double* dlam = static_cast<double*>(lam_all.p);
+    double* dL = static_cast<double*>(Lam.p);
+    double* dFB = static_cast<double*>(FB.p);
+    ppc_stats S{};
+    S.n_free = d.n_free;
+    S.nnz = d.nnz;
+    S.n_tri = d.n_tri;
+    hipEvent_t* ev = h->ev;
+    PPC_HIP(hipEventRecord(ev[4], s));
+    PPC_HIP(hipMemcpyAsync(Unod.p, U_host, sizeof(double) * (size_t)N * d.n_nodes, hipMemcpyHostToDevice, s));
+    launch_to_free(pr, N, static_cast<double*>(Unod.p), w.U, s);
+    // forward replay from the per-subinterval checkpoints U_{n-1}, storing every step
+    launch_fine_sweep_traj(pr, p, w.U, w.F, dtraj, s);
+    check_sweep(read_chain_counts(pr, N, s, nullptr, nullptr));
+    S.fine_launches++;
+    launch_loss(pr, p, dtraj, static_cast<double*>(part.p), static_cast<double*>(out1.p), s);
+    // backward PP-PC on the adjoint: Lambda_c = lambda_{cm+1}
+    fill(dL, (long)N * n, 0.0, s);
+    AdjArgs b{};
+    b.traj = dtraj;
+    b.lam_in = dL;
+    b.lam_out = dFB;
+    b.lam_all = dlam;
+    b.tol_lin = 1e-12;
+    b.T = p->T;
+    int status = PPC_NOT_CONVERGED, k = 0;
+    for (k = 0; k <= p->max_iters; ++k) {
+        PPC_HIP(hipEventRecord(ev[0], s));
+        launch_adjoint_sweep(pr, p, b, s);
+        PPC_HIP(hipEventRecord(ev[1], s));
+        S.fine_launches++;
+        launch_jumps(pr, N, dL, dFB, w.J, w.scal, s);
+        PPC_HIP(hipMemcpyAsync(w.host_scal, w.scal, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+        const SweepCounts c = read_chain_counts(pr, N, s, nullptr, nullptr);
+        S.fine_ms += elapsed(ev[0], ev[1]);
+        S.lin_total += c.lin;
+        S.lin_max = std::max(S.lin_max, c.lin_max);
+        S.lin_capped += c.capped;
+        const double jj = w.host_scal[0], uu = w.host_scal[1];
+        if (!std::isfinite(jj)) fail(PPC_ERR_NONFINITE, "non-finite adjoint jump norm");
+        const double eps = uu > 0.0 ? std::sqrt(jj) / std::sqrt(uu) : (jj == 0.0 ? 0.0 : INFINITY);
+        S.eps = eps;
+        if (eps <= p->tol_ppc) {
+            status = PPC_OK;
+            break;
+        }
+        if (k == p->max_iters) break;
+        // coarse correction of the time-reversed jumps (the backward cyclic system read
+        // in reversed subinterval order is the forward one), K frozen at the samples U
+        PPC_HIP(hipEventRecord(ev[2], s));
+        launch_reverse_rows(N, n, w.J, static_cast<double*>(JR.p), s);
+        launch_coarse(pr, p, w.U, static_cast<double*>(JR.p), static_cast<double*>(dLR.p), false, false, s);
+        launch_add_reversed(N, n, static_cast<double*>(dLR.p), dL, s);
+        PPC_HIP(hipEventRecord(ev[3], s));
+        read_cocg(pr, H, s, nullptr, &S.cocg_total, &S.cocg_max);
+        S.coarse_ms += elapsed(ev[2], ev[3]);
+        S.coarse_solves++;
+    }
+    S.iterations = std::min(k, p->max_iters);
+    launch_gradients(pr, p, dtraj, dlam, static_cast<double*>(dsig.p), static_cast<double*>(dke.p),
+                     static_cast<double*>(dkm.p), n_mat, s);
+    if (loss) PPC_HIP(hipMemcpyAsync(loss, out1.p, sizeof(double), hipMemcpyDeviceToHost, s));
+    if (dsigma) PPC_HIP(hipMemcpyAsync(dsigma, dsig.p, sizeof(double) * d.n_tri, hipMemcpyDeviceToHost, s));
+    if (dbrauer) PPC_HIP(hipMemcpyAsync(dbrauer, dkm.p, sizeof(double) * 3 * n_mat, hipMemcpyDeviceToHost, s));
+    PPC_HIP(hipEventRecord(ev[5], s));
+    PPC_HIP(hipStreamSynchronize(s));
+    S.total_ms = elapsed(ev[4], ev[5]);
+    S.status = status;
+    if (iters_out) *iters_out = S.iterations;
+    if (st) *st = S;
+    return status;
+}
+
 }  // namespace
 }  // namespace ppc
 
@@ -705,6 +804,17 @@ int ppc_solve(ppc_handle* h, ppc_problem* pr, const ppc_params* p, const double*
         (void)hipFree(du);
         if (di) (void)hipFree(di);
         return rc;
+    });
+}
+
+int ppc_adjoint(ppc_handle* h, ppc_problem* pr, const ppc_params* p, const double* U_periodic,
+                double* loss, double* dsigma, double* dbrauer, int32_t* iters_out, ppc_stats* stats) {
+    return guarded(h, [&]() -> int {
+        check_handle_problem(h, pr);
+        check_params(p);
+        if (!U_periodic) fail(PPC_ERR_ARG, "null U_periodic");
+        if (pr->batch) fail(PPC_ERR_ARG, "the adjoint takes a single design");
+        return adjoint_device(h, pr, p, U_periodic, loss, dsigma, dbrauer, iters_out, stats, h->stream);
     });
 }
 

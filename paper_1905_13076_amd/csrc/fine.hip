@@ -402,7 +402,11 @@ __device__ __forceinline__ void fine_chain(const FineArgs& a, const int c, unsig
     S* dinv = LP == 2 ? d_l : pv + P_D * NP;
 
     const double* U0 = a.U + (long)c * n;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) u[i] = U0[i];
+    double* Tc = a.traj ? a.traj + (long)c * (a.m + 1) * n : nullptr;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        u[i] = U0[i];
+        if (Tc) Tc[i] = U0[i];
+    }
     __syncthreads();
 
     const double t0 = (double)c * (a.T / a.N);
@@ -527,6 +531,8 @@ __device__ __forceinline__ void fine_chain(const FineArgs& a, const int c, unsig
         }
         newton_total += it;
         newton_max = it > newton_max ? it : newton_max;
+        if (Tc)
+            for (int i = threadIdx.x; i < n; i += blockDim.x) Tc[(long)j * n + i] = u[i];
     }
 
     double* Fo = a.F + (long)((c + 1) % a.N) * n;
@@ -542,6 +548,127 @@ __device__ __forceinline__ void fine_chain(const FineArgs& a, const int c, unsig
         cnt[C_FAILSTEP] = fail_step;
         cnt[C_RESID] = resid_evals;
     }
+}
+
+// out_i = -(M y)_i (CSR, kRowGroup lanes per row); returns the partial ||M y||^2
+__device__ inline double mass_apply_neg(const FineArgs& a, const double* __restrict__ y,
+                                        double* __restrict__ out) {
+    constexpr int G = kRowGroup;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int sub = lane % G, grp = lane / G;
+    constexpr int RPW = 64 / G;
+    double part = 0.0;
+    for (int base = wave * RPW; base < a.n; base += nw * RPW) {
+        const int i = base + grp;
+        double acc = 0.0;
+        if (i < a.n) {
+            const int k1 = a.rowptr[i + 1];
+            for (int k = a.rowptr[i] + sub; k < k1; k += G) acc += a.mval[k] * y[a.colidx[k]];
+        }
+#pragma unroll
+        for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+        if (i < a.n && sub == 0) {
+            out[i] = -acc;
+            part += acc * acc;
+        }
+    }
+    return part;
+}
+
+// One chain of the adjoint backward sweep: from Lambda_{c+1} down to lambda_{cm+1},
+// solving J_j lambda_j = M (lambda_{j+1}/dt + 2/(T dt) (du_j - du_{j+1})) for
+// j = (c+1)m .. cm+1 with J_j assembled at the stored forward state u_j.
+template <typename S, int R, int LP>
+__device__ __forceinline__ void adjoint_chain(const FineArgs& a, const AdjArgs& b, const int c,
+                                              unsigned char* dyn_lds, double* lds_d, S* lds_s) {
+    int ph_d = 0, ph_s = 0;
+    const int n = a.n, m = a.m, N = a.N;
+    const long NP = a.n_pad;
+    double* vec = a.vec + (long)c * kFineVec * NP;
+    double* lam = vec + V_U * NP;
+    double* y = vec + V_UP * NP;
+    double* rhs = vec + V_R * NP;
+    S* pv = reinterpret_cast<S*>(a.pcg) + (long)c * kPcgVec * NP;
+    S* px = pv + P_X * NP;
+    S* jv = reinterpret_cast<S*>(a.jac) + (long)c * a.vals_pad;
+    double* el = a.elem + (long)c * 8 * a.ne_pad;
+    S* p_l = reinterpret_cast<S*>(dyn_lds);
+    S* d_l = p_l + NP;
+    S* r_l = p_l + NP;
+    float* df_l = reinterpret_cast<float*>(r_l + NP);
+    S* tq_l = reinterpret_cast<S*>(df_l + NP);
+    S* dinv = LP == 2 ? d_l : pv + P_D * NP;
+    const double* T0 = b.traj + (long)c * (m + 1) * n;
+    const double* T1 = b.traj + (long)((c + 1) % N) * (m + 1) * n;
+    const double* Lin = b.lam_in + (long)((c + 1) % N) * n;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) lam[i] = Lin[i];
+    __syncthreads();
+    const double inv_dt = 1.0 / a.dt;
+    const double gcoef = 2.0 / (b.T * a.dt);
+    int lin_total = 0, lin_max = 0, capped = 0;
+    for (int jl = m; jl >= 1; --jl) {
+        const double* uj = T0 + (long)jl * n;
+        const double* ujm = T0 + (long)(jl - 1) * n;
+        const double* nx0 = jl < m ? uj : T1;
+        const double* nx1 = jl < m ? T0 + (long)(jl + 1) * n : T1 + n;
+        for (int i = threadIdx.x; i < n; i += blockDim.x)
+            y[i] = lam[i] * inv_dt + gcoef * ((uj[i] - ujm[i]) - (nx1[i] - nx0[i]));
+        __syncthreads();
+        double v[1] = {mass_apply_neg(a, y, rhs)};
+        block_sum<double, 1>(v, lds_d, ph_d);
+        const double rn = sqrt(v[0]);
+        element_pass<double>(a, uj, nullptr, 0.0, ujm, el, inv_dt);
+        __syncthreads();
+        assemble<S>(a, el, inv_dt, jv);
+        __syncthreads();
+        if constexpr (R > 0) {
+            for (int i = threadIdx.x; i < n; i += blockDim.x) df_l[i] = (float)(1.0 / (double)jv[a.dpos[i]]);
+        } else {
+            for (int i = threadIdx.x; i < n; i += blockDim.x) dinv[i] = (S)1 / jv[a.dpos[i]];
+        }
+        __syncthreads();
+        int k = 0;
+        if (rn > 0.0) {
+            if constexpr (R > 0)
+                k = pcg_regs<S, R>(a, jv, p_l, r_l, df_l, tq_l, rhs, px, b.tol_lin * rn, lds_s, ph_s);
+            else
+                k = pcg_mem<S, LP>(a, jv, pv, p_l, d_l, rhs, b.tol_lin * rn, lds_s, ph_s);
+        } else {
+            for (int i = threadIdx.x; i < n; i += blockDim.x) px[i] = 0;
+        }
+        __syncthreads();
+        lin_total += k;
+        lin_max = k > lin_max ? k : lin_max;
+        if (k == a.max_lin) ++capped;
+        double* Lall = b.lam_all + ((long)c * m + (jl - 1)) * n;
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            const double vv = (double)px[i];
+            lam[i] = vv;
+            Lall[i] = vv;
+        }
+        __syncthreads();
+    }
+    double* out = b.lam_out + (long)c * n;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) out[i] = lam[i];
+    if (threadIdx.x == 0) {
+        int* cnt = a.count + 8 * c;
+        cnt[C_STATUS] = 0;
+        cnt[C_NEWTON] = 0;
+        cnt[C_LIN] = lin_total;
+        cnt[C_NEWTON_MAX] = 0;
+        cnt[C_LIN_MAX] = lin_max;
+        cnt[C_CAPPED] = capped;
+        cnt[C_FAILSTEP] = -1;
+        cnt[C_RESID] = 0;
+    }
+}
+
+template <typename S, int R, int BLOCK, int LP>
+__global__ __launch_bounds__(BLOCK) void k_adjoint_sweep(FineArgs a, AdjArgs b) {
+    extern __shared__ unsigned char dyn_lds[];
+    __shared__ double lds_d[2 * 16 * 4];
+    __shared__ S lds_s[2 * 16 * 4];
+    adjoint_chain<S, R, LP>(a, b, blockIdx.x, dyn_lds, lds_d, lds_s);
 }
 
 template <typename S, int R, int BLOCK, int LP>
@@ -665,6 +792,7 @@ FineArgs make_fine_args(ppc_problem* pr, const ppc_params* p, const double* U, d
     a.tail_ptr = d.tail_ptr;
     a.tail_col = d.tail_col;
     a.predictor = p->reserved[0] == 0 ? 1 : 0;
+    a.traj = nullptr;
     return a;
 }
 
@@ -681,6 +809,47 @@ void launch_fine_sweep(ppc_problem* pr, const ppc_params* p, const double* U, do
         launch_typed<double>(a, p->N, sh, s);
     else
         launch_typed<float>(a, p->N, sh, s);
+    PPC_HIP(hipGetLastError());
+}
+
+void launch_fine_sweep_traj(ppc_problem* pr, const ppc_params* p, const double* U, double* F,
+                            double* traj, hipStream_t s) {
+    FineArgs a = make_fine_args(pr, p, U, F);
+    a.traj = traj;
+    const FineShape sh = fine_shape(pr, p);
+    if (p->precision == 0)
+        launch_typed<double>(a, p->N, sh, s);
+    else
+        launch_typed<float>(a, p->N, sh, s);
+    PPC_HIP(hipGetLastError());
+}
+
+namespace {
+
+template <int R, int LP>
+void launch_adj_shape(const FineArgs& a, const AdjArgs& b, size_t lds, hipStream_t s) {
+    static bool attr_set = false;
+    if (!attr_set) {
+        PPC_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_adjoint_sweep<double, R, kFineBlock, LP>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBudget));
+        attr_set = true;
+    }
+    hipLaunchKernelGGL((k_adjoint_sweep<double, R, kFineBlock, LP>), dim3(a.N), dim3(kFineBlock), lds, s, a, b);
+}
+
+}  // namespace
+
+// The adjoint solves are FP64 whatever the forward precision.
+void launch_adjoint_sweep(ppc_problem* pr, const ppc_params* p, const AdjArgs& b, hipStream_t s) {
+    const FineArgs a = make_fine_args(pr, p, nullptr, nullptr);
+    const FineShape sh = pick_shape(pr->mesh.n_free, pr->ws.n_pad, pr->mesh.n_tail, sizeof(double), p->block);
+    if (sh.R == 1) launch_adj_shape<1, 0>(a, b, sh.lds, s);
+    else if (sh.R == 2) launch_adj_shape<2, 0>(a, b, sh.lds, s);
+    else if (sh.R == 4) launch_adj_shape<4, 0>(a, b, sh.lds, s);
+    else if (sh.R == 8) launch_adj_shape<8, 0>(a, b, sh.lds, s);
+    else if (sh.LP == 2) launch_adj_shape<0, 2>(a, b, sh.lds, s);
+    else if (sh.LP == 1) launch_adj_shape<0, 1>(a, b, sh.lds, s);
+    else launch_adj_shape<0, 0>(a, b, 0, s);
     PPC_HIP(hipGetLastError());
 }
 

@@ -188,6 +188,7 @@ struct FineArgs {
     // ELL pattern of the fine-sweep SpMV
     int W, ntail, nvals;
     int predictor;
+    double* traj;            // [N][m+1][n] fine trajectory of each chain, or null
     long ell_pad;
     const int* ecol;
     const int* vslot;
@@ -195,6 +196,17 @@ struct FineArgs {
     const int* tail_row;
     const int* tail_ptr;
     const int* tail_col;
+};
+
+// Adjoint backward sweep: chain c maps Lambda_{c+1} = lambda_{(c+1)m+1} to
+// lambda_{cm+1} through J_j lambda_j = (M/dt) lambda_{j+1} + dP/du_j.
+struct AdjArgs {
+    const double* traj;      // [N][m+1][n] forward trajectory per chain
+    const double* lam_in;    // [N][n] Lambda_c
+    double* lam_out;         // [N][n] B_c(Lambda_{c+1})
+    double* lam_all;         // [N][m][n] lambda_j of the sweep
+    double tol_lin;          // relative tolerance of each adjoint solve
+    double T;
 };
 
 // Kernel shape of a design's fine sweep: register rows R (0: memory path), workgroup,
@@ -254,6 +266,19 @@ void launch_fine_sweep(ppc_problem* pr, const ppc_params* p, const double* U, do
 void fine_batch_prepare(FineBatch& b, const std::vector<ppc_problem*>& parts, const ppc_params* p,
                         hipStream_t s);
 void fine_batch_launch(FineBatch& b, const std::vector<char>& active, hipStream_t s);
+FineArgs make_fine_args(ppc_problem* pr, const ppc_params* p, const double* U, double* F);
+FineShape fine_shape(const ppc_problem* pr, const ppc_params* p);
+void launch_fine_sweep_traj(ppc_problem* pr, const ppc_params* p, const double* U, double* F,
+                            double* traj, hipStream_t s);
+void launch_adjoint_sweep(ppc_problem* pr, const ppc_params* p, const AdjArgs& b, hipStream_t s);
+
+// adjoint helpers (adjoint.hip)
+void launch_reverse_rows(int N, int n, const double* src, double* dst, hipStream_t s);
+void launch_add_reversed(int N, int n, const double* dR, double* L, hipStream_t s);
+void launch_loss(ppc_problem* pr, const ppc_params* p, const double* traj, double* part, double* out,
+                 hipStream_t s);
+void launch_gradients(ppc_problem* pr, const ppc_params* p, const double* traj, const double* lam_all,
+                      double* dsig, double* dk_elem, double* dk_mat, int n_mat, hipStream_t s);
 
 // coarse correction pieces (coarse.hip)
 void launch_jumps(ppc_problem* pr, int N, const double* U, const double* F, double* J,

@@ -192,6 +192,26 @@ class Problem:
         k = iters.value
         return U, resid[: k + 1].copy(), k, st.as_dict(), rc
 
+    # -- adjoint -------------------------------------------------------------------------------
+    def adjoint(self, prm, U_periodic, n_mat):
+        """Loss and gradients at a periodic state U_periodic ([N, n_nodes], host array or
+        CUDA tensor).  Returns (loss, dP/dsigma [n_tri], dP/dk [n_mat, 3], iterations, stats)."""
+        if hasattr(U_periodic, "detach"):
+            U_periodic = U_periodic.detach().cpu().numpy()
+        Uh = _f64(U_periodic)
+        if Uh.shape != (prm.N, self.n_nodes):
+            raise ValueError(f"expected shape {(prm.N, self.n_nodes)}")
+        loss = np.zeros(1)
+        dsig = np.zeros(self.n_tri)
+        dk = np.zeros(3 * n_mat)
+        iters = c_int32()
+        st = nat.Stats()
+        rc = lib().ppc_adjoint(self.handle.h, self.p, byref(prm), _pd(Uh), _pd(loss), _pd(dsig), _pd(dk),
+                               byref(iters), byref(st))
+        if rc < 0:
+            raise _err(self.handle.h, rc)
+        return float(loss[0]), dsig, dk.reshape(n_mat, 3), iters.value, st.as_dict()
+
     # -- single pieces ------------------------------------------------------------------------
     def fine_sweep(self, prm, U):
         """F[n mod N] = F_n(U[n-1]) for all chains (one launch).  U: CUDA [N, n_nodes]."""
