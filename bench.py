@@ -58,6 +58,9 @@ def parse():
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c5small"])
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--tol", type=float, default=1e-8, help="PP-PC stopping tolerance on eps")
+    ap.add_argument("--tol-cocg", type=float, default=1e-6,
+                    help="relative tolerance of the harmonic solves (a correction only needs to be "
+                         "accurate relative to the current jumps)")
     ap.add_argument("--cpu-baseline", dest="cpu", action="store_true", default=True)
     ap.add_argument("--no-cpu-baseline", dest="cpu", action="store_false")
     ap.add_argument("--cpu-procs", type=int, default=16)
@@ -180,7 +183,7 @@ def main():
     pr = P.Problem(h, prob)
     setup_s = time.perf_counter() - t0
     prec = 0 if a.precision == "fp64" else 1
-    prm = P.problem_params(prob, tol_ppc=a.tol, precision=prec,
+    prm = P.problem_params(prob, tol_ppc=a.tol, precision=prec, tol_cocg=a.tol_cocg,
                            **({"tol_lin": 1e-4} if prec == 1 else {}))
     out = torch.empty((prob.N, pr.n_nodes), dtype=torch.float64, device="cuda")
     for _ in range(a.warmup):
@@ -230,6 +233,7 @@ def main():
                         f"{prob.N // 2 + 1} harmonics, amplitude {prob.amps[0]:.1f} A",
             "precision": a.precision,
             "tol_ppc": a.tol,
+            "tol_cocg": a.tol_cocg,
             "iterations": k,
             "err_vs_oracle": err,
             "max_b_steel_T": st["max_b_steel"],

@@ -113,7 +113,12 @@ typedef struct {
     int32_t block;          /* fine-kernel path: 0 = library choice (register rows for small
                                meshes, else LDS-resident p / diagonal); 1024 = force the
                                workgroup-memory PCG path */
-    int32_t reserved[7];
+    int32_t no_predictor;   /* 1: start every Newton solve from u_{j-1}; 0: also try the
+                               extrapolation 2 u_{j-1} - u_{j-2} and keep the smaller residual */
+    int32_t lin_point;      /* samples the coarse stiffness is linearised at: 0 = the current
+                               iterate U^k, 1 = the fine results F^k of the same sweep (equal
+                               at the fixed point) */
+    int32_t reserved[5];
 } ppc_params;
 
 /* Counters and timings of the last solve (all chains, all iterations). */
@@ -145,7 +150,8 @@ int ppc_version(void);
 
 /* Defaults: T = 0.02, N = 10, m = 20, shift 0, lin 0, init 0, FP64, tol_ppc 1e-12,
  * max_iters 60, tol_newton 1e-13, max_newton 50, tol_lin 1e-8, max_lin 20000,
- * tol_cocg 1e-10, max_cocg 20000.  Returns PPC_ERR_ARG on a null pointer. */
+ * tol_cocg 1e-10, max_cocg 20000, block 0, predictor on, lin_point 1 (fine results).
+ * Returns PPC_ERR_ARG on a null pointer. */
 int ppc_params_default(ppc_params* p);
 
 /* Message of the last error on this handle (never null; valid until the next call on

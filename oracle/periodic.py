@@ -239,7 +239,7 @@ def make_pool(prob, processes):
     return mp.get_context("fork").Pool(processes, initializer=_init_worker, initargs=(prob,))
 
 
-def coarse_correction(fe, U, J, shift="ie", lin="tensor"):
+def coarse_correction(fe, U, J, shift="ie", lin="tensor", U_lin=None):
     """Delta U from the jumps J (rows n = 0..N-1, J[n] = F_n - U_n mod N).
 
     In the linear case eq. (4) with implicit-Euler G (eq. (8)) is equivalent to the
@@ -249,15 +249,19 @@ def coarse_correction(fe, U, J, shift="ie", lin="tensor"):
     G dU = Q J for dU = U^{k+1} - U^k; that correction form is used."""
     prob = fe.prob
     N, T = prob.N, prob.T
-    Kbar = coarse_stiffness(fe, U, lin)
+    Kbar = coarse_stiffness(fe, U if U_lin is None else U_lin, lin)
     Q = fe.M / (T / N) + Kbar
     R = np.asarray((Q @ J.T).T)
     return harmonic_solve(fe, Kbar, R, T, shift)
 
 
 def ppc(fe, tol=1e-12, max_iter=60, U_init=None, shift="ie", lin="tensor",
-        newton_tol=NEWTON_TOL, pool=None, callback=None, init="auto"):
+        newton_tol=NEWTON_TOL, pool=None, callback=None, init="auto", lin_point="F"):
     """Plain PP-PC (eq. (4)).
+
+    lin_point selects the samples the frozen coarse stiffness is linearised at: "U" the
+    current iterate U^k, "F" the fine results F^k of the same sweep (they coincide at the
+    fixed point, so the answer does not change).
 
     Per iteration k: fine sweep F_n(U_{n-1}^k); jumps J_n = F_n - U^k_{n mod N};
     eps^k = ||J||_F/||U^k||_F (the paper does not state the tolerance quantity; this
@@ -281,7 +285,7 @@ def ppc(fe, tol=1e-12, max_iter=60, U_init=None, shift="ie", lin="tensor",
             return U, np.array(hist), k
         if k == max_iter:
             break
-        U = U + coarse_correction(fe, U, J, shift, lin)
+        U = U + coarse_correction(fe, U, J, shift, lin, U_lin=Fs if lin_point == "F" else None)
     raise RuntimeError(f"PP-PC did not converge: eps history {hist[-5:]}")
 
 

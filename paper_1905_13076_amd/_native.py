@@ -50,7 +50,7 @@ class Params(ctypes.Structure):
                 ("tol_ppc", c_double), ("max_iters", c_int32), ("tol_newton", c_double),
                 ("max_newton", c_int32), ("tol_lin", c_double), ("max_lin", c_int32),
                 ("tol_cocg", c_double), ("max_cocg", c_int32), ("block", c_int32),
-                ("reserved", c_int32 * 7)]
+                ("no_predictor", c_int32), ("lin_point", c_int32), ("reserved", c_int32 * 5)]
 
 
 class Stats(ctypes.Structure):

@@ -89,7 +89,7 @@ float elapsed(hipEvent_t a, hipEvent_t b) {
 }  // namespace
 
 void workspace_free(Workspace& w) {
-    void* ptrs[] = {w.fvec, w.fpcg, w.fjac, w.felem, w.fcount, w.U, w.F, w.J, w.R, w.kbar,
+    void* ptrs[] = {w.fvec, w.fpcg, w.fjac, w.felem, w.fcount, w.U, w.F, w.J, w.R, w.kbar, w.kbar32,
                     w.nubar, w.rhat, w.cwork, w.sig, w.ccount, w.twiddle, w.partial, w.scal};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
@@ -117,6 +117,7 @@ void ensure_workspace(ppc_problem* pr, const ppc_params* p) {
     w.J = dalloc<double>(N * d.n_free);
     w.R = dalloc<double>(N * d.n_free);
     w.kbar = dalloc<double>(d.nnz);
+    w.kbar32 = dalloc<float>(d.nnz);
     w.nubar = dalloc<double>(3 * (size_t)d.n_tri);
     w.rhat = dalloc<double2>(2 * H * d.n_free);
     w.cwork = dalloc<double2>(H * 4 * w.n_pad);
@@ -262,7 +263,7 @@ int solve_device(ppc_handle* h, ppc_problem* pr, const ppc_params* p, const doub
         }
         if (k == p->max_iters) break;
         PPC_HIP(hipEventRecord(ev[2], s));
-        launch_coarse(pr, p, w.U, w.J, w.U, true, false, s);
+        launch_coarse(pr, p, p->lin_point == 1 ? w.F : w.U, w.J, w.U, true, false, s);
         PPC_HIP(hipEventRecord(ev[3], s));
         read_cocg(pr, H, s, nullptr, &S.cocg_total, &S.cocg_max);  // synchronises
         S.coarse_ms += elapsed(ev[2], ev[3]);
@@ -335,7 +336,8 @@ int solve_batch_device(ppc_handle* h, ppc_problem* bp, const ppc_params* p, cons
         if (list.empty()) return;
         for (int d : list) {
             Workspace& w = parts[d]->ws;
-            launch_coarse_pre(parts[d], p, excitation ? nullptr : w.U, excitation ? nullptr : w.J, excitation, s);
+            launch_coarse_pre(parts[d], p, excitation ? nullptr : (p->lin_point == 1 ? w.F : w.U),
+                              excitation ? nullptr : w.J, excitation, s);
         }
         cw.clear();
         for (int d : list)
@@ -572,6 +574,8 @@ int ppc_params_default(ppc_params* p) {
     p->tol_cocg = 1e-10;
     p->max_cocg = 20000;
     p->block = 0;
+    p->no_predictor = 0;
+    p->lin_point = 1;
     return PPC_OK;
 }
 

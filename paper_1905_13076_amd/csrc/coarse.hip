@@ -142,7 +142,7 @@ __global__ void k_linearise(int ne, int n, int nsamp, const double* __restrict__
 __global__ void k_kbar(int nnz, int ne, const int* __restrict__ slot_ptr, const int* __restrict__ slot_src,
                        const double* __restrict__ area, const double* __restrict__ gx,
                        const double* __restrict__ gy, const double* __restrict__ nub,
-                       double* __restrict__ kbar) {
+                       double* __restrict__ kbar, float* __restrict__ kbar32) {
     for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < nnz; s += gridDim.x * blockDim.x) {
         double acc = 0.0;
         for (int k = slot_ptr[s]; k < slot_ptr[s + 1]; ++k) {
@@ -154,6 +154,7 @@ __global__ void k_kbar(int nnz, int ne, const int* __restrict__ slot_ptr, const 
             acc += area[e] * (nub[e] * xa * xb + nub[ne + e] * (xa * yb + ya * xb) + nub[2 * ne + e] * ya * yb);
         }
         kbar[s] = acc;
+        kbar32[s] = (float)acc;
     }
 }
 
@@ -333,9 +334,196 @@ __device__ __forceinline__ void cocg_body(const CocgArgs& a, const int p, double
     }
 }
 
+__device__ inline float2 cmulf(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// Complex-FP32 COCG refined to FP64: x = 0; repeat r = b - A x (FP64); stop when
+// ||r|| <= tol ||b||; solve A d = r in complex FP32 (FP32 K, M copies, FP32 vectors and
+// accumulation) to kInnerTol relative; x += d.
+__device__ __forceinline__ void cocg_mixed_body(const CocgArgs& a, const int p, double* lds) {
+    constexpr double kInnerTol = 1e-5;
+    constexpr int kMaxRefine = 30;
+    const int n = a.n;
+    const double2 sg = a.sig[p];
+    const float2 sgf = make_float2((float)sg.x, (float)sg.y);
+    const double2* __restrict__ b = a.B + (long)p * n;
+    double2* __restrict__ x = a.X + (long)p * n;
+    double2* wk = a.work + (long)p * 4 * a.n_pad;               // 4 * n_pad double2 of room
+    double2* rd = wk;                                          // FP64 residual
+    float2* rf = reinterpret_cast<float2*>(wk + a.n_pad);      // FP32 r, p, q, dinv, d
+    float2* pf = rf + a.n_pad;
+    float2* qf = pf + a.n_pad;
+    float2* df = qf + a.n_pad;
+    float2* xf = df + a.n_pad;
+    int ph = 0;
+    constexpr int G = kRowGroup;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int sub = lane % G, grp = lane / G;
+    constexpr int RPW = 64 / G;
+    double v0[1] = {0.0};
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const double2 bi = b[i];
+        x[i] = make_double2(0.0, 0.0);
+        rd[i] = bi;
+        v0[0] += bi.x * bi.x + bi.y * bi.y;
+        const int dd = a.diag[i];
+        const double2 D = make_double2(a.kbar[dd] + sg.x * a.mval[dd], sg.y * a.mval[dd]);
+        const double2 di = cdiv(make_double2(1.0, 0.0), D);
+        df[i] = make_float2((float)di.x, (float)di.y);
+    }
+    block_sum_d<1>(v0, lds, ph);
+    const double bn2 = v0[0];
+    double rr = bn2;
+    int total = 0, status = 0, refine = 0;
+    while (rr > a.tol * a.tol * bn2 && refine < kMaxRefine && total < a.max_it && status == 0) {
+        ++refine;
+        // inner complex-FP32 COCG on A d = r / ||r|| (unit right-hand side: FP32 keeps its
+        // range whatever the harmonic's magnitude), then x += ||r|| d
+        const double rs = 1.0 / sqrt(rr);
+        double v[3] = {0.0, 0.0, 0.0};
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            const double2 r64 = rd[i];
+            const float2 ri = make_float2((float)(r64.x * rs), (float)(r64.y * rs));
+            const float2 zi = cmulf(df[i], ri);
+            rf[i] = ri;
+            pf[i] = zi;
+            xf[i] = make_float2(0.f, 0.f);
+            const float2 rz = cmulf(ri, zi);
+            v[0] += rz.x;
+            v[1] += rz.y;
+            v[2] += (double)(ri.x * ri.x + ri.y * ri.y);
+        }
+        block_sum_d<3>(v, lds, ph);
+        float2 rho = make_float2((float)v[0], (float)v[1]);
+        const double in2 = v[2];
+        double irr = in2;
+        while (irr > kInnerTol * kInnerTol * in2 && total < a.max_it) {
+            double m2[2] = {0.0, 0.0};
+            for (int base = wave * RPW; base < n; base += nw * RPW) {
+                const int i = base + grp;
+                float ax = 0.f, ay = 0.f, bx = 0.f, by = 0.f;
+                if (i < n) {
+                    const int k1 = a.rowptr[i + 1];
+                    for (int kk = a.rowptr[i] + sub; kk < k1; kk += G) {
+                        const float2 pc = pf[a.colidx[kk]];
+                        const float kv = a.kbar32[kk], mv = a.mval32[kk];
+                        ax += kv * pc.x;
+                        ay += kv * pc.y;
+                        bx += mv * pc.x;
+                        by += mv * pc.y;
+                    }
+                }
+#pragma unroll
+                for (int off = G / 2; off > 0; off >>= 1) {
+                    ax += __shfl_xor(ax, off);
+                    ay += __shfl_xor(ay, off);
+                    bx += __shfl_xor(bx, off);
+                    by += __shfl_xor(by, off);
+                }
+                if (i < n && sub == 0) {
+                    const float2 qi = make_float2(ax + sgf.x * bx - sgf.y * by, ay + sgf.x * by + sgf.y * bx);
+                    qf[i] = qi;
+                    const float2 pq = cmulf(pf[i], qi);
+                    m2[0] += pq.x;
+                    m2[1] += pq.y;
+                }
+            }
+            block_sum_d<2>(m2, lds, ph);
+            const double2 mu = make_double2(m2[0], m2[1]);
+            if (mu.x == 0.0 && mu.y == 0.0) { status = PPC_ERR_BREAKDOWN; break; }
+            const double2 al = cdiv(make_double2(rho.x, rho.y), mu);
+            const float2 alpha = make_float2((float)al.x, (float)al.y);
+            double v2[3] = {0.0, 0.0, 0.0};
+            for (int i = threadIdx.x; i < n; i += blockDim.x) {
+                const float2 ap = cmulf(alpha, pf[i]), aq = cmulf(alpha, qf[i]);
+                float2 xi = xf[i];
+                xi.x += ap.x;
+                xi.y += ap.y;
+                xf[i] = xi;
+                float2 ri = rf[i];
+                ri.x -= aq.x;
+                ri.y -= aq.y;
+                rf[i] = ri;
+                const float2 rz = cmulf(ri, cmulf(df[i], ri));
+                v2[0] += rz.x;
+                v2[1] += rz.y;
+                v2[2] += (double)(ri.x * ri.x + ri.y * ri.y);
+            }
+            block_sum_d<3>(v2, lds, ph);
+            ++total;
+            irr = v2[2];
+            if (irr <= kInnerTol * kInnerTol * in2) break;
+            if (v2[0] == 0.0 && v2[1] == 0.0) { status = PPC_ERR_BREAKDOWN; break; }
+            if (!isfinite(irr)) { status = PPC_ERR_NONFINITE; break; }
+            const double2 be = cdiv(make_double2(v2[0], v2[1]), make_double2(rho.x, rho.y));
+            const float2 beta = make_float2((float)be.x, (float)be.y);
+            rho = make_float2((float)v2[0], (float)v2[1]);
+            for (int i = threadIdx.x; i < n; i += blockDim.x) {
+                const float2 zi = cmulf(df[i], rf[i]);
+                const float2 bp = cmulf(beta, pf[i]);
+                pf[i] = make_float2(zi.x + bp.x, zi.y + bp.y);
+            }
+            __syncthreads();
+        }
+        // x += ||r|| d ; r = b - A x in FP64
+        const double rsc = sqrt(rr);
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            double2 xi = x[i];
+            xi.x += rsc * (double)xf[i].x;
+            xi.y += rsc * (double)xf[i].y;
+            x[i] = xi;
+        }
+        __syncthreads();
+        double v3[1] = {0.0};
+        for (int base = wave * RPW; base < n; base += nw * RPW) {
+            const int i = base + grp;
+            double ax = 0.0, ay = 0.0, bx = 0.0, by = 0.0;
+            if (i < n) {
+                const int k1 = a.rowptr[i + 1];
+                for (int kk = a.rowptr[i] + sub; kk < k1; kk += G) {
+                    const double2 xc = x[a.colidx[kk]];
+                    const double kv = a.kbar[kk], mv = a.mval[kk];
+                    ax += kv * xc.x;
+                    ay += kv * xc.y;
+                    bx += mv * xc.x;
+                    by += mv * xc.y;
+                }
+            }
+#pragma unroll
+            for (int off = G / 2; off > 0; off >>= 1) {
+                ax += __shfl_xor(ax, off);
+                ay += __shfl_xor(ay, off);
+                bx += __shfl_xor(bx, off);
+                by += __shfl_xor(by, off);
+            }
+            if (i < n && sub == 0) {
+                const double2 bi = b[i];
+                const double2 ri = make_double2(bi.x - (ax + sg.x * bx - sg.y * by),
+                                                bi.y - (ay + sg.x * by + sg.y * bx));
+                rd[i] = ri;
+                v3[0] += ri.x * ri.x + ri.y * ri.y;
+            }
+        }
+        block_sum_d<1>(v3, lds, ph);
+        rr = v3[0];
+    }
+    if (threadIdx.x == 0) {
+        a.count[4 * p + 0] = status;
+        a.count[4 * p + 1] = total;
+        a.count[4 * p + 2] = (rr <= a.tol * a.tol * bn2) ? 1 : 0;
+        a.count[4 * p + 3] = refine;
+    }
+}
+
+__device__ __forceinline__ void cocg_dispatch(const CocgArgs& a, const int p, double* lds) {
+    if (a.mixed) cocg_mixed_body(a, p, lds);
+    else cocg_body(a, p, lds);
+}
+
 __global__ __launch_bounds__(1024) void k_cocg(CocgArgs a) {
     __shared__ double lds[2 * 16 * 3];
-    cocg_body(a, blockIdx.x, lds);
+    cocg_dispatch(a, blockIdx.x, lds);
 }
 
 // Batched designs: block b solves harmonic work[b].y of design work[b].x.
@@ -343,7 +531,7 @@ __global__ __launch_bounds__(1024) void k_cocg_batch(const CocgArgs* __restrict_
                                                      const int2* __restrict__ work) {
     __shared__ double lds[2 * 16 * 3];
     const int2 wk = work[blockIdx.x];
-    cocg_body(args[wk.x], wk.y, lds);
+    cocg_dispatch(args[wk.x], wk.y, lds);
 }
 
 // sigma_p, p = 0..N/2: exact implicit-Euler symbol (1 - e^{-i w_p dT})/dT or i w_p
@@ -474,7 +662,7 @@ void launch_coarse_pre(ppc_problem* pr, const ppc_params* p, const double* U, co
                        d.efree, d.gx, d.gy, d.area, d.k0, d.mat, pr->lawtab, p->lin_mode, w.nubar);
     const int sg = std::max(1, std::min((d.nnz + eb - 1) / eb, 4096));
     hipLaunchKernelGGL(k_kbar, dim3(sg), dim3(eb), 0, s, d.nnz, ne, d.slot_ptr, d.slot_src, d.area, d.gx,
-                       d.gy, w.nubar, w.kbar);
+                       d.gy, w.nubar, w.kbar, w.kbar32);
     const dim3 rg((n + 255) / 256, N);
     if (excitation_rhs)
         hipLaunchKernelGGL(k_excitation_rows, rg, dim3(256), 0, s, n, N, p->T, d.fload, pr->wavtab,
@@ -508,6 +696,9 @@ CocgArgs make_cocg_args(ppc_problem* pr, const ppc_params* p) {
     a.tol = p->tol_cocg;
     a.max_it = p->max_cocg;
     a.count = w.ccount;
+    a.mixed = p->precision == 1 ? 1 : 0;
+    a.kbar32 = w.kbar32;
+    a.mval32 = d.mval32;
     return a;
 }
 

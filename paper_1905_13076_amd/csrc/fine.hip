@@ -791,7 +791,7 @@ FineArgs make_fine_args(ppc_problem* pr, const ppc_params* p, const double* U, d
     a.tail_row = d.tail_row;
     a.tail_ptr = d.tail_ptr;
     a.tail_col = d.tail_col;
-    a.predictor = p->reserved[0] == 0 ? 1 : 0;
+    a.predictor = p->no_predictor == 0 ? 1 : 0;
     a.traj = nullptr;
     return a;
 }

@@ -74,6 +74,7 @@ struct DeviceMesh {
     double* sigma = nullptr;   // [n_tri]
     double* js = nullptr;      // [n_tri]
     double* mval = nullptr;    // [nnz] conductivity mass M
+    float* mval32 = nullptr;   // [nnz] FP32 copy for the mixed harmonic solves
     double* mdiag = nullptr;   // [n_free]
     double* fload = nullptr;   // [n_free] load per ampere F
     double fnorm = 0.0;        // ||F||_2
@@ -112,6 +113,7 @@ struct Workspace {
     double* R = nullptr;
     // coarse
     double* kbar = nullptr;    // [nnz]
+    float* kbar32 = nullptr;   // [nnz] FP32 copy for the mixed harmonic solves
     double* nubar = nullptr;   // [3][n_tri]
     double2* rhat = nullptr;   // [2][H][n_free]: right-hand sides, then solutions
     double2* cwork = nullptr;  // [H][4][n_pad] COCG vectors r p q dinv
@@ -245,6 +247,9 @@ struct CocgArgs {
     double tol;
     int max_it;
     int* count;
+    int mixed;               // 1: complex-FP32 inner COCG refined by FP64 residuals
+    const float* kbar32;
+    const float* mval32;
 };
 
 constexpr int kFineVec = 5;   // u, u_prev, R, R_trial, u_{j-2}

@@ -138,6 +138,8 @@ int validate_params(const ppc_params* p, std::string& msg) {
     if (p->max_lin < 1) { msg = "max_lin must be >= 1"; return PPC_ERR_ARG; }
     if (!finite(p->tol_cocg) || !(p->tol_cocg > 0.0) || p->tol_cocg >= 1.0) { msg = "tol_cocg must be in (0, 1)"; return PPC_ERR_ARG; }
     if (p->max_cocg < 1) { msg = "max_cocg must be >= 1"; return PPC_ERR_ARG; }
+    if (p->no_predictor < 0 || p->no_predictor > 1) { msg = "no_predictor must be 0 or 1"; return PPC_ERR_ARG; }
+    if (p->lin_point < 0 || p->lin_point > 1) { msg = "lin_point must be 0 or 1"; return PPC_ERR_ARG; }
     if (p->block != 0 && (p->block < 64 || p->block > 1024 || (p->block % 64) != 0)) {
         msg = "block must be 0 or a multiple of 64 in [64, 1024]";
         return PPC_ERR_ARG;
@@ -210,6 +212,10 @@ __global__ void k_load(int n, const int* __restrict__ node_ptr, const int* __res
         fload[i] = acc;
         mdiag[i] = mval[diag[i]];
     }
+}
+
+__global__ void k_to_f32(int n, const double* __restrict__ x, float* __restrict__ y) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) y[i] = (float)x[i];
 }
 
 // ||x||_2 over one block, fixed summation order
@@ -472,6 +478,8 @@ void build_problem(ppc_problem* pr, const ppc_mesh* mesh, const ppc_material* ma
                        d.sigma, d.area, d.mval);
     hipLaunchKernelGGL(k_load, dim3(grid_for(n, 256)), dim3(256), 0, s, n, d.node_ptr, d.node_src,
                        d.js, d.area, d.diag, d.mval, d.fload, d.mdiag);
+    d.mval32 = dalloc<float>(nnz);
+    hipLaunchKernelGGL(k_to_f32, dim3(grid_for(nnz, 256)), dim3(256), 0, s, nnz, d.mval, d.mval32);
     hipLaunchKernelGGL(k_norm2, dim3(1), dim3(1024), 0, s, n, d.fload, fn);
     PPC_HIP(hipGetLastError());
     PPC_HIP(hipMemcpyAsync(&d.fnorm, fn, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -482,7 +490,7 @@ void build_problem(ppc_problem* pr, const ppc_mesh* mesh, const ppc_material* ma
 void mesh_free(DeviceMesh& d) {
     void* ptrs[] = {d.rowptr, d.colidx, d.diag, d.slot_ptr, d.slot_src, d.node_ptr, d.node_src,
                     d.efree, d.free_node, d.mat, d.xy, d.tri, d.area, d.k0, d.gx, d.gy,
-                    d.sigma, d.js, d.mval, d.mdiag, d.fload, d.ecol, d.vslot, d.dpos,
+                    d.sigma, d.js, d.mval, d.mval32, d.mdiag, d.fload, d.ecol, d.vslot, d.dpos,
                     d.tail_row, d.tail_ptr, d.tail_col};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);

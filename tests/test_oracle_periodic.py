@@ -161,7 +161,8 @@ def test_energy_identity_of_the_periodic_linear_solution():
 def test_nonlinear_routes_and_variants_share_the_fixed_point():
     """Nonlinear (saturating Brauer sheath): sequential periods and PP-PC from U^0 = 0
     with the exact shift, the harmonic-balance shift and the chord linearisation all
-    reach one periodic solution; only iteration counts differ."""
+    reach one periodic solution, as does linearising the coarse stiffness at the fine
+    results instead of the iterate; only iteration counts differ."""
     fe = _tiny_nl(nr=6, ntheta=12, N=8, m=5, amp=400.0)
     US, _ = periodic.route_s(fe, tol=1e-14)
     _, _, b2, _, _ = fe.element_state(US[2])
@@ -170,6 +171,7 @@ def test_nonlinear_routes_and_variants_share_the_fixed_point():
         "zero": periodic.ppc(fe, tol=1e-12, init="zero"),
         "iw": periodic.ppc(fe, tol=1e-12, init="zero", shift="iw"),
         "chord": periodic.ppc(fe, tol=1e-12, init="zero", lin="chord"),
+        "at-F": periodic.ppc(fe, tol=1e-12, init="zero", lin_point="F"),
     }
     for name, (U, hist, k) in runs.items():
         assert rel(U, US) <= 1e-10, name
