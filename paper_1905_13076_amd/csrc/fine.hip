@@ -45,23 +45,74 @@ __device__ inline void reluct(const double* __restrict__ lawtab, int mid, double
     }
 }
 
+// DPP lane move within 16-lane rows (CTRL: quad_perm / mirror codes of the gfx9 DPP
+// encoding); every lane of the wave must be active.
+template <int CTRL, typename T>
+__device__ inline T dpp_mov(T v) {
+    if constexpr (sizeof(T) == 8) {
+        const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+        const unsigned lo = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)u, CTRL, 0xF, 0xF, false);
+        const unsigned hi = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)(u >> 32), CTRL, 0xF, 0xF, false);
+        return __builtin_bit_cast(T, ((unsigned long long)hi << 32) | lo);
+    } else {
+        return __builtin_bit_cast(T, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+    }
+}
+
+template <typename T>
+__device__ inline T read_lane(T v, int l) {
+    if constexpr (sizeof(T) == 8) {
+        const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+        const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, l);
+        const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), l);
+        return __builtin_bit_cast(T, ((unsigned long long)hi << 32) | lo);
+    } else {
+        return __builtin_bit_cast(T, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+    }
+}
+
+// Wave sum in a fixed order: pairs, quads, half rows and rows by DPP (each step adds two
+// partial sums that commute, so all lanes of a row hold the same bits), then the four
+// row sums as (r0 + r1) + (r2 + r3).  Returns the same value on every lane.
+template <typename T>
+__device__ inline T wave_sum(T v) {
+    v += dpp_mov<0xB1>(v);    // quad_perm [1,0,3,2]
+    v += dpp_mov<0x4E>(v);    // quad_perm [2,3,0,1]
+    v += dpp_mov<0x141>(v);   // row_half_mirror
+    v += dpp_mov<0x140>(v);   // row_mirror
+    return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
+}
+
 // Sum of K values over the workgroup in a fixed order; every thread gets the result.
-template <typename T, int K>
+// NW > 0 states the wave count at compile time: the wave partials are then read as one
+// contiguous run per value and added as a pairwise tree; NW == 0 adds them in wave order.
+template <typename T, int K, int NW = 0>
 __device__ inline void block_sum(T (&v)[K], T* lds, int& phase) {
 #pragma unroll
-    for (int k = 0; k < K; ++k)
-        for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off);
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     T* buf = lds + phase * 16 * K;
     if (lane == 0)
 #pragma unroll
-        for (int k = 0; k < K; ++k) buf[w * K + k] = v[k];
+        for (int k = 0; k < K; ++k) buf[k * 16 + w] = v[k];
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        T s = 0;
-        for (int j = 0; j < nw; ++j) s += buf[j * K + k];
-        v[k] = s;
+        if constexpr (NW > 0) {
+            T t[NW];
+#pragma unroll
+            for (int j = 0; j < NW; ++j) t[j] = buf[k * 16 + j];
+#pragma unroll
+            for (int h = NW / 2; h > 0; h >>= 1)
+#pragma unroll
+                for (int j = 0; j < h; ++j) t[j] = t[2 * j] + t[2 * j + 1];
+            v[k] = t[0];
+        } else {
+            const int nw = blockDim.x >> 6;
+            T s = 0;
+            for (int j = 0; j < nw; ++j) s += buf[k * 16 + j];
+            v[k] = s;
+        }
     }
     phase ^= 1;
 }
@@ -166,6 +217,20 @@ __device__ inline void assemble(const FineArgs& a, const double* __restrict__ el
     }
 }
 
+// Raw buffer resource over [base, base + bytes) (gfx9 word 3: 32-bit untyped data);
+// loads past the end return 0 instead of faulting.
+__device__ inline __amdgpu_buffer_rsrc_t buffer_rsrc(const void* base, unsigned bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)bytes, 0x00020000);
+}
+
+template <typename S>
+__device__ inline S buffer_load(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+    if constexpr (sizeof(S) == 8)
+        return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+    else
+        return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+
 // Row-sum of one tail (long) row by a whole wave; returns the sum on every lane.
 template <typename S, typename PV>
 __device__ inline S tail_row_sum(const FineArgs& a, const S* __restrict__ jv, PV p, int t, int lane) {
@@ -181,17 +246,19 @@ __device__ inline S tail_row_sum(const FineArgs& a, const S* __restrict__ jv, PV
 // (i = tid + k B, k < R) keep x and q in registers; p, r and the inverse diagonal (FP32:
 // it only shapes the preconditioner) live in LDS, so the SpMV gathers and every vector
 // pass stay on the CU and only the ELL values and columns stream from memory.
-template <typename S, int R>
+template <typename S, int R, int B>
 __device__ int pcg_regs(const FineArgs& a, const S* __restrict__ jv, S* __restrict__ p_l,
                         S* __restrict__ r_l, const float* __restrict__ d_l, S* __restrict__ tq_l,
                         const double* __restrict__ Rres, S* __restrict__ xout, double tgt,
                         S* lds_s, int& ph) {
-    const int B = blockDim.x, tid = threadIdx.x, n = a.n;
+    const int tid = threadIdx.x, n = a.n;
     const int lane = tid & 63, wave = tid >> 6, nw = B >> 6;
     const long NP = a.ell_pad;
     const int W = a.W;
     S x[R], q[R];
     unsigned tailmask = 0;
+    const __amdgpu_buffer_rsrc_t rv_j = buffer_rsrc(jv, (unsigned)(W * NP * sizeof(S)));
+    const __amdgpu_buffer_rsrc_t rv_c = buffer_rsrc(a.ecol, (unsigned)(W * NP * 4));
     S loc[2] = {0, 0};
 #pragma unroll
     for (int k = 0; k < R; ++k) {
@@ -208,21 +275,36 @@ __device__ int pcg_regs(const FineArgs& a, const S* __restrict__ jv, S* __restri
             if (a.ecol[i] < 0) tailmask |= 1u << k;
         }
     }
-    block_sum<S, 2>(loc, lds_s, ph);
+    block_sum<S, 2, B / 64>(loc, lds_s, ph);
     S rz = loc[0];
     double rr = (double)loc[1];
     int it = 0;
     while (rr > tgt * tgt && it < a.max_lin) {
         S dot[1] = {0};
+        // slot-major: each slot w issues the value and column loads of all R rows of the
+        // thread at once (wave-uniform bases, one lane offset), so R loads are in flight
+        // per round trip; every row still sums its slots in order 0..W-1.
+        // The loads are unconditional: rows past the ELL arrays read 0, tail rows hold
+        // zero values (their column -1 is clamped), and rows >= n are never used.
+#pragma unroll
+        for (int k = 0; k < R; ++k) q[k] = 0;
+        for (int w = 0; w < W; ++w) {
+            S v[R];
+            int col[R];
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                const unsigned row0 = (unsigned)(w * NP + k * B);
+                v[k] = buffer_load<S>(rv_j, tid * sizeof(S), row0 * sizeof(S));
+                col[k] = buffer_load<int>(rv_c, tid * 4u, row0 * 4u);
+            }
+            __builtin_amdgcn_sched_barrier(0);   // keep the 2R loads of slot w in flight together
+#pragma unroll
+            for (int k = 0; k < R; ++k) q[k] += v[k] * p_l[col[k] < 0 ? 0 : col[k]];
+        }
 #pragma unroll
         for (int k = 0; k < R; ++k) {
             const int i = tid + k * B;
-            if (i < n && !((tailmask >> k) & 1u)) {
-                S acc = 0;
-                for (int w = 0; w < W; ++w) acc += jv[w * NP + i] * p_l[a.ecol[w * NP + i]];
-                q[k] = acc;
-                dot[0] += p_l[i] * acc;
-            }
+            if (i < n && !((tailmask >> k) & 1u)) dot[0] += p_l[i] * q[k];
         }
         for (int t = wave; t < a.ntail; t += nw) {
             const S acc = tail_row_sum<S>(a, jv, p_l, t, lane);
@@ -231,7 +313,7 @@ __device__ int pcg_regs(const FineArgs& a, const S* __restrict__ jv, S* __restri
                 dot[0] += p_l[a.tail_row[t]] * acc;
             }
         }
-        block_sum<S, 1>(dot, lds_s, ph);
+        block_sum<S, 1, B / 64>(dot, lds_s, ph);
         const S pq = dot[0];
         if (!(pq > (S)0)) break;                 // loss of positivity: Newton decides
         const S alpha = rz / pq;
@@ -249,7 +331,7 @@ __device__ int pcg_regs(const FineArgs& a, const S* __restrict__ jv, S* __restri
                 l2[1] += rv * rv;
             }
         }
-        block_sum<S, 2>(l2, lds_s, ph);
+        block_sum<S, 2, B / 64>(l2, lds_s, ph);
         ++it;
         rr = (double)l2[1];
         if (rr <= tgt * tgt) break;
@@ -378,7 +460,7 @@ __device__ inline double mass_norm2(const FineArgs& a, const double* __restrict_
 
 // R > 0: PCG rows in registers, p / diagonal / tail sums in dynamic LDS;
 // R == 0: PCG vectors in memory, with p (LP >= 1) and the diagonal (LP == 2) in LDS.
-template <typename S, int R, int LP>
+template <typename S, int R, int BLOCK, int LP>
 __device__ __forceinline__ void fine_chain(const FineArgs& a, const int c, unsigned char* dyn_lds,
                                            double* lds_d, S* lds_s) {
     int ph_d = 0, ph_s = 0;                   // chain n = c + 1
@@ -475,7 +557,7 @@ __device__ __forceinline__ void fine_chain(const FineArgs& a, const int c, unsig
             const double ltarget = fmax(a.tol_lin * rn, 0.5 * target);
             int k;
             if constexpr (R > 0)
-                k = pcg_regs<S, R>(a, jv, p_l, r_l, df_l, tq_l, R_, px, ltarget, lds_s, ph_s);
+                k = pcg_regs<S, R, BLOCK>(a, jv, p_l, r_l, df_l, tq_l, R_, px, ltarget, lds_s, ph_s);
             else
                 k = pcg_mem<S, LP>(a, jv, pv, p_l, d_l, R_, ltarget, lds_s, ph_s);
             __syncthreads();
@@ -578,7 +660,7 @@ __device__ inline double mass_apply_neg(const FineArgs& a, const double* __restr
 // One chain of the adjoint backward sweep: from Lambda_{c+1} down to lambda_{cm+1},
 // solving J_j lambda_j = M (lambda_{j+1}/dt + 2/(T dt) (du_j - du_{j+1})) for
 // j = (c+1)m .. cm+1 with J_j assembled at the stored forward state u_j.
-template <typename S, int R, int LP>
+template <typename S, int R, int BLOCK, int LP>
 __device__ __forceinline__ void adjoint_chain(const FineArgs& a, const AdjArgs& b, const int c,
                                               unsigned char* dyn_lds, double* lds_d, S* lds_s) {
     int ph_d = 0, ph_s = 0;
@@ -630,7 +712,7 @@ __device__ __forceinline__ void adjoint_chain(const FineArgs& a, const AdjArgs& 
         int k = 0;
         if (rn > 0.0) {
             if constexpr (R > 0)
-                k = pcg_regs<S, R>(a, jv, p_l, r_l, df_l, tq_l, rhs, px, b.tol_lin * rn, lds_s, ph_s);
+                k = pcg_regs<S, R, BLOCK>(a, jv, p_l, r_l, df_l, tq_l, rhs, px, b.tol_lin * rn, lds_s, ph_s);
             else
                 k = pcg_mem<S, LP>(a, jv, pv, p_l, d_l, rhs, b.tol_lin * rn, lds_s, ph_s);
         } else {
@@ -668,7 +750,7 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint_sweep(FineArgs a, AdjArgs b) 
     extern __shared__ unsigned char dyn_lds[];
     __shared__ double lds_d[2 * 16 * 4];
     __shared__ S lds_s[2 * 16 * 4];
-    adjoint_chain<S, R, LP>(a, b, blockIdx.x, dyn_lds, lds_d, lds_s);
+    adjoint_chain<S, R, BLOCK, LP>(a, b, blockIdx.x, dyn_lds, lds_d, lds_s);
 }
 
 template <typename S, int R, int BLOCK, int LP>
@@ -676,7 +758,7 @@ __global__ __launch_bounds__(BLOCK) void k_fine_sweep(FineArgs a) {
     extern __shared__ unsigned char dyn_lds[];
     __shared__ double lds_d[2 * 16 * 4];
     __shared__ S lds_s[2 * 16 * 4];
-    fine_chain<S, R, LP>(a, blockIdx.x, dyn_lds, lds_d, lds_s);
+    fine_chain<S, R, BLOCK, LP>(a, blockIdx.x, dyn_lds, lds_d, lds_s);
 }
 
 // Batched designs: block b runs chain work[b].y of design work[b].x, whose arguments are
@@ -688,7 +770,7 @@ __global__ __launch_bounds__(BLOCK) void k_fine_sweep_batch(const FineArgs* __re
     __shared__ double lds_d[2 * 16 * 4];
     __shared__ S lds_s[2 * 16 * 4];
     const int2 wk = work[blockIdx.x];
-    fine_chain<S, R, LP>(args[wk.x], wk.y, dyn_lds, lds_d, lds_s);
+    fine_chain<S, R, BLOCK, LP>(args[wk.x], wk.y, dyn_lds, lds_d, lds_s);
 }
 
 namespace {
