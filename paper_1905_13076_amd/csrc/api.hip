@@ -89,7 +89,7 @@ float elapsed(hipEvent_t a, hipEvent_t b) {
 }  // namespace
 
 void workspace_free(Workspace& w) {
-    void* ptrs[] = {w.fvec, w.fpcg, w.fjac, w.felem, w.fcount, w.U, w.F, w.J, w.R, w.kbar, w.kbar32,
+    void* ptrs[] = {w.fvec, w.fpcg, w.fjac, w.felem, w.jbase, w.fcount, w.U, w.F, w.J, w.R, w.kbar, w.kbar32,
                     w.nubar, w.rhat, w.cwork, w.sig, w.ccount, w.twiddle, w.partial, w.scal};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
@@ -110,7 +110,10 @@ void ensure_workspace(ppc_problem* pr, const ppc_params* p) {
     w.fvec = dalloc<double>(N * kFineVec * w.n_pad);
     w.fpcg = dalloc<double>(N * kPcgVec * w.n_pad);     // sized for FP64, also used as FP32
     w.fjac = dalloc<double>(N * w.vals_pad);
-    w.felem = dalloc<double>(N * 8 * w.ne_pad);
+    w.nl_pad = pad64(std::max(d.n_nl, 1));
+    w.felem = dalloc<double>(N * 8 * w.nl_pad);
+    w.jbase = dalloc<double>(w.vals_pad);
+    w.jbase_dt = 0.0;
     w.fcount = dalloc<int>(N * 8);
     w.U = dalloc<double>(N * d.n_free);
     w.F = dalloc<double>(N * d.n_free);

@@ -5,16 +5,20 @@
 //     R(u) = M (u - u_prev)/dt + K(u) u - i(t_j) F = 0,   t_j = T_{n-1} + j dt,
 // by damped Newton with the exact Jacobian
 //     J = M/dt + sum_e [ nu_e K0_e + (2 nu'_e / A_e) (K0_e u_e)(K0_e u_e)^T ],
-// (nu' = d nu / d|B|^2) assembled element-wise into CSR values by a deterministic gather
-// over a slot -> contribution list (no atomics), and solved by Jacobi-PCG.
+// (nu' = d nu / d|B|^2) solved by Jacobi-PCG.  Linear elements make J and R affine in u,
+// so both are split into a base matrix Jb = M/dt + sum over linear e of nu_e K0_e, built
+// once per sweep, and a Brauer part: a Newton iteration re-evaluates only the Brauer
+// elements, the value positions they reach (a deterministic gather over a position ->
+// contribution list, no atomics) and R = Jb u - M u_prev/dt + Brauer forces - i F.
 //
-// Mapping to CDNA: the chain's vectors, Jacobian values and element scratch live in HBM
-// (L2 / MALL resident for small meshes); every phase is a workgroup-wide pass with
-// coalesced row / element streams; the CSR SpMV gives kRowGroup lanes of a 64-wide
-// wave to each row so that value and column streams are read contiguously; dot
-// products are wave-shuffle trees followed by a fixed-order sum over the waves, so
-// results are bitwise reproducible.  The PCG scalar type S is double (FP64 form) or
-// float (mixed form: FP32 Jacobian and PCG, FP64 Newton residual refining it).
+// Mapping to CDNA: the chain's vectors and Jacobian values live in HBM (L2 / MALL
+// resident for small meshes), the PCG keeps p (and for meshes that fit, r and the FP32
+// Jacobi diagonal) in LDS and its rows in registers; the ELL SpMV streams values and
+// 16-bit columns with raw buffer loads (a static count in flight, out-of-range lanes
+// read zero) and gathers p from LDS.  Dot products are DPP wave sums followed by a
+// fixed-order sum over the waves, so results are bitwise reproducible.  The PCG scalar
+// type S is double (FP64 form) or float (mixed form: FP32 Jacobian and PCG, FP64 Newton
+// residual refining it).
 #include <cfloat>
 #include <cmath>
 
@@ -122,113 +126,176 @@ enum { E_F0 = 0, E_W0 = 3, E_NU = 6, E_SF = 7 };
 // Newton accepts a residual that stops halving (or a stalled line search) once it is
 // below kFloorCap * scale: it then sits at the rounding floor of its evaluation.
 constexpr double kFloorCap = 1e-9;
-enum { V_U = 0, V_UP = 1, V_R = 2, V_RT = 3, V_UPP = 4 };
+enum { V_U = 0, V_UP = 1, V_R = 2, V_RT = 3, V_UPP = 4, V_UT = 5, V_CP = 6 };
 enum { P_R = 0, P_P = 1, P_Q = 2, P_X = 3, P_D = 4 };
 enum { C_STATUS = 0, C_NEWTON = 1, C_LIN = 2, C_NEWTON_MAX = 3, C_LIN_MAX = 4, C_CAPPED = 5,
        C_FAILSTEP = 6, C_RESID = 7 };
 
-// Element pass at ut = u + lam du (du may be null): w = K0 ut, b2 = ut.w/A, nu, nu',
-// and the element force nu w_a + (M_e (ut - u_prev))_a / dt.
-template <typename D>
-__device__ inline void element_pass(const FineArgs& a, const double* __restrict__ u,
-                                    const D* __restrict__ du, double lam,
-                                    const double* __restrict__ up, double* __restrict__ el,
-                                    double inv_dt) {
-    const int ne = a.ne;
-    const long P = a.ne_pad;
-    for (int e = threadIdx.x; e < ne; e += blockDim.x) {
-        double ut[3], d[3];
+// The Jacobian and residual split into a state-independent base and a Brauer part:
+//     J(u) = Jb + sum over Brauer e [ nu_e K0_e + (2 nu'_e / A_e) w_e w_e^T ],
+//     R(u) = Jb u - M u_prev / dt + sum over Brauer e nu_e K0_e u_e - i(t) F,
+// with Jb = M/dt + sum over linear e nu_e K0_e built once per sweep (k_jbase), so a
+// Newton iteration touches only the Brauer elements and the value positions they reach.
+
+// Brauer element pass at the state ut: w = K0 ut_e, b2 = ut_e.w / A, nu, nu' and the
+// element force nu w (scratch el, planes of nl_pad).
+__device__ inline void nl_element_pass(const FineArgs& a, const double* __restrict__ ut,
+                                       double* __restrict__ el) {
+    const int nl = a.n_nl;
+    const long P = a.nl_pad;
+    for (int j = threadIdx.x; j < nl; j += blockDim.x) {
+        double x[3];
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
-            const int g = a.efree[q * ne + e];
-            double v = 0.0, vp = 0.0;
-            if (g >= 0) {
-                v = u[g];
-                if (du) v = v + lam * (double)du[g];
-                vp = up[g];
-            }
-            ut[q] = v;
-            d[q] = v - vp;
+            const int g = a.nl_efree[q * nl + j];
+            x[q] = g >= 0 ? ut[g] : 0.0;
         }
-        const double k00 = a.k0[e], k01 = a.k0[ne + e], k02 = a.k0[2 * ne + e];
-        const double k11 = a.k0[3 * ne + e], k12 = a.k0[4 * ne + e], k22 = a.k0[5 * ne + e];
-        const double w0 = k00 * ut[0] + k01 * ut[1] + k02 * ut[2];
-        const double w1 = k01 * ut[0] + k11 * ut[1] + k12 * ut[2];
-        const double w2 = k02 * ut[0] + k12 * ut[1] + k22 * ut[2];
-        const double A = a.area[e];
-        const double b2 = (ut[0] * w0 + ut[1] * w1 + ut[2] * w2) / A;
+        const double k00 = a.nl_k0[j], k01 = a.nl_k0[nl + j], k02 = a.nl_k0[2 * nl + j];
+        const double k11 = a.nl_k0[3 * nl + j], k12 = a.nl_k0[4 * nl + j], k22 = a.nl_k0[5 * nl + j];
+        const double w0 = k00 * x[0] + k01 * x[1] + k02 * x[2];
+        const double w1 = k01 * x[0] + k11 * x[1] + k12 * x[2];
+        const double w2 = k02 * x[0] + k12 * x[1] + k22 * x[2];
+        const double A = a.nl_area[j];
+        const double b2 = (x[0] * w0 + x[1] * w1 + x[2] * w2) / A;
         double nu, dnu;
-        reluct(a.lawtab, a.mat[e], b2, nu, dnu);
-        const double cm = a.sigma[e] * A / 12.0;
-        const double ds = d[0] + d[1] + d[2];
-        el[(E_F0 + 0) * P + e] = nu * w0 + cm * (d[0] + ds) * inv_dt;
-        el[(E_F0 + 1) * P + e] = nu * w1 + cm * (d[1] + ds) * inv_dt;
-        el[(E_F0 + 2) * P + e] = nu * w2 + cm * (d[2] + ds) * inv_dt;
-        el[(E_W0 + 0) * P + e] = w0;
-        el[(E_W0 + 1) * P + e] = w1;
-        el[(E_W0 + 2) * P + e] = w2;
-        el[E_NU * P + e] = nu;
-        el[E_SF * P + e] = 2.0 * dnu / A;
+        reluct(a.lawtab, a.nl_mat[j], b2, nu, dnu);
+        el[(E_F0 + 0) * P + j] = nu * w0;
+        el[(E_F0 + 1) * P + j] = nu * w1;
+        el[(E_F0 + 2) * P + j] = nu * w2;
+        el[(E_W0 + 0) * P + j] = w0;
+        el[(E_W0 + 1) * P + j] = w1;
+        el[(E_W0 + 2) * P + j] = w2;
+        el[E_NU * P + j] = nu;
+        el[E_SF * P + j] = 2.0 * dnu / A;
     }
 }
 
-// Node pass: R_i = sum of incident element forces - i(t) F_i; returns partial ||R||^2.
-__device__ inline double node_pass(const FineArgs& a, const double* __restrict__ el, double cur,
-                                   double* __restrict__ R) {
-    const long P = a.ne_pad;
+// Brauer element forces of row i (node order)
+__device__ inline double nl_force(const FineArgs& a, const double* __restrict__ el, int i) {
+    const long P = a.nl_pad;
+    double acc = 0.0;
+    for (int k = a.nlf_ptr[i]; k < a.nlf_ptr[i + 1]; ++k) {
+        const int code = a.nlf_src[k];
+        const int j = code / 3, q = code - 3 * j;
+        acc += el[(E_F0 + q) * P + j];
+    }
+    return acc;
+}
+
+// R = Jb ut - cp + (Brauer forces) - cur F over all rows, cp = M u_prev / dt; returns the
+// partial ||R||^2 of this thread.  ELL rows load all their slots before the gathers; the
+// tail rows are summed by one wave each.
+__device__ inline double resid_rows(const FineArgs& a, const double* __restrict__ ut,
+                                    const double* __restrict__ cp, const double* __restrict__ el,
+                                    double cur, double* __restrict__ R) {
+    const long NP = a.ell_pad;
+    const int n = a.n, W = a.W;
     double part = 0.0;
-    for (int i = threadIdx.x; i < a.n; i += blockDim.x) {
-        double acc = 0.0;
-        for (int k = a.node_ptr[i]; k < a.node_ptr[i + 1]; ++k) {
-            const int code = a.node_src[k];
-            const int e = code / 3, q = code - 3 * e;
-            acc += el[(E_F0 + q) * P + e];
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        int col[kEllMaxWidth];
+        double val[kEllMaxWidth];
+#pragma unroll
+        for (int w = 0; w < kEllMaxWidth; ++w) {
+            col[w] = w < W ? a.ecol[w * NP + i] : 0;
+            val[w] = w < W ? a.jbase[w * NP + i] : 0.0;
         }
-        acc = acc - cur * a.fload[i];
+        if (col[0] < 0) continue;                 // tail row
+        double acc = 0.0;
+#pragma unroll
+        for (int w = 0; w < kEllMaxWidth; ++w)
+            if (w < W) acc += val[w] * ut[col[w]];
+        acc = acc - cp[i] + nl_force(a, el, i) - cur * a.fload[i];
         R[i] = acc;
         part += acc * acc;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const long base = (long)W * NP;
+    for (int t = wave; t < a.ntail; t += nw) {
+        double acc = 0.0;
+        const int j1 = a.tail_ptr[t + 1];
+        for (int j = a.tail_ptr[t] + lane; j < j1; j += 64) acc += a.jbase[base + j] * ut[a.tail_col[j]];
+        acc = wave_sum(acc);
+        if (lane == 0) {
+            const int i = a.tail_row[t];
+            acc = acc - cp[i] + nl_force(a, el, i) - cur * a.fload[i];
+            R[i] = acc;
+            part += acc * acc;
+        }
     }
     return part;
 }
 
-// Jacobian values in ELL order: position v takes CSR slot vslot[v] (padding: 0), the
-// slot summing M_s/dt and every element contribution nu K0_ab + (2nu'/A) w_a w_b.
+// Jacobian values of the Brauer-touched positions: Jb plus, per contribution of slot
+// order, nu K0_ab + (2nu'/A) w_a w_b; every other position keeps its base value.
 template <typename S>
-__device__ inline void assemble(const FineArgs& a, const double* __restrict__ el, double inv_dt,
-                                S* __restrict__ jv) {
-    const long P = a.ne_pad;
-    const int ne = a.ne;
-    for (int v = threadIdx.x; v < a.nvals; v += blockDim.x) {
-        const int s = a.vslot[v];
-        double acc = 0.0;
-        if (s >= 0) {
-            acc = a.mval[s] * inv_dt;
-            for (int k = a.slot_ptr[s]; k < a.slot_ptr[s + 1]; ++k) {
-                const int code = a.slot_src[k];
-                const int e = code / 9, ab = code - 9 * e;
-                const int qa = ab / 3, qb = ab - 3 * qa;
-                const int lo = qa < qb ? qa : qb, hi = qa < qb ? qb : qa;
-                const int kidx = lo == 0 ? hi : (lo == 1 ? 2 + hi : 5);
-                acc += el[E_NU * P + e] * a.k0[kidx * ne + e] +
-                       el[E_SF * P + e] * el[(E_W0 + qa) * P + e] * el[(E_W0 + qb) * P + e];
-            }
+__device__ inline void assemble_nl(const FineArgs& a, const double* __restrict__ el, S* __restrict__ jv) {
+    const long P = a.nl_pad;
+    const int nl = a.n_nl;
+    for (int t = threadIdx.x; t < a.n_nlv; t += blockDim.x) {
+        const int v = a.nlv_val[t];
+        double acc = a.jbase[v];
+        for (int k = a.nlv_ptr[t]; k < a.nlv_ptr[t + 1]; ++k) {
+            const int code = a.nlv_src[k];
+            const int j = code / 9, ab = code - 9 * j;
+            const int qa = ab / 3, qb = ab - 3 * qa;
+            const int lo = qa < qb ? qa : qb, hi = qa < qb ? qb : qa;
+            const int kidx = lo == 0 ? hi : (lo == 1 ? 2 + hi : 5);
+            acc += el[E_NU * P + j] * a.nl_k0[kidx * nl + j] +
+                   el[E_SF * P + j] * el[(E_W0 + qa) * P + j] * el[(E_W0 + qb) * P + j];
         }
         jv[v] = (S)acc;
     }
 }
 
-// Raw buffer resource over [base, base + bytes) (gfx9 word 3: 32-bit untyped data);
-// loads past the end return 0 instead of faulting.
+// every value position takes its base value (start of a chain)
+template <typename S>
+__device__ inline void init_jac(const FineArgs& a, S* __restrict__ jv) {
+    for (int v = threadIdx.x; v < a.nvals; v += blockDim.x) jv[v] = (S)a.jbase[v];
+}
+
+// cp = M u_prev / dt (CSR, kRowGroup lanes per row, once per time step); returns the
+// partial ||cp||^2.
+__device__ inline double mass_prev(const FineArgs& a, const double* __restrict__ up, double inv_dt,
+                                   double* __restrict__ cp) {
+    constexpr int G = kRowGroup;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int sub = lane % G, grp = lane / G;
+    constexpr int RPW = 64 / G;
+    double part = 0.0;
+    for (int base = wave * RPW; base < a.n; base += nw * RPW) {
+        const int i = base + grp;
+        double acc = 0.0;
+        if (i < a.n) {
+            const int k1 = a.rowptr[i + 1];
+            for (int k = a.rowptr[i] + sub; k < k1; k += G) acc += a.mval[k] * up[a.colidx[k]];
+        }
+#pragma unroll
+        for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+        if (i < a.n && sub == 0) {
+            const double v = acc * inv_dt;
+            cp[i] = v;
+            part += v * v;
+        }
+    }
+    return part;
+}
+
+// Raw buffer resource over [base, base + bytes) (gfx9 word 3: 32-bit untyped data).
+// The hardware range check covers the lane offset (voffset) only, so callers put the
+// whole byte offset there: a load at an offset >= bytes returns 0 without a memory
+// access, and kBufferNone marks a lane that loads nothing.
 __device__ inline __amdgpu_buffer_rsrc_t buffer_rsrc(const void* base, unsigned bytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)bytes, 0x00020000);
 }
 
+constexpr unsigned kBufferNone = 0x80000000u;
+
 template <typename S>
-__device__ inline S buffer_load(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+__device__ inline S buffer_load(__amdgpu_buffer_rsrc_t r, unsigned voff) {
     if constexpr (sizeof(S) == 8)
-        return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+        return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b64(r, voff, 0, 0));
     else
-        return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+        return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b32(r, voff, 0, 0));
 }
 
 // Row-sum of one tail (long) row by a whole wave; returns the sum on every lane.
@@ -258,7 +325,16 @@ __device__ int pcg_regs(const FineArgs& a, const S* __restrict__ jv, S* __restri
     S x[R], q[R];
     unsigned tailmask = 0;
     const __amdgpu_buffer_rsrc_t rv_j = buffer_rsrc(jv, (unsigned)(W * NP * sizeof(S)));
-    const __amdgpu_buffer_rsrc_t rv_c = buffer_rsrc(a.ecol, (unsigned)(W * NP * 4));
+    const __amdgpu_buffer_rsrc_t rv_c = buffer_rsrc(a.ecol16, (unsigned)(W * NP * 2));
+    // One tail row of at most B entries (the usual case): every thread takes one of its
+    // entries and the first block reduction of an iteration carries the row's product
+    // with p.q, so no wave runs a serial row sum.  Otherwise one wave per tail row.
+    const bool tail1 = a.ntail == 1 && a.tail_ptr[1] - a.tail_ptr[0] <= B;
+    const int t_beg = tail1 ? a.tail_ptr[0] : 0;
+    const int t_len = tail1 ? a.tail_ptr[1] - t_beg : 0;
+    const int t_row = tail1 ? a.tail_row[0] : 0;
+    const __amdgpu_buffer_rsrc_t rv_tv = buffer_rsrc(jv + W * NP + t_beg, (unsigned)(t_len * sizeof(S)));
+    const __amdgpu_buffer_rsrc_t rv_tc = buffer_rsrc(a.tail_col + t_beg, (unsigned)(t_len * 4));
     S loc[2] = {0, 0};
 #pragma unroll
     for (int k = 0; k < R; ++k) {
@@ -280,40 +356,60 @@ __device__ int pcg_regs(const FineArgs& a, const S* __restrict__ jv, S* __restri
     double rr = (double)loc[1];
     int it = 0;
     while (rr > tgt * tgt && it < a.max_lin) {
-        S dot[1] = {0};
-        // slot-major: each slot w issues the value and column loads of all R rows of the
-        // thread at once (wave-uniform bases, one lane offset), so R loads are in flight
-        // per round trip; every row still sums its slots in order 0..W-1.
-        // The loads are unconditional: rows past the ELL arrays read 0, tail rows hold
-        // zero values (their column -1 is clamped), and rows >= n are never used.
+        // this thread's tail entry: loads issued first, used after the ELL rounds
+        const S tv = buffer_load<S>(rv_tv, tid < t_len ? tid * (unsigned)sizeof(S) : kBufferNone);
+        const unsigned tc = (unsigned)__builtin_amdgcn_raw_buffer_load_b32(rv_tc, tid < t_len ? tid * 4u : kBufferNone, 0, 0);
+        // ELL rows, slot-major: U slots of all R row groups per round (U R = 8 loads of
+        // each stream in flight), all LDS gathers of a round issued before its FMAs.
+        // Every load is issued: rows >= n load nothing and slots >= W fall past the ELL
+        // arrays, both reading value 0 and column 0; tail rows hold zero values and
+        // column 0.  Every row adds its slots in order 0..W-1, then exact zeros.
+        constexpr int U = R >= 8 ? 1 : 8 / R;
 #pragma unroll
         for (int k = 0; k < R; ++k) q[k] = 0;
-        for (int w = 0; w < W; ++w) {
-            S v[R];
-            int col[R];
+        for (int w0 = 0; w0 < W; w0 += U) {
+            S v[U][R], pg[U][R];
+            unsigned col[U][R];
 #pragma unroll
-            for (int k = 0; k < R; ++k) {
-                const unsigned row0 = (unsigned)(w * NP + k * B);
-                v[k] = buffer_load<S>(rv_j, tid * sizeof(S), row0 * sizeof(S));
-                col[k] = buffer_load<int>(rv_c, tid * 4u, row0 * 4u);
-            }
-            __builtin_amdgcn_sched_barrier(0);   // keep the 2R loads of slot w in flight together
+            for (int u = 0; u < U; ++u)
 #pragma unroll
-            for (int k = 0; k < R; ++k) q[k] += v[k] * p_l[col[k] < 0 ? 0 : col[k]];
+                for (int k = 0; k < R; ++k) {
+                    const int i = tid + k * B;
+                    const unsigned e = (unsigned)((w0 + u) * NP + i);
+                    v[u][k] = buffer_load<S>(rv_j, i < n ? e * (unsigned)sizeof(S) : kBufferNone);
+                    col[u][k] = __builtin_amdgcn_raw_buffer_load_b16(rv_c, i < n ? e * 2u : kBufferNone, 0, 0);
+                }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int k = 0; k < R; ++k) pg[u][k] = p_l[col[u][k]];
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int k = 0; k < R; ++k) q[k] += v[u][k] * pg[u][k];
         }
+        S dot[2] = {0, 0};
 #pragma unroll
         for (int k = 0; k < R; ++k) {
             const int i = tid + k * B;
             if (i < n && !((tailmask >> k) & 1u)) dot[0] += p_l[i] * q[k];
         }
-        for (int t = wave; t < a.ntail; t += nw) {
-            const S acc = tail_row_sum<S>(a, jv, p_l, t, lane);
-            if (lane == 0) {
-                tq_l[t] = acc;
-                dot[0] += p_l[a.tail_row[t]] * acc;
+        if (tail1) {
+            const S qt = tv * p_l[tc];
+            dot[1] = qt;
+            dot[0] += p_l[t_row] * qt;
+        } else {
+            for (int t = wave; t < a.ntail; t += nw) {
+                const S acc = tail_row_sum<S>(a, jv, p_l, t, lane);
+                if (lane == 0) {
+                    tq_l[t] = acc;
+                    dot[0] += p_l[a.tail_row[t]] * acc;
+                }
             }
         }
-        block_sum<S, 1, B / 64>(dot, lds_s, ph);
+        block_sum<S, 2, B / 64>(dot, lds_s, ph);
         const S pq = dot[0];
         if (!(pq > (S)0)) break;                 // loss of positivity: Newton decides
         const S alpha = rz / pq;
@@ -322,7 +418,7 @@ __device__ int pcg_regs(const FineArgs& a, const S* __restrict__ jv, S* __restri
         for (int k = 0; k < R; ++k) {
             const int i = tid + k * B;
             if (i < n) {
-                if ((tailmask >> k) & 1u) q[k] = tq_l[a.ecol[NP + i]];
+                if ((tailmask >> k) & 1u) q[k] = tail1 ? dot[1] : tq_l[a.ecol[NP + i]];
                 x[k] += alpha * p_l[i];
                 const S rv = r_l[i] - alpha * q[k];
                 r_l[i] = rv;
@@ -437,27 +533,6 @@ __device__ int pcg_mem(const FineArgs& a, const S* __restrict__ jv, S* __restric
     return it;
 }
 
-// ||M x||^2 partial, CSR with kRowGroup lanes per row (once per time step)
-__device__ inline double mass_norm2(const FineArgs& a, const double* __restrict__ x) {
-    constexpr int G = kRowGroup;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    const int sub = lane % G, grp = lane / G;
-    constexpr int RPW = 64 / G;
-    double part = 0.0;
-    for (int base = wave * RPW; base < a.n; base += nw * RPW) {
-        const int i = base + grp;
-        double acc = 0.0;
-        if (i < a.n) {
-            const int k1 = a.rowptr[i + 1];
-            for (int k = a.rowptr[i] + sub; k < k1; k += G) acc += a.mval[k] * x[a.colidx[k]];
-        }
-#pragma unroll
-        for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-        if (i < a.n && sub == 0) part += acc * acc;
-    }
-    return part;
-}
-
 // R > 0: PCG rows in registers, p / diagonal / tail sums in dynamic LDS;
 // R == 0: PCG vectors in memory, with p (LP >= 1) and the diagonal (LP == 2) in LDS.
 template <typename S, int R, int BLOCK, int LP>
@@ -472,10 +547,12 @@ __device__ __forceinline__ void fine_chain(const FineArgs& a, const int c, unsig
     double* R_ = vec + V_R * NP;
     double* Rt = vec + V_RT * NP;
     double* upp = vec + V_UPP * NP;
+    double* ut = vec + V_UT * NP;             // trial state of the line search
+    double* cp = vec + V_CP * NP;             // M u_prev / dt
     S* pv = reinterpret_cast<S*>(a.pcg) + (long)c * kPcgVec * NP;
     S* px = pv + P_X * NP;
     S* jv = reinterpret_cast<S*>(a.jac) + (long)c * a.vals_pad;
-    double* el = a.elem + (long)c * 8 * a.ne_pad;
+    double* el = a.elem + (long)c * 8 * a.nl_pad;
     S* p_l = reinterpret_cast<S*>(dyn_lds);
     S* d_l = p_l + NP;                        // memory path: inverse diagonal (LP == 2)
     S* r_l = p_l + NP;                        // register path: r
@@ -489,6 +566,7 @@ __device__ __forceinline__ void fine_chain(const FineArgs& a, const int c, unsig
         u[i] = U0[i];
         if (Tc) Tc[i] = U0[i];
     }
+    init_jac<S>(a, jv);
     __syncthreads();
 
     const double t0 = (double)c * (a.T / a.N);
@@ -505,38 +583,39 @@ __device__ __forceinline__ void fine_chain(const FineArgs& a, const int c, unsig
         }
         __syncthreads();
         const double cur = current(t, a.f0, a.n_h, a.wavtab);
-        double v1[1] = {mass_norm2(a, up)};
+        double v1[1] = {mass_prev(a, up, inv_dt, cp)};
         block_sum<double, 1>(v1, lds_d, ph_d);
-        const double scale = fabs(cur) * a.fnorm + sqrt(v1[0]) / a.dt;
+        const double scale = fabs(cur) * a.fnorm + sqrt(v1[0]);
         const double target = a.tol_newton * scale;
 
-        element_pass<double>(a, u, nullptr, 0.0, up, el, inv_dt);
+        nl_element_pass(a, u, el);
         ++resid_evals;
         __syncthreads();
-        double v2[1] = {node_pass(a, el, cur, R_)};
+        double v2[1] = {resid_rows(a, u, cp, el, cur, R_)};
         block_sum<double, 1>(v2, lds_d, ph_d);
         double rn = sqrt(v2[0]);
         if (!isfinite(rn)) { status = PPC_ERR_NONFINITE; fail_step = j; break; }
         // Newton starts from the linear extrapolation 2 u_{j-1} - u_{j-2} when that has the
         // smaller residual (it changes only the iteration count, not the step's solution)
         if (j >= 2 && a.predictor && rn > target) {
-            for (int i = threadIdx.x; i < n; i += blockDim.x) u[i] = 2.0 * up[i] - upp[i];
+            for (int i = threadIdx.x; i < n; i += blockDim.x) ut[i] = 2.0 * up[i] - upp[i];
             __syncthreads();
-            element_pass<double>(a, u, nullptr, 0.0, up, el, inv_dt);
+            nl_element_pass(a, ut, el);
             ++resid_evals;
             __syncthreads();
-            double v4[1] = {node_pass(a, el, cur, Rt)};
+            double v4[1] = {resid_rows(a, ut, cp, el, cur, Rt)};
             block_sum<double, 1>(v4, lds_d, ph_d);
             const double rp = sqrt(v4[0]);
             if (rp < rn) {
                 double* tmp = R_;
                 R_ = Rt;
                 Rt = tmp;
+                tmp = u;
+                u = ut;
+                ut = tmp;
                 rn = rp;
             } else {
-                for (int i = threadIdx.x; i < n; i += blockDim.x) u[i] = up[i];
-                __syncthreads();
-                element_pass<double>(a, u, nullptr, 0.0, up, el, inv_dt);
+                nl_element_pass(a, u, el);
                 ++resid_evals;
                 __syncthreads();
             }
@@ -546,7 +625,7 @@ __device__ __forceinline__ void fine_chain(const FineArgs& a, const int c, unsig
         for (;; ++it) {
             if (rn <= target) break;
             if (it == a.max_newton) { status = PPC_ERR_NEWTON; fail_step = j; break; }
-            assemble<S>(a, el, inv_dt, jv);
+            assemble_nl<S>(a, el, jv);
             __syncthreads();
             if constexpr (R > 0) {
                 for (int i = threadIdx.x; i < n; i += blockDim.x) df_l[i] = (float)(1.0 / (double)jv[a.dpos[i]]);
@@ -582,10 +661,12 @@ __device__ __forceinline__ void fine_chain(const FineArgs& a, const int c, unsig
             double rt = 0.0;
             bool accepted = false, stalled = false;
             while (true) {
-                element_pass<S>(a, u, px, lam, up, el, inv_dt);
+                for (int i = threadIdx.x; i < n; i += blockDim.x) ut[i] = u[i] + lam * (double)px[i];
+                __syncthreads();
+                nl_element_pass(a, ut, el);
                 ++resid_evals;
                 __syncthreads();
-                double v3[1] = {node_pass(a, el, cur, Rt)};
+                double v3[1] = {resid_rows(a, ut, cp, el, cur, Rt)};
                 block_sum<double, 1>(v3, lds_d, ph_d);
                 rt = sqrt(v3[0]);
                 if (rt <= (1.0 - 1e-4 * lam) * rn) { accepted = true; break; }
@@ -599,15 +680,16 @@ __device__ __forceinline__ void fine_chain(const FineArgs& a, const int c, unsig
                 break;
             }
             if (accepted) {
-                for (int i = threadIdx.x; i < n; i += blockDim.x) u[i] = u[i] + lam * (double)px[i];
-                double* tmp = R_;
+                double* tmp = u;
+                u = ut;
+                ut = tmp;
+                tmp = R_;
                 R_ = Rt;
                 Rt = tmp;
                 // a step that fails to halve a residual below the floor cap: the residual
                 // sits at the rounding floor of its own evaluation
                 const bool floor = rt > 0.5 * rn && rt <= kFloorCap * scale;
                 rn = rt;
-                __syncthreads();
                 if (floor) { ++it; break; }
             }
         }
@@ -673,7 +755,7 @@ __device__ __forceinline__ void adjoint_chain(const FineArgs& a, const AdjArgs& 
     S* pv = reinterpret_cast<S*>(a.pcg) + (long)c * kPcgVec * NP;
     S* px = pv + P_X * NP;
     S* jv = reinterpret_cast<S*>(a.jac) + (long)c * a.vals_pad;
-    double* el = a.elem + (long)c * 8 * a.ne_pad;
+    double* el = a.elem + (long)c * 8 * a.nl_pad;
     S* p_l = reinterpret_cast<S*>(dyn_lds);
     S* d_l = p_l + NP;
     S* r_l = p_l + NP;
@@ -684,6 +766,7 @@ __device__ __forceinline__ void adjoint_chain(const FineArgs& a, const AdjArgs& 
     const double* T1 = b.traj + (long)((c + 1) % N) * (m + 1) * n;
     const double* Lin = b.lam_in + (long)((c + 1) % N) * n;
     for (int i = threadIdx.x; i < n; i += blockDim.x) lam[i] = Lin[i];
+    init_jac<S>(a, jv);
     __syncthreads();
     const double inv_dt = 1.0 / a.dt;
     const double gcoef = 2.0 / (b.T * a.dt);
@@ -699,9 +782,9 @@ __device__ __forceinline__ void adjoint_chain(const FineArgs& a, const AdjArgs& 
         double v[1] = {mass_apply_neg(a, y, rhs)};
         block_sum<double, 1>(v, lds_d, ph_d);
         const double rn = sqrt(v[0]);
-        element_pass<double>(a, uj, nullptr, 0.0, ujm, el, inv_dt);
+        nl_element_pass(a, uj, el);
         __syncthreads();
-        assemble<S>(a, el, inv_dt, jv);
+        assemble_nl<S>(a, el, jv);
         __syncthreads();
         if constexpr (R > 0) {
             for (int i = threadIdx.x; i < n; i += blockDim.x) df_l[i] = (float)(1.0 / (double)jv[a.dpos[i]]);
@@ -819,13 +902,50 @@ void launch_typed(const FineArgs& a, int N, const FineShape& sh, hipStream_t s) 
 
 }  // namespace
 
+// Base Jacobian Jb of a sweep: value position v takes M_s / dt of its CSR slot s plus
+// nu K0_ab of every linear element contribution of s (slot order); padding takes 0.
+__global__ void k_jbase(int nvals, int ne, const int* __restrict__ vslot, const int* __restrict__ slot_ptr,
+                        const int* __restrict__ slot_src, const int* __restrict__ mat,
+                        const double* __restrict__ lawtab, const double* __restrict__ k0,
+                        const double* __restrict__ mval, double inv_dt, double* __restrict__ jb) {
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < nvals; v += gridDim.x * blockDim.x) {
+        const int s = vslot[v];
+        double acc = 0.0;
+        if (s >= 0) {
+            acc = mval[s] * inv_dt;
+            for (int k = slot_ptr[s]; k < slot_ptr[s + 1]; ++k) {
+                const int code = slot_src[k];
+                const int e = code / 9, ab = code - 9 * e;
+                const double* L = lawtab + 5 * mat[e];
+                if (L[0] != 0.0) continue;        // Brauer: added per Newton iteration
+                const int qa = ab / 3, qb = ab - 3 * qa;
+                const int lo = qa < qb ? qa : qb, hi = qa < qb ? qb : qa;
+                const int kidx = lo == 0 ? hi : (lo == 1 ? 2 + hi : 5);
+                acc += L[1] * k0[(long)kidx * ne + e];
+            }
+        }
+        jb[v] = acc;
+    }
+}
+
+// (Re)build the base Jacobian when the step size changed since the last build.
+void ensure_jbase(ppc_problem* pr, const ppc_params* p, hipStream_t s) {
+    Workspace& w = pr->ws;
+    const DeviceMesh& d = pr->mesh;
+    const double dt = p->T / (double)(p->N * p->m);
+    if (w.jbase_dt == dt) return;
+    const int nb = std::max(1, std::min((d.n_vals + 255) / 256, 4096));
+    hipLaunchKernelGGL(k_jbase, dim3(nb), dim3(256), 0, s, d.n_vals, d.n_tri, d.vslot, d.slot_ptr, d.slot_src,
+                       d.mat, pr->lawtab, d.k0, d.mval, 1.0 / dt, w.jbase);
+    PPC_HIP(hipGetLastError());
+    w.jbase_dt = dt;
+}
+
 FineArgs make_fine_args(ppc_problem* pr, const ppc_params* p, const double* U, double* F) {
     const DeviceMesh& d = pr->mesh;
     Workspace& w = pr->ws;
     FineArgs a{};
     a.n = d.n_free;
-    a.ne = d.n_tri;
-    a.nnz = d.nnz;
     a.N = p->N;
     a.m = p->m;
     a.T = p->T;
@@ -837,16 +957,6 @@ FineArgs make_fine_args(ppc_problem* pr, const ppc_params* p, const double* U, d
     a.max_lin = p->max_lin;
     a.rowptr = d.rowptr;
     a.colidx = d.colidx;
-    a.diag = d.diag;
-    a.slot_ptr = d.slot_ptr;
-    a.slot_src = d.slot_src;
-    a.node_ptr = d.node_ptr;
-    a.node_src = d.node_src;
-    a.efree = d.efree;
-    a.mat = d.mat;
-    a.area = d.area;
-    a.k0 = d.k0;
-    a.sigma = d.sigma;
     a.mval = d.mval;
     a.fload = d.fload;
     a.lawtab = pr->lawtab;
@@ -859,16 +969,28 @@ FineArgs make_fine_args(ppc_problem* pr, const ppc_params* p, const double* U, d
     a.pcg = w.fpcg;
     a.jac = w.fjac;
     a.elem = w.felem;
+    a.nl_pad = (long)w.nl_pad;
+    a.jbase = w.jbase;
+    a.n_nl = d.n_nl;
+    a.n_nlv = d.n_nlv;
+    a.nl_efree = d.nl_efree;
+    a.nl_mat = d.nl_mat;
+    a.nl_area = d.nl_area;
+    a.nl_k0 = d.nl_k0;
+    a.nlv_val = d.nlv_val;
+    a.nlv_ptr = d.nlv_ptr;
+    a.nlv_src = d.nlv_src;
+    a.nlf_ptr = d.nlf_ptr;
+    a.nlf_src = d.nlf_src;
     a.count = w.fcount;
     a.n_pad = (long)w.n_pad;
     a.vals_pad = (long)w.vals_pad;
-    a.ne_pad = (long)w.ne_pad;
     a.W = d.ell_w;
     a.ntail = d.n_tail;
     a.nvals = d.n_vals;
     a.ell_pad = (long)d.ell_pad;
     a.ecol = d.ecol;
-    a.vslot = d.vslot;
+    a.ecol16 = d.ecol16;
     a.dpos = d.dpos;
     a.tail_row = d.tail_row;
     a.tail_ptr = d.tail_ptr;
@@ -880,11 +1002,14 @@ FineArgs make_fine_args(ppc_problem* pr, const ppc_params* p, const double* U, d
 
 FineShape fine_shape(const ppc_problem* pr, const ppc_params* p) {
     const size_t elem = p->precision == 0 ? sizeof(double) : sizeof(float);
-    return pick_shape(pr->mesh.n_free, pr->ws.n_pad, pr->mesh.n_tail, elem, p->block);
+    // the register-row SpMV reads 16-bit columns (built for n < 65536; R B <= 8192 rows)
+    const int block = pr->mesh.ecol16 ? p->block : kFineBlock;
+    return pick_shape(pr->mesh.n_free, pr->ws.n_pad, pr->mesh.n_tail, elem, block);
 }
 
 void launch_fine_sweep(ppc_problem* pr, const ppc_params* p, const double* U, double* F,
                        hipStream_t s) {
+    ensure_jbase(pr, p, s);
     const FineArgs a = make_fine_args(pr, p, U, F);
     const FineShape sh = fine_shape(pr, p);
     if (p->precision == 0)
@@ -896,6 +1021,7 @@ void launch_fine_sweep(ppc_problem* pr, const ppc_params* p, const double* U, do
 
 void launch_fine_sweep_traj(ppc_problem* pr, const ppc_params* p, const double* U, double* F,
                             double* traj, hipStream_t s) {
+    ensure_jbase(pr, p, s);
     FineArgs a = make_fine_args(pr, p, U, F);
     a.traj = traj;
     const FineShape sh = fine_shape(pr, p);
@@ -923,6 +1049,7 @@ void launch_adj_shape(const FineArgs& a, const AdjArgs& b, size_t lds, hipStream
 
 // The adjoint solves are FP64 whatever the forward precision.
 void launch_adjoint_sweep(ppc_problem* pr, const ppc_params* p, const AdjArgs& b, hipStream_t s) {
+    ensure_jbase(pr, p, s);
     const FineArgs a = make_fine_args(pr, p, nullptr, nullptr);
     const FineShape sh = pick_shape(pr->mesh.n_free, pr->ws.n_pad, pr->mesh.n_tail, sizeof(double), p->block);
     if (sh.R == 1) launch_adj_shape<1, 0>(a, b, sh.lds, s);
@@ -980,6 +1107,7 @@ void fine_batch_prepare(FineBatch& b, const std::vector<ppc_problem*>& parts, co
     std::vector<FineArgs> host(D);
     b.shapes.resize(D);
     for (int d = 0; d < D; ++d) {
+        ensure_jbase(parts[d], p, s);
         host[d] = make_fine_args(parts[d], p, parts[d]->ws.U, parts[d]->ws.F);
         b.shapes[d] = fine_shape(parts[d], p);
         b.sizes.push_back(parts[d]->mesh.n_free);

@@ -86,6 +86,7 @@ struct DeviceMesh {
     int tail_nnz = 0;
     int n_vals = 0;            // value positions: ell_w * n_pad + tail_nnz
     int* ecol = nullptr;       // [ell_w][n_pad]; tail rows: ecol[0][i] = -1, ecol[1][i] = tail index
+    unsigned short* ecol16 = nullptr;   // same columns as 16-bit indices (n < 65536), tail rows 0
     int* vslot = nullptr;      // [n_vals] CSR slot of each value position (-1: padding)
     int* dpos = nullptr;       // [n_free] value position of the diagonal
     int* tail_row = nullptr;   // [n_tail]
@@ -94,6 +95,21 @@ struct DeviceMesh {
     size_t ell_pad = 0;        // n_pad used by the ELL arrays
     bool nonlinear = false;    // any element with a Brauer law
     int n_contrib = 0;
+    // Brauer (nonlinear) elements in a compact numbering j, and the ELL value positions
+    // and rows that their Jacobian and force contributions reach.  Everything else in
+    // the fine-sweep Jacobian and residual is affine in the state (the base matrix).
+    int n_nl = 0;              // Brauer elements
+    int* nl_elem = nullptr;    // [n_nl] element of each j
+    int* nl_efree = nullptr;   // [3][n_nl] free index of each vertex, -1 on Dirichlet
+    int* nl_mat = nullptr;     // [n_nl]
+    double* nl_area = nullptr; // [n_nl]
+    double* nl_k0 = nullptr;   // [6][n_nl]
+    int n_nlv = 0;             // ELL value positions with Brauer contributions
+    int* nlv_val = nullptr;    // [n_nlv] value position
+    int* nlv_ptr = nullptr;    // [n_nlv + 1]
+    int* nlv_src = nullptr;    // codes j*9 + a*3 + b
+    int* nlf_ptr = nullptr;    // [n_free + 1] per row: incident Brauer elements
+    int* nlf_src = nullptr;    // codes j*3 + a
 };
 
 void mesh_free(DeviceMesh& d);
@@ -104,7 +120,9 @@ struct Workspace {
     double* fvec = nullptr;    // [N][kFineVec][n_pad] FP64 Newton vectors
     void* fpcg = nullptr;      // [N][kPcgVec][n_pad] PCG vectors (FP64 or FP32)
     void* fjac = nullptr;      // [N][nnz_pad] Jacobian values
-    double* felem = nullptr;   // [N][8][ne_pad] element scratch
+    double* felem = nullptr;   // [N][8][nl_pad] Brauer element scratch
+    double* jbase = nullptr;   // [vals_pad] base Jacobian M/dt + sum over linear elements
+    double jbase_dt = 0.0;     // dt the base Jacobian was built for (0: none)
     int* fcount = nullptr;     // [N][8] counters per chain
     // PP-PC state (free layout [N][n_free])
     double* U = nullptr;
@@ -123,7 +141,7 @@ struct Workspace {
     double* partial = nullptr; // reduction partials
     double* scal = nullptr;    // small scalars
     double* host_scal = nullptr; // pinned host mirror
-    size_t n_pad = 0, nnz_pad = 0, ne_pad = 0, vals_pad = 0;
+    size_t n_pad = 0, nnz_pad = 0, ne_pad = 0, vals_pad = 0, nl_pad = 0;
 };
 
 void workspace_free(Workspace& w);
@@ -157,22 +175,12 @@ namespace ppc {
 
 // Arguments of one design's fine sweep (device pointers and sizes).
 struct FineArgs {
-    int n, ne, nnz, N, m;
+    int n, N, m;
     double T, dt, fnorm;
     double tol_newton, tol_lin;
     int max_newton, max_lin;
     const int* rowptr;
     const int* colidx;
-    const int* diag;
-    const int* slot_ptr;
-    const int* slot_src;
-    const int* node_ptr;
-    const int* node_src;
-    const int* efree;
-    const int* mat;
-    const double* area;
-    const double* k0;
-    const double* sigma;
     const double* mval;
     const double* fload;
     const double* lawtab;   // [n_mat][5]: law, nu, k1, k2, k3
@@ -184,16 +192,28 @@ struct FineArgs {
     double* vec;            // [N][kFineVec][n_pad]
     void* pcg;              // [N][kPcgVec][n_pad] of S
     void* jac;              // [N][nnz_pad] of S
-    double* elem;           // [N][8][ne_pad]
+    double* elem;           // [N][8][nl_pad] Brauer element scratch
     int* count;             // [N][8]
-    long n_pad, vals_pad, ne_pad;
+    long n_pad, vals_pad, nl_pad;
+    // state-independent base Jacobian and the Brauer part
+    const double* jbase;    // [nvals]
+    int n_nl, n_nlv;
+    const int* nl_efree;
+    const int* nl_mat;
+    const double* nl_area;
+    const double* nl_k0;
+    const int* nlv_val;
+    const int* nlv_ptr;
+    const int* nlv_src;
+    const int* nlf_ptr;
+    const int* nlf_src;
     // ELL pattern of the fine-sweep SpMV
     int W, ntail, nvals;
     int predictor;
     double* traj;            // [N][m+1][n] fine trajectory of each chain, or null
     long ell_pad;
     const int* ecol;
-    const int* vslot;
+    const unsigned short* ecol16;
     const int* dpos;
     const int* tail_row;
     const int* tail_ptr;
@@ -252,7 +272,7 @@ struct CocgArgs {
     const float* mval32;
 };
 
-constexpr int kFineVec = 5;   // u, u_prev, R, R_trial, u_{j-2}
+constexpr int kFineVec = 7;   // u, u_prev, R, R_trial, u_{j-2}, trial state, M u_prev / dt
 constexpr int kPcgVec = 5;    // r, p, q, x, dinv
 
 // set-up (setup.hip)

@@ -182,6 +182,17 @@ __global__ void k_geometry(int ne, const double* __restrict__ xy, const int* __r
     }
 }
 
+// compact copies of the area and K0 of the Brauer elements
+__global__ void k_gather_nl(int nnl, int ne, const int* __restrict__ nl_elem,
+                            const double* __restrict__ area, const double* __restrict__ k0,
+                            double* __restrict__ nl_area, double* __restrict__ nl_k0) {
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < nnl; j += gridDim.x * blockDim.x) {
+        const int e = nl_elem[j];
+        nl_area[j] = area[e];
+        for (int q = 0; q < 6; ++q) nl_k0[(size_t)q * nnl + j] = k0[(size_t)q * ne + e];
+    }
+}
+
 // M_s = sum over contributions (e, a, b) of sigma_e A_e / 12 (1 + delta_ab)
 __global__ void k_mass(int nnz, const int* __restrict__ slot_ptr, const int* __restrict__ slot_src,
                        const double* __restrict__ sigma, const double* __restrict__ area,
@@ -417,6 +428,41 @@ void build_problem(ppc_problem* pr, const ppc_mesh* mesh, const ppc_material* ma
     for (int e = 0; e < ne; ++e)
         if (L.law[mat->mat_id[e]] == PPC_LAW_BRAUER) pr->nl_elem.push_back(e);
     d.nonlinear = !pr->nl_elem.empty();
+    // Brauer elements in a compact numbering j; the ELL value positions whose slot holds a
+    // Brauer contribution (codes j*9 + a*3 + b, slot order); per row, the incident
+    // Brauer elements (codes j*3 + a, node order).
+    const int nnl = (int)pr->nl_elem.size();
+    std::vector<int> nl_of_elem(ne, -1), nl_efree(3 * (size_t)nnl), nl_mat(nnl);
+    for (int j = 0; j < nnl; ++j) {
+        const int e = pr->nl_elem[j];
+        nl_of_elem[e] = j;
+        for (int a = 0; a < 3; ++a) nl_efree[(size_t)a * nnl + j] = efree[(size_t)a * ne + e];
+        nl_mat[j] = mat->mat_id[e];
+    }
+    std::vector<int> nlv_val, nlv_ptr(1, 0), nlv_src;
+    for (size_t v = 0; v < vslot.size(); ++v) {
+        const int sl = vslot[v];
+        if (sl < 0) continue;
+        const size_t before = nlv_src.size();
+        for (int k = slot_ptr[sl]; k < slot_ptr[sl + 1]; ++k) {
+            const int j = nl_of_elem[slot_src[k] / 9];
+            if (j >= 0) nlv_src.push_back(j * 9 + slot_src[k] % 9);
+        }
+        if (nlv_src.size() > before) {
+            nlv_val.push_back((int)v);
+            nlv_ptr.push_back((int)nlv_src.size());
+        }
+    }
+    std::vector<int> nlf_ptr(n + 1, 0), nlf_src;
+    for (int i = 0; i < n; ++i) {
+        for (int k = node_ptr[i]; k < node_ptr[i + 1]; ++k) {
+            const int j = nl_of_elem[node_src[k] / 3];
+            if (j >= 0) nlf_src.push_back(j * 3 + node_src[k] % 3);
+        }
+        nlf_ptr[i + 1] = (int)nlf_src.size();
+    }
+    d.n_nl = nnl;
+    d.n_nlv = (int)nlv_val.size();
     {
         std::vector<double> lt(5 * (size_t)mat->n_mat);
         for (int k = 0; k < mat->n_mat; ++k) {
@@ -453,12 +499,25 @@ void build_problem(ppc_problem* pr, const ppc_mesh* mesh, const ppc_material* ma
     d.node_src = upload(node_src, s);
     d.efree = upload(efree, s);
     d.ecol = upload(ecol, s);
+    if (n < 65536) {
+        std::vector<unsigned short> e16(ecol.size());
+        for (size_t v = 0; v < ecol.size(); ++v) e16[v] = (unsigned short)(ecol[v] < 0 ? 0 : ecol[v]);
+        d.ecol16 = upload(e16, s);
+    }
     d.vslot = upload(vslot, s);
     d.dpos = upload(dpos, s);
     d.tail_row = upload(tail_row, s);
     d.tail_ptr = upload(tail_ptr, s);
     d.tail_col = upload(tail_col, s);
     d.free_node = upload(free_node, s);
+    d.nl_elem = upload(pr->nl_elem, s);
+    d.nl_efree = upload(nl_efree, s);
+    d.nl_mat = upload(nl_mat, s);
+    d.nlv_val = upload(nlv_val, s);
+    d.nlv_ptr = upload(nlv_ptr, s);
+    d.nlv_src = upload(nlv_src, s);
+    d.nlf_ptr = upload(nlf_ptr, s);
+    d.nlf_src = upload(nlf_src, s);
     d.mat = upload(std::vector<int>(mat->mat_id, mat->mat_id + ne), s);
     d.xy = upload(std::vector<double>(mesh->xy, mesh->xy + 2 * (size_t)nn), s);
     d.tri = upload(std::vector<int>(mesh->tri, mesh->tri + 3 * (size_t)ne), s);
@@ -468,12 +527,17 @@ void build_problem(ppc_problem* pr, const ppc_mesh* mesh, const ppc_material* ma
     d.k0 = dalloc<double>(6 * (size_t)ne);
     d.gx = dalloc<double>(3 * (size_t)ne);
     d.gy = dalloc<double>(3 * (size_t)ne);
+    d.nl_area = dalloc<double>(nnl);
+    d.nl_k0 = dalloc<double>(6 * (size_t)nnl);
     d.mval = dalloc<double>(nnz);
     d.mdiag = dalloc<double>(n);
     d.fload = dalloc<double>(n);
     double* fn = dalloc<double>(1);
     hipLaunchKernelGGL(k_geometry, dim3(grid_for(ne, 256)), dim3(256), 0, s, ne, d.xy, d.tri, d.area,
                        d.k0, d.gx, d.gy);
+    if (nnl > 0)
+        hipLaunchKernelGGL(k_gather_nl, dim3(grid_for(nnl, 256)), dim3(256), 0, s, nnl, ne, d.nl_elem,
+                           d.area, d.k0, d.nl_area, d.nl_k0);
     hipLaunchKernelGGL(k_mass, dim3(grid_for(nnz, 256)), dim3(256), 0, s, nnz, d.slot_ptr, d.slot_src,
                        d.sigma, d.area, d.mval);
     hipLaunchKernelGGL(k_load, dim3(grid_for(n, 256)), dim3(256), 0, s, n, d.node_ptr, d.node_src,
@@ -490,8 +554,9 @@ void build_problem(ppc_problem* pr, const ppc_mesh* mesh, const ppc_material* ma
 void mesh_free(DeviceMesh& d) {
     void* ptrs[] = {d.rowptr, d.colidx, d.diag, d.slot_ptr, d.slot_src, d.node_ptr, d.node_src,
                     d.efree, d.free_node, d.mat, d.xy, d.tri, d.area, d.k0, d.gx, d.gy,
-                    d.sigma, d.js, d.mval, d.mval32, d.mdiag, d.fload, d.ecol, d.vslot, d.dpos,
-                    d.tail_row, d.tail_ptr, d.tail_col};
+                    d.sigma, d.js, d.mval, d.mval32, d.mdiag, d.fload, d.ecol, d.ecol16, d.vslot, d.dpos,
+                    d.tail_row, d.tail_ptr, d.tail_col, d.nl_elem, d.nl_efree, d.nl_mat, d.nl_area,
+                    d.nl_k0, d.nlv_val, d.nlv_ptr, d.nlv_src, d.nlf_ptr, d.nlf_src};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     d = DeviceMesh{};
