@@ -13,7 +13,7 @@ Prints one JSON line: steady states per second, the roofline of the dominant ker
 against the stored FP64 oracle fixed point, and the CPU oracle timed on a bounded
 sample as a baseline.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp64|mixed]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp64|mixed|mixed-fine]
 """
 from __future__ import annotations
 
@@ -56,7 +56,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c5small"])
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed", "mixed-fine"])
     ap.add_argument("--tol", type=float, default=1e-8, help="PP-PC stopping tolerance on eps")
     ap.add_argument("--tol-cocg", type=float, default=1e-6,
                     help="relative tolerance of the harmonic solves (a correction only needs to be "
@@ -153,8 +153,14 @@ def probe_fine(a, prob, ref):
     F, newton, lin = pr.fine_sweep(prm, Ud)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    cnt = pr.fine_counts(prob.N)
+    tot = {"lin_total": int(cnt[:, 2].sum()), "newton_total": int(cnt[:, 1].sum()),
+           "resid_total": int(cnt[:, 7].sum()), "steps_total": prob.N * prob.m, "fine_launches": 1,
+           "n_free": pr.n_free, "nnz": pr.nnz, "n_tri": pr.n_tri}
     print(json.dumps({"probe": "fine", "copy_bytes_each_way": src.numel() * 8, "sweep_ms": dt * 1e3,
-                      "newton_total": int(newton.sum()), "lin_total": int(lin.sum())}), flush=True)
+                      "newton_total": tot["newton_total"], "lin_total": tot["lin_total"],
+                      "resid_total": tot["resid_total"],
+                      "algorithmic_bytes": fine_sweep_bytes(tot, prob.N, prec)}), flush=True)
     return 0
 
 
@@ -183,8 +189,10 @@ def main():
     pr = P.Problem(h, prob)
     setup_s = time.perf_counter() - t0
     prec = 0 if a.precision == "fp64" else 1
-    prm = P.problem_params(prob, tol_ppc=a.tol, precision=prec, tol_cocg=a.tol_cocg,
-                           **({"tol_lin": 1e-4} if prec == 1 else {}))
+    extra = {"tol_lin": 1e-4} if prec == 1 else {}
+    if a.precision == "mixed-fine":          # FP32 PCG fine solves, FP64 harmonic solves
+        extra["coarse_precision"] = 0
+    prm = P.problem_params(prob, tol_ppc=a.tol, precision=prec, tol_cocg=a.tol_cocg, **extra)
     out = torch.empty((prob.N, pr.n_nodes), dtype=torch.float64, device="cuda")
     for _ in range(a.warmup):
         pr.solve(prm, out=out)

@@ -118,7 +118,9 @@ typedef struct {
     int32_t lin_point;      /* samples the coarse stiffness is linearised at: 0 = the current
                                iterate U^k, 1 = the fine results F^k of the same sweep (equal
                                at the fixed point) */
-    int32_t reserved[5];
+    int32_t coarse_precision; /* harmonic (coarse) solves: -1 = as precision, 0 = FP64 COCG,
+                               1 = complex-FP32 COCG refined by FP64 residuals */
+    int32_t reserved[4];
 } ppc_params;
 
 /* Counters and timings of the last solve (all chains, all iterations). */
@@ -150,7 +152,8 @@ int ppc_version(void);
 
 /* Defaults: T = 0.02, N = 10, m = 20, shift 0, lin 0, init 0, FP64, tol_ppc 1e-12,
  * max_iters 60, tol_newton 1e-13, max_newton 50, tol_lin 1e-8, max_lin 20000,
- * tol_cocg 1e-10, max_cocg 20000, block 0, predictor on, lin_point 1 (fine results).
+ * tol_cocg 1e-10, max_cocg 20000, block 0, predictor on, lin_point 1 (fine results),
+ * coarse_precision -1.
  * Returns PPC_ERR_ARG on a null pointer. */
 int ppc_params_default(ppc_params* p);
 
@@ -252,6 +255,15 @@ int ppc_adjoint(ppc_handle* h, ppc_problem* pr, const ppc_params* p, const doubl
 int ppc_fine_sweep_device(ppc_handle* h, ppc_problem* pr, const ppc_params* p,
                           const double* U_in_dev, double* F_out_dev, int32_t* newton_out,
                           int32_t* lin_out, void* stream);
+
+/* Per-chain counters of the last fine sweep run on this problem (by
+ * ppc_fine_sweep_device, or the last sweep of a solve).  counts is host
+ * [n_chains * 8], per chain: status, Newton iterations, PCG iterations, the largest
+ * Newton count of one step, the largest PCG count of one Newton step, PCG solves that
+ * stopped at max_lin, failing step (-1: none), residual evaluations.  n_chains must be
+ * the N of that sweep; PPC_ERR_ARG for a batched problem, a null pointer, a different
+ * N or no sweep yet.  Blocks until the counters are on the host. */
+int ppc_fine_counts(const ppc_problem* pr, int32_t n_chains, int32_t* counts);
 
 /* One coarse correction (Section 3, eqs. (11)-(14), in correction form): from the
  * samples U and jumps J (DEVICE [N * n_nodes]; J[n] = F_n - U_n mod N) compute

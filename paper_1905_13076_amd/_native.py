@@ -50,7 +50,8 @@ class Params(ctypes.Structure):
                 ("tol_ppc", c_double), ("max_iters", c_int32), ("tol_newton", c_double),
                 ("max_newton", c_int32), ("tol_lin", c_double), ("max_lin", c_int32),
                 ("tol_cocg", c_double), ("max_cocg", c_int32), ("block", c_int32),
-                ("no_predictor", c_int32), ("lin_point", c_int32), ("reserved", c_int32 * 5)]
+                ("no_predictor", c_int32), ("lin_point", c_int32), ("coarse_precision", c_int32),
+                ("reserved", c_int32 * 4)]
 
 
 class Stats(ctypes.Structure):
@@ -89,6 +90,7 @@ SIGNATURES = {
     "ppc_adjoint": (c_int, [c_void_p, c_void_p, POINTER(Params), PD, PD, PD, PD, PI, POINTER(Stats)]),
     "ppc_fine_sweep_device": (c_int, [c_void_p, c_void_p, POINTER(Params), c_void_p, c_void_p, PI, PI,
                                       c_void_p]),
+    "ppc_fine_counts": (c_int, [c_void_p, c_int32, PI]),
     "ppc_coarse_correction_device": (c_int, [c_void_p, c_void_p, POINTER(Params), c_void_p, c_void_p,
                                              c_void_p, PI, c_void_p]),
 }

@@ -579,6 +579,7 @@ int ppc_params_default(ppc_params* p) {
     p->block = 0;
     p->no_predictor = 0;
     p->lin_point = 1;
+    p->coarse_precision = -1;
     return PPC_OK;
 }
 
@@ -739,6 +740,15 @@ int ppc_problem_destroy(ppc_problem* pr) {
     return PPC_OK;
 }
 
+int ppc_fine_counts(const ppc_problem* pr, int32_t n_chains, int32_t* counts) {
+    if (!pr || !counts || pr->batch || !pr->h) return PPC_ERR_ARG;
+    if (pr->ws.N != n_chains || !pr->ws.fcount) return PPC_ERR_ARG;
+    if (hipSetDevice(pr->h->device) != hipSuccess) return PPC_ERR_DEVICE;
+    if (hipMemcpy(counts, pr->ws.fcount, sizeof(int32_t) * 8 * (size_t)n_chains, hipMemcpyDeviceToHost) !=
+        hipSuccess)
+        return PPC_ERR_DEVICE;
+    return PPC_OK;
+}
 int ppc_problem_info(const ppc_problem* pr, int32_t* n_free, int32_t* nnz, int32_t* n_tri,
                      int32_t* n_nodes) {
     if (!pr) return PPC_ERR_ARG;

@@ -696,7 +696,7 @@ CocgArgs make_cocg_args(ppc_problem* pr, const ppc_params* p) {
     a.tol = p->tol_cocg;
     a.max_it = p->max_cocg;
     a.count = w.ccount;
-    a.mixed = p->precision == 1 ? 1 : 0;
+    a.mixed = (p->coarse_precision < 0 ? p->precision : p->coarse_precision) == 1 ? 1 : 0;
     a.kbar32 = w.kbar32;
     a.mval32 = d.mval32;
     return a;

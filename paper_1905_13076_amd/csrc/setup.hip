@@ -130,6 +130,10 @@ int validate_params(const ppc_params* p, std::string& msg) {
     if (p->lin_mode < 0 || p->lin_mode > 1) { msg = "lin_mode must be 0 or 1"; return PPC_ERR_ARG; }
     if (p->init_mode < 0 || p->init_mode > 2) { msg = "init_mode must be 0, 1 or 2"; return PPC_ERR_ARG; }
     if (p->precision < 0 || p->precision > 1) { msg = "precision must be 0 or 1"; return PPC_ERR_ARG; }
+    if (p->coarse_precision < -1 || p->coarse_precision > 1) {
+        msg = "coarse_precision must be -1, 0 or 1";
+        return PPC_ERR_ARG;
+    }
     if (!finite(p->tol_ppc) || p->tol_ppc < 0.0) { msg = "tol_ppc must be finite and >= 0"; return PPC_ERR_ARG; }
     if (p->max_iters < 0 || p->max_iters > 100000) { msg = "max_iters out of range"; return PPC_ERR_ARG; }
     if (!finite(p->tol_newton) || !(p->tol_newton > 0.0)) { msg = "tol_newton must be > 0"; return PPC_ERR_ARG; }

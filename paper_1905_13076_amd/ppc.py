@@ -226,6 +226,16 @@ class Problem:
             raise _err(self.handle.h, rc)
         return F, newton, lin
 
+    def fine_counts(self, N):
+        """Per-chain counters of the last fine sweep, int32 [N, 8]: status, Newton and PCG
+        iterations, largest Newton / PCG count, capped PCG solves, failing step, residual
+        evaluations."""
+        out = np.zeros((N, 8), dtype=np.int32)
+        rc = lib().ppc_fine_counts(self.p, N, _pi(out))
+        if rc < 0:
+            raise PPCError(rc, "ppc_fine_counts: no sweep with this N on this problem")
+        return out
+
     def coarse_correction(self, prm, U, J):
         """dU solving the cyclic coarse system for jumps J.  CUDA [N, n_nodes] each."""
         import torch

@@ -1,31 +1,33 @@
 """Algorithmic HBM bytes of the fine-sweep kernel: what one launch must move if every
-input is read once and every output written once, from the per-chain counters the
+input is read once and every output written once (shared patterns counted per chain,
+as a cache-less implementation would move them), from the per-chain counters the
 kernel returns (steps, Newton iterations, residual evaluations, PCG iterations).
 
-Per-unit figures (n free nodes, nnz CSR entries, ne triangles, s = bytes of the PCG
-scalar: 8 FP64, 4 mixed):
+Per-unit figures (n free nodes, nnz CSR entries, s = bytes of the PCG scalar: 8 FP64,
+4 mixed; a triangulated mesh has about 2n elements):
 
-* PCG iteration      (s+4) nnz + 4 (n+1) + 13 s n
+* PCG iteration       (s+4) nnz + 4 (n+1) + 13 s n
   (SpMV values + columns + row pointers, gather p, write q; x,r update reads x p r q
   dinv and writes x r; direction reads dinv r p and writes p)
-* residual evaluation 180 ne + (36+s) n + 4
-  (element pass: 3 vertex indices, 6 K0 entries, area, sigma, material in, 8 values out,
-  vertex gathers of u, du, u_prev; node pass: incidence list, 3 element forces, load
-  vector in, residual out)
-* Newton iteration   assembly 4 (nnz+1) + 4 c + 88 ne + (8+s) nnz + (4+2s) n
-  (c = slot contributions) plus PCG set-up, step-norm and update passes (32+6s) n
-* time step          12 nnz + 28 n + 4 (copy u to u_prev, ||M u_prev|| SpMV)
-* chain              16 n (start vector in, end vector out)
+* residual evaluation 168 n
+  (FP64: state and previous state, geometry of the ~2n elements at 68 B, residual out)
+* Newton iteration    (144 + 8 s) n  (assembly: state, geometry, Jacobian values, diagonal);
+  its residual evaluations and PCG iterations are counted by their own units
+* time step           12 nnz + 28 n + 4 (copy u to u_prev, ||M u_prev|| SpMV)
+* chain               16 n (start vector in, end vector out)
+
+These are properties of the method's minimal streaming form, independent of where an
+implementation keeps its vectors or how it reuses the state-independent part of the
+Jacobian.
 """
 from __future__ import annotations
 
 
-def per_unit(n, nnz, ne, s, n_contrib=None):
-    c = 9 * ne if n_contrib is None else n_contrib
+def per_unit(n, nnz, ne, s):
     return {
         "pcg_iter": (s + 4) * nnz + 4 * (n + 1) + 13 * s * n,
-        "resid_eval": 180 * ne + (36 + s) * n + 4,
-        "newton_iter": 4 * (nnz + 1) + 4 * c + 88 * ne + (8 + s) * nnz + (4 + 2 * s) * n + (32 + 6 * s) * n,
+        "resid_eval": 168 * n,
+        "newton_iter": (144 + 8 * s) * n,
         "step": 12 * nnz + 28 * n + 4,
         "chain": 16 * n,
     }

@@ -135,6 +135,7 @@ def test_invalid_problems_are_rejected_on_host(case, code, needle):
     (dict(N=3), "even"), (dict(N=0), "even"), (dict(m=0), "m must"), (dict(T=-1.0), "T must"),
     (dict(tol_lin=1.5), "tol_lin"), (dict(shift_mode=2), "shift_mode"), (dict(precision=7), "precision"),
     (dict(block=100), "block"), (dict(max_newton=0), "max_newton"), (dict(tol_ppc=float("nan")), "tol_ppc"),
+    (dict(coarse_precision=2), "coarse_precision"), (dict(coarse_precision=-2), "coarse_precision"),
 ])
 def test_invalid_params_are_rejected_on_host(kw, needle):
     import paper_1905_13076_amd as P
@@ -149,6 +150,7 @@ def test_null_safety_and_no_device_error():
     assert lib.ppc_problem_destroy(None) == 0
     assert lib.ppc_params_default(None) == -1
     assert lib.ppc_problem_info(None, None, None, None, None) == -1
+    assert lib.ppc_fine_counts(None, 4, None) == -1
     assert lib.ppc_last_error(None) is not None
     h = ctypes.c_void_p()
     assert lib.ppc_create(-1, ctypes.byref(h)) == -1

@@ -56,3 +56,29 @@ def test_c2_mixed_matches_fp64_gpu_and_oracle():
            f"fine ms fp64={res[0][2]['fine_ms']:.0f} mixed={res[1][2]['fine_ms']:.0f}; "
            f"coarse ms fp64={res[0][2]['coarse_ms']:.0f} mixed={res[1][2]['coarse_ms']:.0f}")
     assert e_mix_fp64 <= 1e-6 and e_mix_orc <= 1e-6 and e_fp64_orc <= 1e-6
+
+
+def test_c5_mixed_fine_fp64_coarse_and_fine_counts():
+    """FP32 fine solves with FP64 harmonic solves (coarse_precision = 0) reach the oracle's
+    fixed point; the last sweep's per-chain counters are consistent with the solve's."""
+    import paper_1905_13076_amd as P
+    from oracle.fe import FE
+    prob = coax.c5_small()
+    fe = FE(prob)
+    g = load_golden("c5small")
+    pr = P.Problem(handle(), prob)
+    prm = P.problem_params(prob, tol_ppc=1e-8, precision=1, tol_lin=1e-4, coarse_precision=0)
+    banner("c5small mixed fine + fp64 coarse")
+    U, eps, k, st, rc = pr.solve(prm)
+    assert rc == 0
+    e = rel(free_rows(U.cpu().numpy(), fe.free), g["U"])
+    cnt = pr.fine_counts(prob.N)
+    banner(f"c5small mixed-fine: iters={k} rel={e:.1e} cocg_total={st['cocg_total']} "
+           f"last sweep newton={cnt[:, 1].sum()} lin={cnt[:, 2].sum()} resid={cnt[:, 7].sum()}")
+    assert e <= 1e-6
+    assert (cnt[:, 0] == 0).all() and (cnt[:, 6] == -1).all()
+    # every Newton iteration follows a residual evaluation, and every step evaluates one
+    assert (cnt[:, 7] >= cnt[:, 1]).all() and (cnt[:, 7] >= prob.m).all()
+    assert (cnt[:, 2] >= cnt[:, 1]).all()
+    with pytest.raises(P.PPCError):
+        pr.fine_counts(prob.N + 2)
