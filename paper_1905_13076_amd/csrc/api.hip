@@ -89,7 +89,7 @@ float elapsed(hipEvent_t a, hipEvent_t b) {
 }  // namespace
 
 void workspace_free(Workspace& w) {
-    void* ptrs[] = {w.fvec, w.fpcg, w.fjac, w.felem, w.jbase, w.fcount, w.U, w.F, w.J, w.R, w.kbar, w.kbar32,
+    void* ptrs[] = {w.fvec, w.fpcg, w.fjac, w.felem, w.jbase, w.ckm, w.fcount, w.U, w.F, w.J, w.R, w.kbar, w.kbar32,
                     w.nubar, w.rhat, w.cwork, w.sig, w.ccount, w.twiddle, w.partial, w.scal};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
@@ -124,6 +124,7 @@ void ensure_workspace(ppc_problem* pr, const ppc_params* p) {
     w.nubar = dalloc<double>(3 * (size_t)d.n_tri);
     w.rhat = dalloc<double2>(2 * H * d.n_free);
     w.cwork = dalloc<double2>(H * 4 * w.n_pad);
+    w.ckm = dalloc<double2>(w.vals_pad);
     w.sig = dalloc<double2>(H);
     w.ccount = dalloc<int>(H * 4);
     w.twiddle = dalloc<double2>(N);
@@ -342,11 +343,7 @@ int solve_batch_device(ppc_handle* h, ppc_problem* bp, const ppc_params* p, cons
             launch_coarse_pre(parts[d], p, excitation ? nullptr : (p->lin_point == 1 ? w.F : w.U),
                               excitation ? nullptr : w.J, excitation, s);
         }
-        cw.clear();
-        for (int d : list)
-            for (int q = 0; q < H; ++q) cw.push_back(make_int2(d, q));
-        PPC_HIP(hipMemcpyAsync(cwork.p, cw.data(), sizeof(int2) * cw.size(), hipMemcpyHostToDevice, s));
-        launch_cocg_batch(static_cast<CocgArgs*>(cargs.p), static_cast<int2*>(cwork.p), (int)cw.size(), s);
+        launch_cocg_batch(parts, list, p, static_cast<CocgArgs*>(cargs.p), static_cast<int2*>(cwork.p), cw, s);
         for (int d : list) launch_coarse_post(parts[d], p, parts[d]->ws.U, !excitation, s);
         for (int d : list) {
             PPC_HIP(hipMemcpyAsync(ccount.data(), parts[d]->ws.ccount, ccount.size() * sizeof(int),

@@ -20,6 +20,7 @@
 #include <cmath>
 
 #include "internal.hpp"
+#include "wave.hpp"
 
 namespace ppc {
 
@@ -332,6 +333,240 @@ __device__ __forceinline__ void cocg_body(const CocgArgs& a, const int p, double
         count[4 * p + 1] = k;
         count[4 * p + 2] = (rr <= target2) ? 1 : 0;
     }
+}
+
+// (Kbar, M) pairs in ELL order: position v takes CSR slot vslot[v] (padding: 0)
+__global__ void k_km(int nvals, const int* __restrict__ vslot, const double* __restrict__ kbar,
+                     const double* __restrict__ mval, double2* __restrict__ km) {
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < nvals; v += gridDim.x * blockDim.x) {
+        const int s = vslot[v];
+        km[v] = s >= 0 ? make_double2(kbar[s], mval[s]) : make_double2(0.0, 0.0);
+    }
+}
+
+// One workgroup per harmonic p: (Kbar + sigma_p M) x = b by Jacobi-preconditioned COCG
+// over the ELL pattern, for meshes whose search direction fits LDS.  p lives in LDS; the
+// row values q = A p and z = D^{-1} r stay in registers between the passes that use
+// them (rows tid + k B, k < R); x, r and D^{-1} live in memory.  The SpMV streams one
+// 16-byte (Kbar, M) pair and one 16-bit column per position (raw buffer loads: rows >= n
+// load nothing, slots past the arrays read zero) and gathers p from LDS.  A single tail
+// row of at most B entries is spread over all threads and reduced with p^T q; longer or
+// several tail rows take one wave each (q in LDS after p).
+template <int R>
+__device__ __forceinline__ void cocg_ell_body(const CocgArgs& a, const int hp, double2* p_l, double* lds) {
+    constexpr int B = kCocgBlock;
+    const int tid = threadIdx.x, n = a.n;
+    const int lane = tid & 63, wave = tid >> 6, nw = B >> 6;
+    const long NP = a.ell_pad;
+    const int W = a.W;
+    double2* tq_l = p_l + a.n_pad;
+    const double2 sg = a.sig[hp];
+    const double2* b = a.B + (long)hp * n;
+    double2* x = a.X + (long)hp * n;
+    double2* r = a.work + ((long)hp * 4 + 0) * a.n_pad;
+    double2* dv = a.work + ((long)hp * 4 + 3) * a.n_pad;
+    // x, r, D^{-1} through buffer resources: one lane offset per row, no per-row addresses
+    const __amdgpu_buffer_rsrc_t bx = buffer_rsrc(x, (unsigned)(n * sizeof(double2)));
+    const __amdgpu_buffer_rsrc_t br = buffer_rsrc(r, (unsigned)(n * sizeof(double2)));
+    const __amdgpu_buffer_rsrc_t bd = buffer_rsrc(dv, (unsigned)(n * sizeof(double2)));
+    const __amdgpu_buffer_rsrc_t rk = buffer_rsrc(a.km, (unsigned)(W * NP * sizeof(double2)));
+    const __amdgpu_buffer_rsrc_t rc = buffer_rsrc(a.ecol16, (unsigned)(W * NP * 2));
+    const bool tail1 = a.ntail == 1 && a.tail_ptr[1] - a.tail_ptr[0] <= B;
+    const int t_beg = tail1 ? a.tail_ptr[0] : 0;
+    const int t_len = tail1 ? a.tail_ptr[1] - t_beg : 0;
+    const int t_row = tail1 ? a.tail_row[0] : 0;
+    const __amdgpu_buffer_rsrc_t rtk = buffer_rsrc(a.km + W * NP + t_beg, (unsigned)(t_len * sizeof(double2)));
+    const __amdgpu_buffer_rsrc_t rtc = buffer_rsrc(a.tail_col + t_beg, (unsigned)(t_len * 4));
+    int ph = 0;
+    unsigned tailmask = 0;
+    double2 z[R], q[R];
+    double v[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int i = tid + k * B;
+        z[k] = make_double2(0.0, 0.0);
+        if (i < n) {
+            const double2 kd = a.km[a.dpos[i]];
+            const double2 di = cdiv(make_double2(1.0, 0.0), make_double2(kd.x + sg.x * kd.y, sg.y * kd.y));
+            buffer_store16(bd, (unsigned)i * 16u, di);
+            const double2 ri = b[i];
+            const double2 zi = cmul(di, ri);
+            buffer_store16(br, (unsigned)i * 16u, ri);
+            p_l[i] = zi;
+            buffer_store16(bx, (unsigned)i * 16u, make_double2(0.0, 0.0));
+            const double2 rz = cmul(ri, zi);
+            v[0] += rz.x;
+            v[1] += rz.y;
+            v[2] += ri.x * ri.x + ri.y * ri.y;
+            if (a.ecol[i] < 0) tailmask |= 1u << k;
+        }
+    }
+    block_sum<double, 3, B / 64>(v, lds, ph);
+    double2 rho = make_double2(v[0], v[1]);
+    const double bn2 = v[2];
+    double rr = bn2;
+    const double target2 = a.tol * a.tol * bn2;
+    int it = 0, status = 0;
+    while (rr > target2 && it < a.max_it) {
+        // this thread's tail entry: loads first, used after the ELL rounds
+        const double2 tkv = buffer_load<double2>(rtk, tid < t_len ? tid * 16u : kBufferNone);
+        const unsigned tcol = (unsigned)__builtin_amdgcn_raw_buffer_load_b32(rtc, tid < t_len ? tid * 4u : kBufferNone, 0, 0);
+        // q = (Kbar + sigma M) p in rounds of 4 complex loads: U slots x KC row groups
+        constexpr int KC = R < 4 ? R : 4;
+        constexpr int U = 4 / KC;
+#pragma unroll
+        for (int k = 0; k < R; ++k) q[k] = make_double2(0.0, 0.0);
+        for (int w0 = 0; w0 < W; w0 += U) {
+#pragma unroll
+            for (int kc = 0; kc < R; kc += KC) {
+                double2 kv[U][KC], pg[U][KC];
+                unsigned col[U][KC];
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+#pragma unroll
+                    for (int kk = 0; kk < KC; ++kk) {
+                        const int i = tid + (kc + kk) * B;
+                        const unsigned e = (unsigned)((w0 + u) * NP + i);
+                        kv[u][kk] = buffer_load<double2>(rk, i < n ? e * 16u : kBufferNone);
+                        col[u][kk] = __builtin_amdgcn_raw_buffer_load_b16(rc, i < n ? e * 2u : kBufferNone, 0, 0);
+                    }
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+#pragma unroll
+                    for (int kk = 0; kk < KC; ++kk) pg[u][kk] = p_l[col[u][kk]];
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+#pragma unroll
+                    for (int kk = 0; kk < KC; ++kk) {
+                        // coefficient Kbar + sigma M of the position, times p
+                        const double cr = kv[u][kk].x + sg.x * kv[u][kk].y, ci = sg.y * kv[u][kk].y;
+                        q[kc + kk].x += cr * pg[u][kk].x - ci * pg[u][kk].y;
+                        q[kc + kk].y += cr * pg[u][kk].y + ci * pg[u][kk].x;
+                    }
+            }
+        }
+        double m4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const int i = tid + k * B;
+            if (i < n && !((tailmask >> k) & 1u)) {
+                const double2 pq = cmul(p_l[i], q[k]);
+                m4[0] += pq.x;
+                m4[1] += pq.y;
+            }
+        }
+        if (tail1) {
+            const double2 coef = make_double2(tkv.x + sg.x * tkv.y, sg.y * tkv.y);
+            const double2 cv = cmul(coef, p_l[tcol]);
+            m4[2] = cv.x;
+            m4[3] = cv.y;
+            const double2 pq = cmul(p_l[t_row], cv);
+            m4[0] += pq.x;
+            m4[1] += pq.y;
+        } else {
+            const long base = (long)W * NP;
+            for (int t = wave; t < a.ntail; t += nw) {
+                double ax = 0.0, ay = 0.0;
+                const int j1 = a.tail_ptr[t + 1];
+                for (int j = a.tail_ptr[t] + lane; j < j1; j += 64) {
+                    const double2 kk = a.km[base + j];
+                    const double2 pc = p_l[a.tail_col[j]];
+                    const double cr = kk.x + sg.x * kk.y, ci = sg.y * kk.y;
+                    ax += cr * pc.x - ci * pc.y;
+                    ay += cr * pc.y + ci * pc.x;
+                }
+                ax = wave_sum(ax);
+                ay = wave_sum(ay);
+                if (lane == 0) {
+                    const double2 qt = make_double2(ax, ay);
+                    tq_l[t] = qt;
+                    const double2 pq = cmul(p_l[a.tail_row[t]], qt);
+                    m4[0] += pq.x;
+                    m4[1] += pq.y;
+                }
+            }
+        }
+        block_sum<double, 4, B / 64>(m4, lds, ph);
+        const double2 mu = make_double2(m4[0], m4[1]);
+        if (mu.x == 0.0 && mu.y == 0.0) { status = PPC_ERR_BREAKDOWN; break; }
+        const double2 alpha = cdiv(rho, mu);
+        double v2[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const int i = tid + k * B;
+            if (i < n) {
+                double2 qi = q[k];
+                if ((tailmask >> k) & 1u) {
+                    if (tail1) {
+                        qi = make_double2(m4[2], m4[3]);
+                    } else {
+                        for (int t = 0; t < a.ntail; ++t)
+                            if (a.tail_row[t] == i) qi = tq_l[t];
+                    }
+                }
+                const unsigned off = (unsigned)i * 16u;
+                const double2 pi = p_l[i];
+                const double2 ap = cmul(alpha, pi), aq = cmul(alpha, qi);
+                double2 xi = buffer_load<double2>(bx, off);
+                double2 ri = buffer_load<double2>(br, off);
+                const double2 di = buffer_load<double2>(bd, off);
+                xi.x += ap.x;
+                xi.y += ap.y;
+                buffer_store16(bx, off, xi);
+                ri.x -= aq.x;
+                ri.y -= aq.y;
+                buffer_store16(br, off, ri);
+                z[k] = cmul(di, ri);
+                const double2 rz = cmul(ri, z[k]);
+                v2[0] += rz.x;
+                v2[1] += rz.y;
+                v2[2] += ri.x * ri.x + ri.y * ri.y;
+            }
+        }
+        block_sum<double, 3, B / 64>(v2, lds, ph);
+        const double2 rho_new = make_double2(v2[0], v2[1]);
+        rr = v2[2];
+        ++it;
+        if (rr <= target2) break;
+        if (rho_new.x == 0.0 && rho_new.y == 0.0) { status = PPC_ERR_BREAKDOWN; break; }
+        if (!isfinite(rr)) { status = PPC_ERR_NONFINITE; break; }
+        const double2 beta = cdiv(rho_new, rho);
+        rho = rho_new;
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const int i = tid + k * B;
+            if (i < n) {
+                const double2 bp = cmul(beta, p_l[i]);
+                p_l[i] = make_double2(z[k].x + bp.x, z[k].y + bp.y);
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        a.count[4 * hp + 0] = status;
+        a.count[4 * hp + 1] = it;
+        a.count[4 * hp + 2] = (rr <= target2) ? 1 : 0;
+        a.count[4 * hp + 3] = 0;
+    }
+}
+
+template <int R>
+__global__ __launch_bounds__(kCocgBlock) void k_cocg_ell(CocgArgs a) {
+    extern __shared__ double2 p_l[];
+    __shared__ double lds[2 * 16 * 4];
+    cocg_ell_body<R>(a, blockIdx.x, p_l, lds);
+}
+
+// Batched designs of one ELL shape: block b solves harmonic work[b].y of design work[b].x.
+template <int R>
+__global__ __launch_bounds__(kCocgBlock) void k_cocg_ell_batch(const CocgArgs* __restrict__ args,
+                                                               const int2* __restrict__ work) {
+    extern __shared__ double2 p_l[];
+    __shared__ double lds[2 * 16 * 4];
+    const int2 wk = work[blockIdx.x];
+    cocg_ell_body<R>(args[wk.x], wk.y, p_l, lds);
 }
 
 __device__ inline float2 cmulf(float2 a, float2 b) {
@@ -663,6 +898,8 @@ void launch_coarse_pre(ppc_problem* pr, const ppc_params* p, const double* U, co
     const int sg = std::max(1, std::min((d.nnz + eb - 1) / eb, 4096));
     hipLaunchKernelGGL(k_kbar, dim3(sg), dim3(eb), 0, s, d.nnz, ne, d.slot_ptr, d.slot_src, d.area, d.gx,
                        d.gy, w.nubar, w.kbar, w.kbar32);
+    const int vg = std::max(1, std::min((d.n_vals + eb - 1) / eb, 4096));
+    hipLaunchKernelGGL(k_km, dim3(vg), dim3(eb), 0, s, d.n_vals, d.vslot, w.kbar, d.mval, w.ckm);
     const dim3 rg((n + 255) / 256, N);
     if (excitation_rhs)
         hipLaunchKernelGGL(k_excitation_rows, rg, dim3(256), 0, s, n, N, p->T, d.fload, pr->wavtab,
@@ -699,8 +936,57 @@ CocgArgs make_cocg_args(ppc_problem* pr, const ppc_params* p) {
     a.mixed = (p->coarse_precision < 0 ? p->precision : p->coarse_precision) == 1 ? 1 : 0;
     a.kbar32 = w.kbar32;
     a.mval32 = d.mval32;
+    a.km = w.ckm;
+    a.ecol16 = d.ecol16;
+    a.ecol = d.ecol;
+    a.dpos = d.dpos;
+    a.ell_pad = (long)d.ell_pad;
+    a.W = d.ell_w;
+    a.ntail = d.n_tail;
+    a.tail_row = d.tail_row;
+    a.tail_ptr = d.tail_ptr;
+    a.tail_col = d.tail_col;
     return a;
 }
+
+namespace {
+
+// Rows per thread of the ELL COCG for this problem (0: use the CSR form): FP64 solves of
+// meshes with 16-bit columns whose search direction (and tail sums) fit LDS.
+int cocg_ell_rows(const ppc_problem* pr, const CocgArgs& a, size_t& lds) {
+    const DeviceMesh& d = pr->mesh;
+    if (a.mixed || !d.ecol16) return 0;
+    lds = (pr->ws.n_pad + (size_t)std::max(d.n_tail, 1)) * sizeof(double2);
+    if (lds > kLdsBudget) return 0;
+    for (int R : {1, 2, 4, 8})
+        if ((long)R * kCocgBlock >= d.n_free) return R;
+    return 0;
+}
+
+template <int R>
+void launch_cocg_ell(const CocgArgs& a, size_t lds, hipStream_t s) {
+    static bool attr_set = false;
+    if (!attr_set) {
+        PPC_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_cocg_ell<R>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBudget));
+        attr_set = true;
+    }
+    hipLaunchKernelGGL(k_cocg_ell<R>, dim3(a.H), dim3(kCocgBlock), lds, s, a);
+}
+
+template <int R>
+void launch_cocg_ell_batch(const CocgArgs* d_args, const int2* d_work, int nblocks, size_t lds,
+                           hipStream_t s) {
+    static bool attr_set = false;
+    if (!attr_set) {
+        PPC_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_cocg_ell_batch<R>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBudget));
+        attr_set = true;
+    }
+    hipLaunchKernelGGL(k_cocg_ell_batch<R>, dim3(nblocks), dim3(kCocgBlock), lds, s, d_args, d_work);
+}
+
+}  // namespace
 
 // Inverse DFT of the harmonic solutions into dU (accumulate: U += dU).
 void launch_coarse_post(ppc_problem* pr, const ppc_params* p, double* dU, bool accumulate,
@@ -718,14 +1004,57 @@ void launch_coarse(ppc_problem* pr, const ppc_params* p, const double* U, const 
                    double* dU, bool accumulate, bool excitation_rhs, hipStream_t s) {
     launch_coarse_pre(pr, p, U, J, excitation_rhs, s);
     const CocgArgs a = make_cocg_args(pr, p);
-    hipLaunchKernelGGL(k_cocg, dim3(a.H), dim3(kCocgBlock), 0, s, a);
+    size_t lds = 0;
+    switch (cocg_ell_rows(pr, a, lds)) {
+        case 1: launch_cocg_ell<1>(a, lds, s); break;
+        case 2: launch_cocg_ell<2>(a, lds, s); break;
+        case 4: launch_cocg_ell<4>(a, lds, s); break;
+        case 8: launch_cocg_ell<8>(a, lds, s); break;
+        default: hipLaunchKernelGGL(k_cocg, dim3(a.H), dim3(kCocgBlock), 0, s, a);
+    }
     PPC_HIP(hipGetLastError());
     launch_coarse_post(pr, p, dU, accumulate, s);
 }
 
-void launch_cocg_batch(const CocgArgs* d_args, const int2* d_work, int nblocks, hipStream_t s) {
-    if (nblocks <= 0) return;
-    hipLaunchKernelGGL(k_cocg_batch, dim3(nblocks), dim3(kCocgBlock), 0, s, d_args, d_work);
+// Harmonic solves of the designs in list (descriptors d_args, one per design): the
+// (design, harmonic) work items are grouped by the designs' COCG form (as the single-
+// design launch picks it, so a design's arithmetic does not depend on its batch) and
+// each group is one launch.  cw keeps the host work list alive for the copy.
+void launch_cocg_batch(const std::vector<ppc_problem*>& parts, const std::vector<int>& list,
+                       const ppc_params* p, const CocgArgs* d_args, int2* d_work, std::vector<int2>& cw,
+                       hipStream_t s) {
+    const int H = p->N / 2 + 1;
+    struct Span {
+        int R;
+        size_t lds;
+        int begin, count;
+    };
+    std::vector<Span> spans;
+    cw.clear();
+    for (int R : {0, 1, 2, 4, 8}) {
+        Span sp{R, 0, (int)cw.size(), 0};
+        for (int d : list) {
+            const CocgArgs a = make_cocg_args(parts[d], p);
+            size_t lds = 0;
+            if (cocg_ell_rows(parts[d], a, lds) != R) continue;
+            sp.lds = std::max(sp.lds, lds);
+            for (int q = 0; q < H; ++q) cw.push_back(make_int2(d, q));
+        }
+        sp.count = (int)cw.size() - sp.begin;
+        if (sp.count > 0) spans.push_back(sp);
+    }
+    if (cw.empty()) return;
+    PPC_HIP(hipMemcpyAsync(d_work, cw.data(), sizeof(int2) * cw.size(), hipMemcpyHostToDevice, s));
+    for (const Span& sp : spans) {
+        const int2* w = d_work + sp.begin;
+        switch (sp.R) {
+            case 1: launch_cocg_ell_batch<1>(d_args, w, sp.count, sp.lds, s); break;
+            case 2: launch_cocg_ell_batch<2>(d_args, w, sp.count, sp.lds, s); break;
+            case 4: launch_cocg_ell_batch<4>(d_args, w, sp.count, sp.lds, s); break;
+            case 8: launch_cocg_ell_batch<8>(d_args, w, sp.count, sp.lds, s); break;
+            default: hipLaunchKernelGGL(k_cocg_batch, dim3(sp.count), dim3(kCocgBlock), 0, s, d_args, w);
+        }
+    }
     PPC_HIP(hipGetLastError());
 }
 

@@ -17,6 +17,7 @@ constexpr int kFineBlock = 1024;        // default fine-kernel workgroup
 constexpr int kCocgBlock = 1024;
 constexpr int kRowGroup = 8;            // lanes per CSR row in the vector SpMV
 constexpr int kEllMaxWidth = 8;         // rows longer than this go to the ELL tail
+constexpr size_t kLdsBudget = 160 * 1024 - 4096;   // dynamic LDS per workgroup (of 160 KB)
 
 // ----------------------------------------------------------------------------------
 // error plumbing: every internal failure throws ppc::Error, caught at the C-ABI
@@ -135,6 +136,7 @@ struct Workspace {
     double* nubar = nullptr;   // [3][n_tri]
     double2* rhat = nullptr;   // [2][H][n_free]: right-hand sides, then solutions
     double2* cwork = nullptr;  // [H][4][n_pad] COCG vectors r p q dinv
+    double2* ckm = nullptr;    // [vals_pad] (Kbar, M) pairs in ELL order
     double2* sig = nullptr;    // [H] shifts sigma_p
     int* ccount = nullptr;     // [H][4]
     double2* twiddle = nullptr;// [N]
@@ -270,6 +272,16 @@ struct CocgArgs {
     int mixed;               // 1: complex-FP32 inner COCG refined by FP64 residuals
     const float* kbar32;
     const float* mval32;
+    // ELL form (FP64, meshes whose search direction fits LDS)
+    const double2* km;       // [n_vals] (Kbar, M) pair of each ELL value position
+    const unsigned short* ecol16;
+    const int* ecol;
+    const int* dpos;
+    long ell_pad;
+    int W, ntail;
+    const int* tail_row;
+    const int* tail_ptr;
+    const int* tail_col;
 };
 
 constexpr int kFineVec = 7;   // u, u_prev, R, R_trial, u_{j-2}, trial state, M u_prev / dt
@@ -313,7 +325,9 @@ void launch_coarse(ppc_problem* pr, const ppc_params* p, const double* U, const 
 void launch_coarse_pre(ppc_problem* pr, const ppc_params* p, const double* U, const double* J,
                        bool excitation_rhs, hipStream_t s);
 CocgArgs make_cocg_args(ppc_problem* pr, const ppc_params* p);
-void launch_cocg_batch(const CocgArgs* d_args, const int2* d_work, int nblocks, hipStream_t s);
+void launch_cocg_batch(const std::vector<ppc_problem*>& parts, const std::vector<int>& list,
+                       const ppc_params* p, const CocgArgs* d_args, int2* d_work, std::vector<int2>& cw,
+                       hipStream_t s);
 void launch_coarse_post(ppc_problem* pr, const ppc_params* p, double* dU, bool accumulate,
                         hipStream_t s);
 void launch_to_nodal(const ppc_problem* pr, int N, const double* Ufree, double* Unodal,

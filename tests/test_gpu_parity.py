@@ -93,6 +93,35 @@ def test_c1_coarse_correction_matches_oracle():
     assert e <= 1e-10
 
 
+@pytest.mark.parametrize("nr,ntheta,bar", [(12, 24, 1e-10), (30, 48, 1e-10), (48, 64, 1e-10),
+                                           (60, 100, 1e-10), (4, 1100, 1e-8)])
+def test_coarse_correction_row_shapes_match_oracle(nr, ntheta, bar):
+    """The FP64 harmonic solves for every register shape of the ELL COCG (1, 2, 4 and 8
+    rows per thread) and for a centre row longer than a workgroup (the per-wave tail
+    form), against the oracle's direct per-harmonic solves.  COCG stops at a residual of
+    1e-13 relative, so the solution error is that times the condition number: the
+    1100-way centre fan of the last mesh (slivers of angle 2 pi / 1100) needs ~1700
+    iterations and is held to 1e-8."""
+    import torch
+    import paper_1905_13076_amd as P
+    from oracle.fe import FE
+    from oracle import periodic
+    prob = coax.tiny(nr=nr, ntheta=ntheta, N=4, m=3, nonlinear=True)
+    fe = FE(prob)
+    rng = np.random.default_rng(nr * 1000 + ntheta)
+    U = 2e-6 * rng.standard_normal((prob.N, fe.n))
+    J = 1e-7 * rng.standard_normal((prob.N, fe.n))
+    dUo = periodic.coarse_correction(fe, U, J)
+    banner(f"coarse row shapes nr={nr} ntheta={ntheta} n={fe.n}")
+    pr = _problem(prob)
+    prm = P.problem_params(prob, tol_cocg=1e-13)
+    dU, cocg = pr.coarse_correction(prm, torch.tensor(_nodal(fe, U), device="cuda"),
+                                    torch.tensor(_nodal(fe, J), device="cuda"))
+    e = rel(free_rows(dU.cpu().numpy(), fe.free), dUo)
+    banner(f"coarse nr={nr} ntheta={ntheta}: rel={e:.2e} cocg={cocg.tolist()}")
+    assert e <= bar
+
+
 @pytest.mark.parametrize("start", ["zero", "periodic"])
 def test_nonlinear_fine_sweep_matches_oracle(start):
     """Brauer steel sheath on the C1 mesh: fine sweep from U = 0 (transient, saturating)
