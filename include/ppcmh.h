@@ -120,7 +120,10 @@ typedef struct {
                                at the fixed point) */
     int32_t coarse_precision; /* harmonic (coarse) solves: -1 = as precision, 0 = FP64 COCG,
                                1 = complex-FP32 COCG refined by FP64 residuals */
-    int32_t reserved[4];
+    int32_t graph;          /* single-design solves: 1 = each PP-PC iteration replays two HIP
+                               graphs (fine sweep + jumps; coarse correction), captured at the
+                               second iteration; 0 = eager launches.  Same kernels, same results */
+    int32_t reserved[3];
 } ppc_params;
 
 /* Counters and timings of the last solve (all chains, all iterations). */
@@ -153,7 +156,7 @@ int ppc_version(void);
 /* Defaults: T = 0.02, N = 10, m = 20, shift 0, lin 0, init 0, FP64, tol_ppc 1e-12,
  * max_iters 60, tol_newton 1e-13, max_newton 50, tol_lin 1e-8, max_lin 20000,
  * tol_cocg 1e-10, max_cocg 20000, block 0, predictor on, lin_point 1 (fine results),
- * coarse_precision -1.
+ * coarse_precision -1, graph 1.
  * Returns PPC_ERR_ARG on a null pointer. */
 int ppc_params_default(ppc_params* p);
 

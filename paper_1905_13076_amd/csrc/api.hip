@@ -94,6 +94,8 @@ void workspace_free(Workspace& w) {
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (w.host_scal) (void)hipHostFree(w.host_scal);
+    if (w.host_fcount) (void)hipHostFree(w.host_fcount);
+    if (w.host_ccount) (void)hipHostFree(w.host_ccount);
     w = Workspace{};
 }
 
@@ -133,6 +135,10 @@ void ensure_workspace(ppc_problem* pr, const ppc_params* p) {
     void* hp = nullptr;
     PPC_HIP(hipHostMalloc(&hp, 16 * sizeof(double), hipHostMallocDefault));
     w.host_scal = static_cast<double*>(hp);
+    PPC_HIP(hipHostMalloc(&hp, 8 * N * sizeof(int), hipHostMallocDefault));
+    w.host_fcount = static_cast<int*>(hp);
+    PPC_HIP(hipHostMalloc(&hp, 4 * H * sizeof(int), hipHostMallocDefault));
+    w.host_ccount = static_cast<int*>(hp);
     w.N = p->N;
 }
 
@@ -145,14 +151,12 @@ struct SweepCounts {
     int fail_chain = -1, fail_step = -1;
 };
 
-SweepCounts read_chain_counts(ppc_problem* pr, int N, hipStream_t s, int32_t* newton_out,
-                              int32_t* lin_out) {
-    std::vector<int> c(8 * (size_t)N);
-    PPC_HIP(hipMemcpyAsync(c.data(), pr->ws.fcount, c.size() * sizeof(int), hipMemcpyDeviceToHost, s));
-    PPC_HIP(hipStreamSynchronize(s));
+// Chain counters [N][8] (status, Newton, PCG, Newton max, PCG max, capped, failing step,
+// residual evaluations) summed over the chains.
+SweepCounts parse_chain_counts(const int* c, int N, int32_t* newton_out, int32_t* lin_out) {
     SweepCounts r;
     for (int k = 0; k < N; ++k) {
-        const int* q = c.data() + 8 * k;
+        const int* q = c + 8 * k;
         if (q[0] != 0 && r.status == 0) {
             r.status = q[0];
             r.fail_chain = k;
@@ -170,6 +174,14 @@ SweepCounts read_chain_counts(ppc_problem* pr, int N, hipStream_t s, int32_t* ne
     return r;
 }
 
+SweepCounts read_chain_counts(ppc_problem* pr, int N, hipStream_t s, int32_t* newton_out,
+                              int32_t* lin_out) {
+    PPC_HIP(hipMemcpyAsync(pr->ws.host_fcount, pr->ws.fcount, 8 * (size_t)N * sizeof(int),
+                           hipMemcpyDeviceToHost, s));
+    PPC_HIP(hipStreamSynchronize(s));
+    return parse_chain_counts(pr->ws.host_fcount, N, newton_out, lin_out);
+}
+
 void check_sweep(const SweepCounts& c) {
     if (c.status != 0)
         fail(c.status, "fine chain " + std::to_string(c.fail_chain + 1) + " failed at step " +
@@ -177,10 +189,8 @@ void check_sweep(const SweepCounts& c) {
                            (c.status == PPC_ERR_NONFINITE ? " (non-finite residual)" : " (Newton did not converge)"));
 }
 
-int read_cocg(ppc_problem* pr, int H, hipStream_t s, int32_t* cocg_out, int64_t* total, int* mx) {
-    std::vector<int> c(4 * (size_t)H);
-    PPC_HIP(hipMemcpyAsync(c.data(), pr->ws.ccount, c.size() * sizeof(int), hipMemcpyDeviceToHost, s));
-    PPC_HIP(hipStreamSynchronize(s));
+// Harmonic-solve counters [H][4] (status, iterations, converged, refinements).
+int parse_cocg(const int* c, int H, int32_t* cocg_out, int64_t* total, int* mx) {
     int status = 0;
     for (int p = 0; p < H; ++p) {
         if (c[4 * p] != 0 && status == 0) status = c[4 * p];
@@ -191,6 +201,41 @@ int read_cocg(ppc_problem* pr, int H, hipStream_t s, int32_t* cocg_out, int64_t*
     if (status != 0)
         fail(status, status == PPC_ERR_BREAKDOWN ? "COCG breakdown in a harmonic solve" : "non-finite COCG residual");
     return 0;
+}
+
+int read_cocg(ppc_problem* pr, int H, hipStream_t s, int32_t* cocg_out, int64_t* total, int* mx) {
+    PPC_HIP(hipMemcpyAsync(pr->ws.host_ccount, pr->ws.ccount, 4 * (size_t)H * sizeof(int),
+                           hipMemcpyDeviceToHost, s));
+    PPC_HIP(hipStreamSynchronize(s));
+    return parse_cocg(pr->ws.host_ccount, H, cocg_out, total, mx);
+}
+
+// An instantiated HIP graph, destroyed with its owner.
+struct GraphExec {
+    hipGraphExec_t exec = nullptr;
+    ~GraphExec() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+    }
+};
+
+// Record the launches and copies that f enqueues on s into g.  The capture always ends,
+// also when f throws, so the stream is never left capturing.
+template <class F>
+void capture_graph(GraphExec& g, hipStream_t s, F&& f) {
+    PPC_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    try {
+        f();
+    } catch (...) {
+        hipGraph_t dropped = nullptr;
+        (void)hipStreamEndCapture(s, &dropped);
+        if (dropped) (void)hipGraphDestroy(dropped);
+        throw;
+    }
+    hipGraph_t graph = nullptr;
+    PPC_HIP(hipStreamEndCapture(s, &graph));
+    const hipError_t e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    PPC_HIP(e);
 }
 
 hipStream_t pick_stream(ppc_handle* h, void* stream) {
@@ -236,16 +281,40 @@ int solve_device(ppc_handle* h, ppc_problem* pr, const ppc_params* p, const doub
             S.coarse_solves++;
         }
     }
+    // Device work of one PP-PC iteration: the fine sweep with the jump norms and the
+    // chain counters copied to pinned host memory, then (if not converged) the coarse
+    // correction with its counters.  With params->graph each part is captured once, at
+    // its second use, and replayed; the first iteration runs eagerly (it also sets the
+    // kernels' attributes and the base Jacobian, which capture must not do).
+    const bool use_graph = p->graph != 0;
+    GraphExec g_fine, g_coarse;
+    auto fine_ops = [&]() {
+        launch_fine_sweep(pr, p, w.U, w.F, s);
+        launch_jumps(pr, N, w.U, w.F, w.J, w.scal, s);
+        PPC_HIP(hipMemcpyAsync(w.host_scal, w.scal, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+        PPC_HIP(hipMemcpyAsync(w.host_fcount, w.fcount, 8 * (size_t)N * sizeof(int), hipMemcpyDeviceToHost, s));
+    };
+    auto coarse_ops = [&]() {
+        launch_coarse(pr, p, p->lin_point == 1 ? w.F : w.U, w.J, w.U, true, false, s);
+        PPC_HIP(hipMemcpyAsync(w.host_ccount, w.ccount, 4 * (size_t)H * sizeof(int), hipMemcpyDeviceToHost, s));
+    };
+    auto run = [&](GraphExec& g, int k, auto& ops) {
+        if (!use_graph || k == 0) {
+            ops();
+            return;
+        }
+        if (!g.exec) capture_graph(g, s, ops);
+        PPC_HIP(hipGraphLaunch(g.exec, s));
+    };
     int status = PPC_NOT_CONVERGED;
     int k = 0;
     for (k = 0; k <= p->max_iters; ++k) {
         PPC_HIP(hipEventRecord(ev[0], s));
-        launch_fine_sweep(pr, p, w.U, w.F, s);
+        run(g_fine, k, fine_ops);
         PPC_HIP(hipEventRecord(ev[1], s));
         S.fine_launches++;
-        launch_jumps(pr, N, w.U, w.F, w.J, w.scal, s);
-        PPC_HIP(hipMemcpyAsync(w.host_scal, w.scal, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
-        const SweepCounts c = read_chain_counts(pr, N, s, nullptr, nullptr);  // synchronises
+        PPC_HIP(hipStreamSynchronize(s));
+        const SweepCounts c = parse_chain_counts(w.host_fcount, N, nullptr, nullptr);
         S.fine_ms += elapsed(ev[0], ev[1]);
         S.newton_total += c.newton;
         S.lin_total += c.lin;
@@ -267,9 +336,10 @@ int solve_device(ppc_handle* h, ppc_problem* pr, const ppc_params* p, const doub
         }
         if (k == p->max_iters) break;
         PPC_HIP(hipEventRecord(ev[2], s));
-        launch_coarse(pr, p, p->lin_point == 1 ? w.F : w.U, w.J, w.U, true, false, s);
+        run(g_coarse, k, coarse_ops);
         PPC_HIP(hipEventRecord(ev[3], s));
-        read_cocg(pr, H, s, nullptr, &S.cocg_total, &S.cocg_max);  // synchronises
+        PPC_HIP(hipStreamSynchronize(s));
+        parse_cocg(w.host_ccount, H, nullptr, &S.cocg_total, &S.cocg_max);
         S.coarse_ms += elapsed(ev[2], ev[3]);
         S.coarse_solves++;
     }
@@ -577,6 +647,7 @@ int ppc_params_default(ppc_params* p) {
     p->no_predictor = 0;
     p->lin_point = 1;
     p->coarse_precision = -1;
+    p->graph = 1;
     return PPC_OK;
 }
 

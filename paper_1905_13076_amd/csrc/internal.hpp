@@ -143,6 +143,8 @@ struct Workspace {
     double* partial = nullptr; // reduction partials
     double* scal = nullptr;    // small scalars
     double* host_scal = nullptr; // pinned host mirror
+    int* host_fcount = nullptr;  // pinned [N][8] chain counters of the last sweep
+    int* host_ccount = nullptr;  // pinned [H][4] harmonic-solve counters
     size_t n_pad = 0, nnz_pad = 0, ne_pad = 0, vals_pad = 0, nl_pad = 0;
 };
 
