@@ -100,7 +100,10 @@ typedef struct {
     int32_t lin_mode;       /* coarse stiffness of a nonlinear problem: 0 = time average
                                of the differential reluctivity tensor, 1 = of the chord nu */
     int32_t init_mode;      /* U^0 when no U_init is given: 0 auto (1 if all laws linear,
-                               else 2), 1 linear coarse periodic solve at u = 0, 2 zero */
+                               else 2), 1 linear coarse periodic solve at u = 0, 2 zero,
+                               3 one fine sweep from rest, U^0_n = F_n(0) (for strongly
+                               saturating designs, where a first correction from zero can
+                               overshoot) */
     int32_t precision;      /* 0: FP64 fine solves; 1: FP32 PCG refined by FP64 Newton */
     double tol_ppc;         /* stop when ||J||_F / ||U||_F <= tol_ppc */
     int32_t max_iters;      /* maximum coarse corrections */
@@ -125,6 +128,10 @@ typedef struct {
                                graphs (fine sweep + jumps; coarse correction), captured at the
                                second iteration; 0 = eager launches.  Same kernels, same results */
     int32_t reserved[3];
+    double b_cap;           /* coarse-correction safeguard (T): 0 = off; > 0 = apply
+                               U += theta dU with the largest theta <= 1 that keeps |B| <= b_cap
+                               in every Brauer element and sample, when the full correction
+                               would exceed it (a frozen linear coarse model cannot saturate) */
 } ppc_params;
 
 /* Counters and timings of the last solve (all chains, all iterations). */
@@ -146,7 +153,7 @@ typedef struct {
     double jump;                 /* ||U_0 - F_N(U_{N-1})|| of the last sweep (eq. (4), n=0) */
     double eps;                  /* last ||J||_F / ||U||_F */
     double max_b_steel;          /* max |B| over nonlinear elements at the returned U (T) */
-    int32_t n_free, nnz, n_tri, reserved_i;
+    int32_t n_free, nnz, n_tri, damped;   /* damped: corrections the b_cap safeguard scaled */
     int64_t resid_total;         /* residual evaluations (element + node passes) */
     int64_t steps_total;         /* implicit-Euler steps taken over every chain */
 } ppc_stats;
@@ -157,7 +164,7 @@ int ppc_version(void);
 /* Defaults: T = 0.02, N = 10, m = 20, shift 0, lin 0, init 0, FP64, tol_ppc 1e-12,
  * max_iters 60, tol_newton 1e-13, max_newton 50, tol_lin 1e-8, max_lin 20000,
  * tol_cocg 1e-10, max_cocg 20000, block 0, predictor on, lin_point 1 (fine results),
- * coarse_precision -1, graph 1.
+ * coarse_precision -1, graph 1, b_cap 0.
  * Returns PPC_ERR_ARG on a null pointer. */
 int ppc_params_default(ppc_params* p);
 

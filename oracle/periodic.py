@@ -27,6 +27,7 @@ import numpy as np
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
+from .fe import BRAUER
 from .timestep import NEWTON_TOL, fine_propagate, ie_step
 
 
@@ -174,20 +175,24 @@ def excitation_rows(fe, N, T):
     return np.outer(fe.prob.current(t), fe.F)
 
 
-def initial_iterate(fe, shift="ie", lin="tensor", mode="auto"):
+def initial_iterate(fe, shift="ie", lin="tensor", mode="auto", pool=None):
     """U^0 (the paper does not state it; reading).
 
     mode "coarse": the coarse periodic solution with zero right-hand side b in
     eqs. (9)-(10), i.e. G U = [f(T_N), f(T_1), ..., f(T_{N-1})], with the coarse
-    stiffness at u = 0.  mode "zero": U^0 = 0.  mode "auto": "coarse" when every
-    material is linear, else "zero" -- at u = 0 a Brauer material has its
-    unsaturated reluctivity, and a coarse solve with it can put tens of tesla into
-    the steel, where exp(k2 b^2) overflows."""
+    stiffness at u = 0.  mode "zero": U^0 = 0.  mode "fine": one fine sweep from zero,
+    U^0_n = F_n(0) -- every subinterval starts from rest, so the samples carry the
+    saturation the fine propagator produces instead of the one a linearisation predicts.
+    mode "auto": "coarse" when every material is linear, else "zero" -- at u = 0 a
+    Brauer material has its unsaturated reluctivity, and a coarse solve with it can put
+    tens of tesla into the steel, where exp(k2 b^2) overflows."""
     prob = fe.prob
     if mode == "auto":
         mode = "coarse" if np.all(prob.mat_model[np.unique(prob.mat_id)] == 0) else "zero"
     if mode == "zero":
         return np.zeros((prob.N, fe.n))
+    if mode == "fine":
+        return fine_sweep(fe, np.zeros((prob.N, fe.n)), pool=pool)
     if mode != "coarse":
         raise ValueError(mode)
     Kbar = coarse_stiffness(fe, np.zeros((1, fe.n)), lin)
@@ -255,8 +260,28 @@ def coarse_correction(fe, U, J, shift="ie", lin="tensor", U_lin=None):
     return harmonic_solve(fe, Kbar, R, T, shift)
 
 
+def brauer_bmax(fe, U):
+    """max |B| over the Brauer elements and the samples (rows) of U (0 without steel)."""
+    mask = fe.model == BRAUER
+    if not np.any(mask):
+        return 0.0
+    return max(math.sqrt(fe.element_state(u)[2][mask].max()) for u in U)
+
+
+def safeguard_step(fe, U, dU, b_cap):
+    """Step theta of the correction U + theta dU (a safeguard of this build; the paper's
+    coarse problem is not a frozen linearisation): theta = 1 when max |B(U + dU)| <= b_cap,
+    else (b_cap - b_U) / (b_new - b_U) with b_U = max |B(U)|, the largest step for which
+    |B| stays below the cap (B is linear in u, so |B(U + theta dU)| <= (1 - theta) b_U +
+    theta b_new), or 1/2 if U itself exceeds the cap."""
+    bu, bn = brauer_bmax(fe, U), brauer_bmax(fe, U + dU)
+    if bn <= b_cap:
+        return 1.0
+    return (b_cap - bu) / (bn - bu) if bu < b_cap else 0.5
+
+
 def ppc(fe, tol=1e-12, max_iter=60, U_init=None, shift="ie", lin="tensor",
-        newton_tol=NEWTON_TOL, pool=None, callback=None, init="auto", lin_point="F"):
+        newton_tol=NEWTON_TOL, pool=None, callback=None, init="auto", lin_point="F", b_cap=None):
     """Plain PP-PC (eq. (4)).
 
     lin_point selects the samples the frozen coarse stiffness is linearised at: "U" the
@@ -266,11 +291,12 @@ def ppc(fe, tol=1e-12, max_iter=60, U_init=None, shift="ie", lin="tensor",
     Per iteration k: fine sweep F_n(U_{n-1}^k); jumps J_n = F_n - U^k_{n mod N};
     eps^k = ||J||_F/||U^k||_F (the paper does not state the tolerance quantity; this
     is the reading); stop and return U^k if eps^k <= tol; else apply the coarse
-    correction.  Returns (U, eps_history, iterations) where iterations counts the
-    corrections applied (fine sweeps = iterations + 1)."""
+    correction, scaled by safeguard_step when b_cap is given.  Returns (U, eps_history,
+    iterations) where iterations counts the corrections applied (fine sweeps =
+    iterations + 1)."""
     prob = fe.prob
     if U_init is None:
-        U = initial_iterate(fe, shift, lin, init)
+        U = initial_iterate(fe, shift, lin, init, pool=pool)
     else:
         U = np.array(U_init, dtype=np.float64, copy=True)
     hist = []
@@ -285,7 +311,8 @@ def ppc(fe, tol=1e-12, max_iter=60, U_init=None, shift="ie", lin="tensor",
             return U, np.array(hist), k
         if k == max_iter:
             break
-        U = U + coarse_correction(fe, U, J, shift, lin, U_lin=Fs if lin_point == "F" else None)
+        dU = coarse_correction(fe, U, J, shift, lin, U_lin=Fs if lin_point == "F" else None)
+        U = U + (safeguard_step(fe, U, dU, b_cap) * dU if b_cap else dU)
     raise RuntimeError(f"PP-PC did not converge: eps history {hist[-5:]}")
 
 

@@ -51,7 +51,7 @@ class Params(ctypes.Structure):
                 ("max_newton", c_int32), ("tol_lin", c_double), ("max_lin", c_int32),
                 ("tol_cocg", c_double), ("max_cocg", c_int32), ("block", c_int32),
                 ("no_predictor", c_int32), ("lin_point", c_int32), ("coarse_precision", c_int32),
-                ("graph", c_int32), ("reserved", c_int32 * 3)]
+                ("graph", c_int32), ("reserved", c_int32 * 3), ("b_cap", c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -61,11 +61,11 @@ class Stats(ctypes.Structure):
                 ("cocg_max", c_int32), ("lin_capped", c_int32), ("fine_ms", c_double),
                 ("coarse_ms", c_double), ("total_ms", c_double), ("jump", c_double),
                 ("eps", c_double), ("max_b_steel", c_double), ("n_free", c_int32),
-                ("nnz", c_int32), ("n_tri", c_int32), ("reserved_i", c_int32),
+                ("nnz", c_int32), ("n_tri", c_int32), ("damped", c_int32),
                 ("resid_total", c_int64), ("steps_total", c_int64)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved_i"}
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 # name -> (restype, argtypes); every symbol declared in include/ppcmh.h

@@ -275,6 +275,24 @@ int solve_device(ppc_handle* h, ppc_problem* pr, const ppc_params* p, const doub
         if (mode == 0) mode = d.nonlinear ? 2 : 1;
         if (mode == 2) {
             fill(w.U, (long)N * n, 0.0, s);
+        } else if (mode == 3) {
+            // one fine sweep from rest: U^0_n = F_n(0)
+            fill(w.U, (long)N * n, 0.0, s);
+            PPC_HIP(hipEventRecord(ev[0], s));
+            launch_fine_sweep(pr, p, w.U, w.F, s);
+            PPC_HIP(hipEventRecord(ev[1], s));
+            const SweepCounts c = read_chain_counts(pr, N, s, nullptr, nullptr);  // synchronises
+            S.fine_launches++;
+            S.fine_ms += elapsed(ev[0], ev[1]);
+            S.newton_total += c.newton;
+            S.lin_total += c.lin;
+            S.newton_max = std::max(S.newton_max, c.newton_max);
+            S.lin_max = std::max(S.lin_max, c.lin_max);
+            S.lin_capped += c.capped;
+            S.resid_total += c.resid;
+            S.steps_total += (int64_t)N * p->m;
+            check_sweep(c);
+            PPC_HIP(hipMemcpyAsync(w.U, w.F, sizeof(double) * (size_t)N * n, hipMemcpyDeviceToDevice, s));
         } else {
             launch_coarse(pr, p, nullptr, nullptr, w.U, false, true, s);
             read_cocg(pr, H, s, nullptr, &S.cocg_total, &S.cocg_max);
@@ -295,7 +313,15 @@ int solve_device(ppc_handle* h, ppc_problem* pr, const ppc_params* p, const doub
         PPC_HIP(hipMemcpyAsync(w.host_fcount, w.fcount, 8 * (size_t)N * sizeof(int), hipMemcpyDeviceToHost, s));
     };
     auto coarse_ops = [&]() {
-        launch_coarse(pr, p, p->lin_point == 1 ? w.F : w.U, w.J, w.U, true, false, s);
+        const double* lin = p->lin_point == 1 ? w.F : w.U;
+        if (p->b_cap > 0.0) {
+            // correction into w.R (free after the DFT), then the safeguarded update
+            launch_coarse(pr, p, lin, w.J, w.R, false, false, s);
+            launch_safeguarded_update(pr, N, p->b_cap, w.R, w.U, w.scal + 8, s);
+            PPC_HIP(hipMemcpyAsync(w.host_scal + 8, w.scal + 8, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+        } else {
+            launch_coarse(pr, p, lin, w.J, w.U, true, false, s);
+        }
         PPC_HIP(hipMemcpyAsync(w.host_ccount, w.ccount, 4 * (size_t)H * sizeof(int), hipMemcpyDeviceToHost, s));
     };
     auto run = [&](GraphExec& g, int k, auto& ops) {
@@ -340,6 +366,7 @@ int solve_device(ppc_handle* h, ppc_problem* pr, const ppc_params* p, const doub
         PPC_HIP(hipEventRecord(ev[3], s));
         PPC_HIP(hipStreamSynchronize(s));
         parse_cocg(w.host_ccount, H, nullptr, &S.cocg_total, &S.cocg_max);
+        if (p->b_cap > 0.0 && w.host_scal[8] < 1.0) S.damped++;
         S.coarse_ms += elapsed(ev[2], ev[3]);
         S.coarse_solves++;
     }
@@ -414,7 +441,15 @@ int solve_batch_device(ppc_handle* h, ppc_problem* bp, const ppc_params* p, cons
                               excitation ? nullptr : w.J, excitation, s);
         }
         launch_cocg_batch(parts, list, p, static_cast<CocgArgs*>(cargs.p), static_cast<int2*>(cwork.p), cw, s);
-        for (int d : list) launch_coarse_post(parts[d], p, parts[d]->ws.U, !excitation, s);
+        for (int d : list) {
+            Workspace& w = parts[d]->ws;
+            if (!excitation && p->b_cap > 0.0) {
+                launch_coarse_post(parts[d], p, w.R, false, s);
+                launch_safeguarded_update(parts[d], N, p->b_cap, w.R, w.U, w.scal + 8, s);
+            } else {
+                launch_coarse_post(parts[d], p, w.U, !excitation, s);
+            }
+        }
         for (int d : list) {
             PPC_HIP(hipMemcpyAsync(ccount.data(), parts[d]->ws.ccount, ccount.size() * sizeof(int),
                                    hipMemcpyDeviceToHost, s));
@@ -426,12 +461,35 @@ int solve_batch_device(ppc_handle* h, ppc_problem* bp, const ppc_params* p, cons
                 S.cocg_total += ccount[4 * q + 1];
                 S.cocg_max = std::max(S.cocg_max, ccount[4 * q + 1]);
             }
+            if (!excitation && p->b_cap > 0.0) {
+                double theta = 1.0;
+                PPC_HIP(hipMemcpy(&theta, parts[d]->ws.scal + 8, sizeof(double), hipMemcpyDeviceToHost));
+                if (theta < 1.0) S.damped++;
+            }
         }
         S.coarse_solves++;
     };
 
+    // chain counters of design d's last sweep into the stats; fails on a chain's status
+    auto take_counts = [&](int d) {
+        PPC_HIP(hipMemcpy(counts.data(), parts[d]->ws.fcount, counts.size() * sizeof(int), hipMemcpyDeviceToHost));
+        for (int c = 0; c < N; ++c) {
+            const int* q = counts.data() + 8 * c;
+            if (q[0] != 0)
+                fail(q[0], "design " + std::to_string(d) + ", fine chain " + std::to_string(c + 1) +
+                               " failed at step " + std::to_string(q[6]));
+            S.newton_total += q[1];
+            S.lin_total += q[2];
+            S.newton_max = std::max(S.newton_max, q[3]);
+            S.lin_max = std::max(S.lin_max, q[4]);
+            S.lin_capped += q[5];
+            S.resid_total += q[7];
+        }
+        S.steps_total += (int64_t)N * p->m;
+    };
+
     // initial iterate per design
-    std::vector<int> coarse_init;
+    std::vector<int> coarse_init, fine_init;
     for (int d = 0; d < D; ++d) {
         Workspace& w = parts[d]->ws;
         const long cnt = (long)N * parts[d]->mesh.n_free;
@@ -440,14 +498,32 @@ int solve_batch_device(ppc_handle* h, ppc_problem* bp, const ppc_params* p, cons
         } else {
             int mode = p->init_mode;
             if (mode == 0) mode = parts[d]->mesh.nonlinear ? 2 : 1;
-            if (mode == 2) fill(w.U, cnt, 0.0, s);
-            else coarse_init.push_back(d);
+            if (mode == 2 || mode == 3) fill(w.U, cnt, 0.0, s);
+            if (mode == 3) fine_init.push_back(d);
+            if (mode == 1) coarse_init.push_back(d);
         }
     }
     coarse(coarse_init, true);
 
     FineBatch fb;
     fine_batch_prepare(fb, parts, p, s);
+    if (!fine_init.empty()) {
+        // one fine sweep from rest for these designs: U^0_n = F_n(0)
+        std::vector<char> from_rest(D, 0);
+        for (int d : fine_init) from_rest[d] = 1;
+        PPC_HIP(hipEventRecord(ev[0], s));
+        fine_batch_launch(fb, from_rest, s);
+        PPC_HIP(hipEventRecord(ev[1], s));
+        PPC_HIP(hipStreamSynchronize(s));
+        S.fine_launches++;
+        S.fine_ms += elapsed(ev[0], ev[1]);
+        for (int d : fine_init) {
+            take_counts(d);
+            Workspace& w = parts[d]->ws;
+            PPC_HIP(hipMemcpyAsync(w.U, w.F, sizeof(double) * (size_t)N * parts[d]->mesh.n_free,
+                                   hipMemcpyDeviceToDevice, s));
+        }
+    }
     std::vector<char> active(D, 1);
     std::vector<int> iters(D, p->max_iters);
     int status = PPC_OK;
@@ -468,20 +544,7 @@ int solve_batch_device(ppc_handle* h, ppc_problem* bp, const ppc_params* p, cons
         std::vector<int> corr;
         for (int d = 0; d < D; ++d) {
             if (!active[d]) continue;
-            PPC_HIP(hipMemcpy(counts.data(), parts[d]->ws.fcount, counts.size() * sizeof(int), hipMemcpyDeviceToHost));
-            for (int c = 0; c < N; ++c) {
-                const int* q = counts.data() + 8 * c;
-                if (q[0] != 0)
-                    fail(q[0], "design " + std::to_string(d) + ", fine chain " + std::to_string(c + 1) +
-                                   " failed at step " + std::to_string(q[6]));
-                S.newton_total += q[1];
-                S.lin_total += q[2];
-                S.newton_max = std::max(S.newton_max, q[3]);
-                S.lin_max = std::max(S.lin_max, q[4]);
-                S.lin_capped += q[5];
-                S.resid_total += q[7];
-            }
-            S.steps_total += (int64_t)N * p->m;
+            take_counts(d);
             const double jj = hs[3 * d], uu = hs[3 * d + 1];
             if (!std::isfinite(jj)) fail(PPC_ERR_NONFINITE, "design " + std::to_string(d) + ": non-finite jump norm");
             const double eps = uu > 0.0 ? std::sqrt(jj) / std::sqrt(uu) : (jj == 0.0 ? 0.0 : INFINITY);
@@ -648,6 +711,7 @@ int ppc_params_default(ppc_params* p) {
     p->lin_point = 1;
     p->coarse_precision = -1;
     p->graph = 1;
+    p->b_cap = 0.0;
     return PPC_OK;
 }
 

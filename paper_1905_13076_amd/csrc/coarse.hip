@@ -863,6 +863,74 @@ __global__ void k_max_b(int ne, int n, int N, const double* __restrict__ U, cons
     if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
+// Per block: max |B| over the Brauer elements and samples of U and of U + dU (pairs).
+__global__ void k_max_b_pair(int ne, int n, int N, const double* __restrict__ U, const double* __restrict__ dU,
+                             const int* __restrict__ efree, const double* __restrict__ gx,
+                             const double* __restrict__ gy, const int* __restrict__ mat,
+                             const double* __restrict__ lawtab, double* __restrict__ part) {
+    __shared__ double red[2][256];
+    double m0 = 0.0, m1 = 0.0;
+    const long total = (long)N * ne;
+    for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < total; k += (long)gridDim.x * blockDim.x) {
+        const long s = k / ne;
+        const int e = (int)(k - s * ne);
+        if (lawtab[5 * mat[e]] == 0.0) continue;
+        double ax = 0.0, ay = 0.0, bx = 0.0, by = 0.0;
+        for (int q = 0; q < 3; ++q) {
+            const int g = efree[q * ne + e];
+            const double u0 = g >= 0 ? U[s * n + g] : 0.0;
+            const double u1 = g >= 0 ? u0 + dU[s * n + g] : 0.0;
+            ax += gx[q * ne + e] * u0;
+            ay += gy[q * ne + e] * u0;
+            bx += gx[q * ne + e] * u1;
+            by += gy[q * ne + e] * u1;
+        }
+        m0 = fmax(m0, sqrt(ax * ax + ay * ay));
+        m1 = fmax(m1, sqrt(bx * bx + by * by));
+    }
+    red[0][threadIdx.x] = m0;
+    red[1][threadIdx.x] = m1;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            red[0][threadIdx.x] = fmax(red[0][threadIdx.x], red[0][threadIdx.x + w]);
+            red[1][threadIdx.x] = fmax(red[1][threadIdx.x], red[1][threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = red[0][0];
+        part[2 * blockIdx.x + 1] = red[1][0];
+    }
+}
+
+// Step of the safeguarded correction: with b_U = max |B(U)| and b_new = max |B(U + dU)|
+// over the Brauer elements, theta = 1 if b_new <= cap, else (cap - b_U) / (b_new - b_U)
+// (so that max |B(U + theta dU)| <= cap, B being linear in u), else 1/2 when U itself is
+// beyond the cap.  out = {theta, b_new, b_U}.
+__global__ void k_damp_theta(int nb, const double* __restrict__ part, double cap, double* __restrict__ out) {
+    if (threadIdx.x == 0) {
+        double bu = 0.0, bn = 0.0;
+        for (int b = 0; b < nb; ++b) {
+            bu = fmax(bu, part[2 * b]);
+            bn = fmax(bn, part[2 * b + 1]);
+        }
+        double theta = 1.0;
+        if (!(bn <= cap)) theta = bu < cap ? (cap - bu) / (bn - bu) : 0.5;
+        out[0] = theta;
+        out[1] = bn;
+        out[2] = bu;
+    }
+}
+
+// U += theta dU with theta read from the device
+__global__ void k_axpy_theta(long total, const double* __restrict__ theta, const double* __restrict__ dU,
+                             double* __restrict__ U) {
+    const double t = theta[0];
+    for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < total; k += (long)gridDim.x * blockDim.x)
+        U[k] += t * dU[k];
+}
+
 __global__ void k_max_partials(int nb, const double* __restrict__ part, double* __restrict__ out) {
     if (threadIdx.x == 0) {
         double m = 0.0;
@@ -1073,6 +1141,18 @@ void launch_to_free(const ppc_problem* pr, int N, const double* Unodal, double* 
     const DeviceMesh& d = pr->mesh;
     hipLaunchKernelGGL(k_gather_free, dim3(1024), dim3(256), 0, s, d.n_free, d.n_nodes, N, d.free_node,
                        Unodal, Ufree);
+    PPC_HIP(hipGetLastError());
+}
+
+// U += theta dU with the safeguard step of k_damp_theta; out3 = {theta, b_new, b_U}.
+void launch_safeguarded_update(ppc_problem* pr, int N, double cap, const double* dU, double* U,
+                               double* out3, hipStream_t s) {
+    const DeviceMesh& d = pr->mesh;
+    hipLaunchKernelGGL(k_max_b_pair, dim3(kRedBlocks), dim3(256), 0, s, d.n_tri, d.n_free, N, U, dU, d.efree,
+                       d.gx, d.gy, d.mat, pr->lawtab, pr->ws.partial);
+    hipLaunchKernelGGL(k_damp_theta, dim3(1), dim3(64), 0, s, kRedBlocks, pr->ws.partial, cap, out3);
+    const long total = (long)N * d.n_free;
+    hipLaunchKernelGGL(k_axpy_theta, dim3(1024), dim3(256), 0, s, total, out3, dU, U);
     PPC_HIP(hipGetLastError());
 }
 

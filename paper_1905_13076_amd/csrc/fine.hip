@@ -227,7 +227,7 @@ __device__ inline S tail_row_sum(const FineArgs& a, const S* __restrict__ jv, PV
 template <typename S, int R, int B>
 __device__ int pcg_regs(const FineArgs& a, const S* __restrict__ jv, S* __restrict__ p_l,
                         S* __restrict__ r_l, const float* __restrict__ d_l, S* __restrict__ tq_l,
-                        const double* __restrict__ Rres, S* __restrict__ xout, double tgt,
+                        const double* __restrict__ Rres, double rs, S* __restrict__ xout, double tgt,
                         S* lds_s, int& ph) {
     const int tid = threadIdx.x, n = a.n;
     const int lane = tid & 63, wave = tid >> 6, nw = B >> 6;
@@ -253,7 +253,7 @@ __device__ int pcg_regs(const FineArgs& a, const S* __restrict__ jv, S* __restri
         x[k] = 0;
         q[k] = 0;
         if (i < n) {
-            const S rv = (S)(-Rres[i]);
+            const S rv = (S)(-Rres[i] * rs);
             const S z = (S)d_l[i] * rv;
             r_l[i] = rv;
             p_l[i] = z;
@@ -365,7 +365,7 @@ __device__ int pcg_regs(const FineArgs& a, const S* __restrict__ jv, S* __restri
 template <typename S, int LP>
 __device__ int pcg_mem(const FineArgs& a, const S* __restrict__ jv, S* __restrict__ pv,
                        S* __restrict__ pl, S* __restrict__ dl, const double* __restrict__ Rres,
-                       double tgt, S* lds_s, int& ph) {
+                       double rs, double tgt, S* lds_s, int& ph) {
     const int B = blockDim.x, tid = threadIdx.x, n = a.n;
     const int lane = tid & 63, wave = tid >> 6, nw = B >> 6;
     const long NP = a.ell_pad;
@@ -378,7 +378,7 @@ __device__ int pcg_mem(const FineArgs& a, const S* __restrict__ jv, S* __restric
     const S* pd = LP == 2 ? dl : pv + P_D * VP;
     S loc[2] = {0, 0};
     for (int i = tid; i < n; i += B) {
-        const S rv = (S)(-Rres[i]);
+        const S rv = (S)(-Rres[i] * rs);
         const S z = pd[i] * rv;
         pr[i] = rv;
         pp[i] = z;
@@ -552,11 +552,16 @@ __device__ __forceinline__ void fine_chain(const FineArgs& a, const int c, unsig
             }
             __syncthreads();
             const double ltarget = fmax(a.tol_lin * rn, 0.5 * target);
+            // FP32 PCG solves for the unit right-hand side -R/||R|| (near convergence the
+            // residual and its products would fall below FP32's range); the step px * xs
+            // is formed in FP64.  FP64 solves use R itself.
+            const double rs = (sizeof(S) == 4 && rn > 0.0) ? 1.0 / rn : 1.0;
+            const double xs = (sizeof(S) == 4 && rn > 0.0) ? rn : 1.0;
             int k;
             if constexpr (R > 0)
-                k = pcg_regs<S, R, BLOCK>(a, jv, p_l, r_l, df_l, tq_l, R_, px, ltarget, lds_s, ph_s);
+                k = pcg_regs<S, R, BLOCK>(a, jv, p_l, r_l, df_l, tq_l, R_, rs, px, ltarget * rs, lds_s, ph_s);
             else
-                k = pcg_mem<S, LP>(a, jv, pv, p_l, d_l, R_, ltarget, lds_s, ph_s);
+                k = pcg_mem<S, LP>(a, jv, pv, p_l, d_l, R_, rs, ltarget * rs, lds_s, ph_s);
             __syncthreads();
             lin_total += k;
             lin_max = k > lin_max ? k : lin_max;
@@ -564,13 +569,13 @@ __device__ __forceinline__ void fine_chain(const FineArgs& a, const int c, unsig
             // ---- Newton update with backtracking -------------------------------------------
             double nrm[2] = {0.0, 0.0};
             for (int i = threadIdx.x; i < n; i += blockDim.x) {
-                const double dv = (double)px[i];
+                const double dv = (double)px[i] * xs;
                 nrm[0] += dv * dv;
                 nrm[1] += u[i] * u[i];
             }
             block_sum<double, 2>(nrm, lds_d, ph_d);
             if (sqrt(nrm[0]) <= 4.0 * DBL_EPSILON * sqrt(nrm[1])) {
-                for (int i = threadIdx.x; i < n; i += blockDim.x) u[i] = u[i] + (double)px[i];
+                for (int i = threadIdx.x; i < n; i += blockDim.x) u[i] = u[i] + (double)px[i] * xs;
                 __syncthreads();
                 ++it;
                 break;
@@ -579,7 +584,7 @@ __device__ __forceinline__ void fine_chain(const FineArgs& a, const int c, unsig
             double rt = 0.0;
             bool accepted = false, stalled = false;
             while (true) {
-                for (int i = threadIdx.x; i < n; i += blockDim.x) ut[i] = u[i] + lam * (double)px[i];
+                for (int i = threadIdx.x; i < n; i += blockDim.x) ut[i] = u[i] + lam * ((double)px[i] * xs);
                 __syncthreads();
                 nl_element_pass(a, ut, el);
                 ++resid_evals;
@@ -713,9 +718,9 @@ __device__ __forceinline__ void adjoint_chain(const FineArgs& a, const AdjArgs& 
         int k = 0;
         if (rn > 0.0) {
             if constexpr (R > 0)
-                k = pcg_regs<S, R, BLOCK>(a, jv, p_l, r_l, df_l, tq_l, rhs, px, b.tol_lin * rn, lds_s, ph_s);
+                k = pcg_regs<S, R, BLOCK>(a, jv, p_l, r_l, df_l, tq_l, rhs, 1.0, px, b.tol_lin * rn, lds_s, ph_s);
             else
-                k = pcg_mem<S, LP>(a, jv, pv, p_l, d_l, rhs, b.tol_lin * rn, lds_s, ph_s);
+                k = pcg_mem<S, LP>(a, jv, pv, p_l, d_l, rhs, 1.0, b.tol_lin * rn, lds_s, ph_s);
         } else {
             for (int i = threadIdx.x; i < n; i += blockDim.x) px[i] = 0;
         }

@@ -336,6 +336,8 @@ void launch_to_nodal(const ppc_problem* pr, int N, const double* Ufree, double* 
                      hipStream_t s);
 void launch_to_free(const ppc_problem* pr, int N, const double* Unodal, double* Ufree,
                     hipStream_t s);
+void launch_safeguarded_update(ppc_problem* pr, int N, double cap, const double* dU, double* U,
+                               double* out3, hipStream_t s);
 void launch_max_b(ppc_problem* pr, int N, const double* U, double* out, hipStream_t s);
 
 }  // namespace ppc

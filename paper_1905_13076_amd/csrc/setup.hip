@@ -128,9 +128,10 @@ int validate_params(const ppc_params* p, std::string& msg) {
     if (p->m < 1) { msg = "m must be >= 1"; return PPC_ERR_ARG; }
     if (p->shift_mode < 0 || p->shift_mode > 1) { msg = "shift_mode must be 0 or 1"; return PPC_ERR_ARG; }
     if (p->lin_mode < 0 || p->lin_mode > 1) { msg = "lin_mode must be 0 or 1"; return PPC_ERR_ARG; }
-    if (p->init_mode < 0 || p->init_mode > 2) { msg = "init_mode must be 0, 1 or 2"; return PPC_ERR_ARG; }
+    if (p->init_mode < 0 || p->init_mode > 3) { msg = "init_mode must be 0, 1, 2 or 3"; return PPC_ERR_ARG; }
     if (p->precision < 0 || p->precision > 1) { msg = "precision must be 0 or 1"; return PPC_ERR_ARG; }
     if (p->graph < 0 || p->graph > 1) { msg = "graph must be 0 or 1"; return PPC_ERR_ARG; }
+    if (!(p->b_cap >= 0.0) || !std::isfinite(p->b_cap)) { msg = "b_cap must be finite and >= 0"; return PPC_ERR_ARG; }
     if (p->coarse_precision < -1 || p->coarse_precision > 1) {
         msg = "coarse_precision must be -1, 0 or 1";
         return PPC_ERR_ARG;

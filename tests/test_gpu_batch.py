@@ -24,11 +24,11 @@ def _designs():
     return out
 
 
-@pytest.mark.parametrize("prec", [0, 1])
-def test_batch_equals_single_design_solves(prec):
+@pytest.mark.parametrize("prec,init", [(0, 0), (1, 0), (0, 3)])
+def test_batch_equals_single_design_solves(prec, init):
     import paper_1905_13076_amd as P
     designs = _designs()
-    prm = P.problem_params(designs[0], precision=prec, tol_lin=1e-8 if prec == 0 else 1e-4)
+    prm = P.problem_params(designs[0], precision=prec, tol_lin=1e-8 if prec == 0 else 1e-4, init_mode=init)
     singles = []
     for d, prob in enumerate(designs):
         banner(f"batch: single design {d} n_nodes={prob.n_nodes} prec={prec}")

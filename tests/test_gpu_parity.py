@@ -159,6 +159,54 @@ def test_c5small_nonlinear_fp64_matches_oracle():
     assert e <= 1e-10
 
 
+def test_c5small_start_from_rest_matches_oracle():
+    """U^0_n = F_n(0) (init_mode 3) on the GPU and in the oracle: same iteration count and
+    the same periodic state."""
+    import paper_1905_13076_amd as P
+    from oracle.fe import FE
+    from oracle import periodic
+    prob = coax.c5_small()
+    fe = FE(prob)
+    Uo, ho, ko = periodic.ppc(fe, tol=1e-12, init="fine")
+    banner("c5small from rest")
+    pr = _problem(prob)
+    prm = P.problem_params(prob, init_mode=3)
+    U, eps, k, st, rc = pr.solve(prm)
+    assert rc == 0
+    e = rel(free_rows(U.cpu().numpy(), fe.free), Uo)
+    banner(f"c5small from rest: iters={k} (oracle {ko}) rel={e:.2e} fine launches {st['fine_launches']}")
+    assert e <= 1e-10
+    assert abs(k - ko) <= 1
+    assert st["fine_launches"] == k + 2       # the sweep from rest, then one per iteration
+
+
+def test_safeguarded_corrections_match_oracle():
+    """The b_cap safeguard active on every late correction (cap below the solution's peak
+    field): the GPU takes the oracle's steps -- same iteration count, same fixed point --
+    and counts the scaled corrections."""
+    import paper_1905_13076_amd as P
+    from oracle.fe import FE
+    from oracle import periodic
+    from workloads.coax import AIR, Layer, SIGMA_CU, layered_coax, steel
+    layers = [Layer(1e-3, SIGMA_CU, 0, +1), Layer(2e-3, 0.0, 0), Layer(2.5e-3, SIGMA_CU, 0),
+              Layer(2.5e-3 + 0.74e-3, 1e6, 1)]
+    prob = layered_coax("tiny-saturating", layers, [AIR, steel()], 8, 16, 50.0, [1], [677.0], [0.0],
+                        0.02, 8, 6)
+    fe = FE(prob)
+    U0, _, _ = periodic.ppc(fe, tol=1e-11, init="fine")
+    cap = 0.75 * periodic.brauer_bmax(fe, U0)
+    Uo, ho, ko = periodic.ppc(fe, tol=1e-11, init="fine", b_cap=cap, max_iter=120)
+    banner(f"safeguard cap={cap:.3f} T, oracle iterations {ko}")
+    pr = _problem(prob)
+    prm = P.problem_params(prob, tol_ppc=1e-11, init_mode=3, b_cap=cap, max_iters=120)
+    U, eps, k, st, rc = pr.solve(prm)
+    assert rc == 0
+    e = rel(free_rows(U.cpu().numpy(), fe.free), Uo)
+    banner(f"safeguard: iters={k} (oracle {ko}) rel={e:.2e} damped={st['damped']}")
+    assert e <= 1e-10 and k == ko
+    assert st["damped"] > 0
+
+
 def test_c2_nonlinear_fp64_matches_oracle():
     """C2, the benchmark workload (nr = 60 x ntheta = 120, steel sheath, N = 40 x 50,
     21 harmonics, FP64), in the launch configuration bench.py times: full PP-PC on the GPU

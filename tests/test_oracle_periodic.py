@@ -134,8 +134,10 @@ def test_c1_routes_agree():
     UL, _ = periodic.route_l(fe)
     US, periods = periodic.route_s(fe, tol=1e-14)
     UP, hist, k = periodic.ppc(fe, tol=1e-12)
+    UF, _, _ = periodic.ppc(fe, tol=1e-12, init="fine")
     assert rel(US, UL) <= 1e-12
     assert rel(UP, UL) <= 1e-12
+    assert rel(UF, UL) <= 1e-12
     assert k <= 10 and np.all(np.diff(np.log(hist)) < 0)   # monotone contraction
 
 
@@ -162,7 +164,8 @@ def test_nonlinear_routes_and_variants_share_the_fixed_point():
     """Nonlinear (saturating Brauer sheath): sequential periods and PP-PC from U^0 = 0
     with the exact shift, the harmonic-balance shift and the chord linearisation all
     reach one periodic solution, as does linearising the coarse stiffness at the fine
-    results instead of the iterate; only iteration counts differ."""
+    results instead of the iterate, and starting from one fine sweep from rest
+    (U^0_n = F_n(0)); only iteration counts differ."""
     fe = _tiny_nl(nr=6, ntheta=12, N=8, m=5, amp=400.0)
     US, _ = periodic.route_s(fe, tol=1e-14)
     _, _, b2, _, _ = fe.element_state(US[2])
@@ -172,6 +175,7 @@ def test_nonlinear_routes_and_variants_share_the_fixed_point():
         "iw": periodic.ppc(fe, tol=1e-12, init="zero", shift="iw"),
         "chord": periodic.ppc(fe, tol=1e-12, init="zero", lin="chord"),
         "at-F": periodic.ppc(fe, tol=1e-12, init="zero", lin_point="F"),
+        "from-rest": periodic.ppc(fe, tol=1e-12, init="fine"),
     }
     for name, (U, hist, k) in runs.items():
         assert rel(U, US) <= 1e-10, name
@@ -191,3 +195,41 @@ def test_epsilon_definition():
     assert periodic.periodicity_residual(U, 0.5 * U) == pytest.approx(0.5)
     assert periodic.periodicity_residual(0 * U, U) == float("inf")
     assert periodic.periodicity_residual(0 * U, 0 * U) == 0.0
+
+
+def _tiny_saturating(nr=8, N=8, m=6):
+    """A thin, strongly driven steel sheath (the batched-designs family) on a small grid."""
+    from workloads.coax import AIR, Layer, SIGMA_CU, layered_coax, steel
+    t = 0.74e-3
+    layers = [Layer(1e-3, SIGMA_CU, 0, +1), Layer(2e-3, 0.0, 0), Layer(2.5e-3, SIGMA_CU, 0),
+              Layer(2.5e-3 + t, 1e6, 1)]
+    return FE(layered_coax("tiny-saturating", layers, [AIR, steel()], nr, 2 * nr, 50.0, [1],
+                           [677.0], [0.0], 0.02, N, m))
+
+
+def test_safeguard_step_meets_the_cap_exactly_along_the_iterate():
+    """B is linear in u: for dU = c U the scaled correction U + theta dU has max |B| equal
+    to the cap (theta = (cap - b_U)/(b_new - b_U)); no scaling when the cap is not met."""
+    fe = _tiny_saturating()
+    rng = np.random.default_rng(3)
+    U = 1e-4 * rng.standard_normal((fe.prob.N, fe.n))
+    bu = periodic.brauer_bmax(fe, U)
+    dU = 2.0 * U                                      # b_new = 3 b_U
+    cap = 2.0 * bu
+    th = periodic.safeguard_step(fe, U, dU, cap)
+    assert th == pytest.approx(0.5, rel=1e-12)
+    assert periodic.brauer_bmax(fe, U + th * dU) == pytest.approx(cap, rel=1e-12)
+    assert periodic.safeguard_step(fe, U, dU, 3.5 * bu) == 1.0
+
+
+def test_safeguarded_ppc_reaches_the_unguarded_fixed_point():
+    """With a cap below the solution's own peak field the safeguard scales every late
+    correction (theta = 1/2 once the iterate sits above the cap), which slows PP-PC but
+    leaves its fixed point unchanged."""
+    fe = _tiny_saturating()
+    U0, h0, k0 = periodic.ppc(fe, tol=1e-11, init="fine")
+    bpeak = periodic.brauer_bmax(fe, U0)
+    assert bpeak > 1.5
+    U1, h1, k1 = periodic.ppc(fe, tol=1e-11, init="fine", b_cap=0.75 * bpeak, max_iter=120)
+    assert rel(U1, U0) <= 1e-9
+    assert k1 > k0
