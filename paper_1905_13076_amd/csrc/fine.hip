@@ -237,6 +237,7 @@ __device__ int pcg_regs(const FineArgs& a, const S* __restrict__ jv, S* __restri
     unsigned tailmask = 0;
     const __amdgpu_buffer_rsrc_t rv_j = buffer_rsrc(jv, (unsigned)(W * NP * sizeof(S)));
     const __amdgpu_buffer_rsrc_t rv_c = buffer_rsrc(a.ecol16, (unsigned)(W * NP * 2));
+    const __amdgpu_buffer_rsrc_t rv_cp = buffer_rsrc(a.ecolp, (unsigned)(((W + 1) / 2) * NP * 4));
     // One tail row of at most B entries (the usual case): every thread takes one of its
     // entries and the first block reduction of an iteration carries the row's product
     // with p.q, so no wave runs a serial row sum.  Otherwise one wave per tail row.
@@ -270,36 +271,78 @@ __device__ int pcg_regs(const FineArgs& a, const S* __restrict__ jv, S* __restri
         // this thread's tail entry: loads issued first, used after the ELL rounds
         const S tv = buffer_load<S>(rv_tv, tid < t_len ? tid * (unsigned)sizeof(S) : kBufferNone);
         const unsigned tc = (unsigned)__builtin_amdgcn_raw_buffer_load_b32(rv_tc, tid < t_len ? tid * 4u : kBufferNone, 0, 0);
-        // ELL rows, slot-major: U slots of all R row groups per round (U R = 8 loads of
-        // each stream in flight), all LDS gathers of a round issued before its FMAs.
-        // Every load is issued: rows >= n load nothing and slots >= W fall past the ELL
-        // arrays, both reading value 0 and column 0; tail rows hold zero values and
-        // column 0.  Every row adds its slots in order 0..W-1, then exact zeros.
-        constexpr int U = R >= 8 ? 1 : 8 / R;
+        // ELL rows, slot-major, all LDS gathers of a round issued before its FMAs.  Every
+        // load is issued: rows >= n load nothing and slots >= W fall past the ELL arrays,
+        // both reading value 0 and column 0; tail rows hold zero values and column 0.
+        // Every row adds its slots in order 0..W-1, then exact zeros.
 #pragma unroll
         for (int k = 0; k < R; ++k) q[k] = 0;
-        for (int w0 = 0; w0 < W; w0 += U) {
-            S v[U][R], pg[U][R];
-            unsigned col[U][R];
+        if constexpr (sizeof(S) == 4) {
+            // FP32: slot pairs, one 32-bit load bringing the columns of slots 2w (low half)
+            // and 2w+1 (high half), so a pair costs two value loads and one column load
+            // per row; UP pairs of all R row groups per round (at most 4 pairs in flight).
+            constexpr int UP = R >= 4 ? 1 : 4 / R;
+            const int W2 = (W + 1) / 2;
+            for (int w2 = 0; w2 < W2; w2 += UP) {
+                S v0[UP][R], v1[UP][R], g0[UP][R], g1[UP][R];
+                unsigned cw[UP][R];
 #pragma unroll
-            for (int u = 0; u < U; ++u)
+                for (int u = 0; u < UP; ++u)
 #pragma unroll
-                for (int k = 0; k < R; ++k) {
-                    const int i = tid + k * B;
-                    const unsigned e = (unsigned)((w0 + u) * NP + i);
-                    v[u][k] = buffer_load<S>(rv_j, i < n ? e * (unsigned)sizeof(S) : kBufferNone);
-                    col[u][k] = __builtin_amdgcn_raw_buffer_load_b16(rv_c, i < n ? e * 2u : kBufferNone, 0, 0);
-                }
-            __builtin_amdgcn_sched_barrier(0);
+                    for (int k = 0; k < R; ++k) {
+                        const int i = tid + k * B;
+                        const unsigned e0 = (unsigned)((2 * (w2 + u)) * NP + i);
+                        const unsigned ep = (unsigned)((w2 + u) * NP + i);
+                        v0[u][k] = buffer_load<S>(rv_j, i < n ? e0 * (unsigned)sizeof(S) : kBufferNone);
+                        v1[u][k] = buffer_load<S>(rv_j, i < n ? (e0 + (unsigned)NP) * (unsigned)sizeof(S) : kBufferNone);
+                        cw[u][k] = (unsigned)__builtin_amdgcn_raw_buffer_load_b32(rv_cp, i < n ? ep * 4u : kBufferNone, 0, 0);
+                    }
+                __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int u = 0; u < U; ++u)
+                for (int u = 0; u < UP; ++u)
 #pragma unroll
-                for (int k = 0; k < R; ++k) pg[u][k] = p_l[col[u][k]];
-            __builtin_amdgcn_sched_barrier(0);
+                    for (int k = 0; k < R; ++k) {
+                        g0[u][k] = p_l[cw[u][k] & 0xffffu];
+                        g1[u][k] = p_l[cw[u][k] >> 16];
+                    }
+                __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int u = 0; u < U; ++u)
+                for (int u = 0; u < UP; ++u)
 #pragma unroll
-                for (int k = 0; k < R; ++k) q[k] += v[u][k] * pg[u][k];
+                    for (int k = 0; k < R; ++k) {
+                        q[k] += v0[u][k] * g0[u][k];
+                        q[k] += v1[u][k] * g1[u][k];
+                    }
+            }
+        } else {
+            // FP64: one slot of 16-bit columns at a time, U slots of all R row groups per
+            // round (U R = 8 loads of each stream in flight).  Packed column pairs measure
+            // no faster here: the FP64 value stream dominates and the wider rounds cost
+            // registers.
+            constexpr int U = R >= 8 ? 1 : 8 / R;
+            for (int w0 = 0; w0 < W; w0 += U) {
+                S v[U][R], pg[U][R];
+                unsigned col[U][R];
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+#pragma unroll
+                    for (int k = 0; k < R; ++k) {
+                        const int i = tid + k * B;
+                        const unsigned e = (unsigned)((w0 + u) * NP + i);
+                        v[u][k] = buffer_load<S>(rv_j, i < n ? e * (unsigned)sizeof(S) : kBufferNone);
+                        col[u][k] = __builtin_amdgcn_raw_buffer_load_b16(rv_c, i < n ? e * 2u : kBufferNone, 0, 0);
+                    }
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+#pragma unroll
+                    for (int k = 0; k < R; ++k) pg[u][k] = p_l[col[u][k]];
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+#pragma unroll
+                    for (int k = 0; k < R; ++k) q[k] += v[u][k] * pg[u][k];
+            }
         }
         S dot[2] = {0, 0};
 #pragma unroll
@@ -913,6 +956,7 @@ FineArgs make_fine_args(ppc_problem* pr, const ppc_params* p, const double* U, d
     a.ell_pad = (long)d.ell_pad;
     a.ecol = d.ecol;
     a.ecol16 = d.ecol16;
+    a.ecolp = d.ecolp;
     a.dpos = d.dpos;
     a.tail_row = d.tail_row;
     a.tail_ptr = d.tail_ptr;
