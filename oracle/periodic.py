@@ -317,12 +317,13 @@ def ppc(fe, tol=1e-12, max_iter=60, U_init=None, shift="ie", lin="tensor",
 
 
 def ppic(fe, tol=1e-12, max_iter=200, U_init=None, lin="tensor", newton_tol=NEWTON_TOL,
-         pool=None):
+         pool=None, callback=None):
     """PP-IC: eq. (4) with the periodic row relaxed as in eq. (5), U_0^{k+1} = U_N^k.
     The iterate holds U_0..U_N; rows n = 1..N follow the classical Parareal update
     U_n^{k+1} = F_n(U_{n-1}^k) + G_n(U_{n-1}^{k+1}) - G_n(U_{n-1}^k) with the
     implicit-Euler coarse propagator of eq. (8) on the frozen coarse stiffness.
-    eps^k uses the same jumps as ppc (row 0 compares F_N with U_0)."""
+    eps^k uses the same jumps as ppc (row 0 compares F_N with U_0).  callback(k, U, Fs,
+    eps) sees every iterate, as in ppc."""
     prob = fe.prob
     N, T = prob.N, prob.T
     dT = T / N
@@ -336,6 +337,8 @@ def ppic(fe, tol=1e-12, max_iter=200, U_init=None, lin="tensor", newton_tol=NEWT
         J = Fs - U
         eps = periodicity_residual(U, J)
         hist.append(eps)
+        if callback is not None:
+            callback(k, U, Fs, eps)
         if eps <= tol:
             return U, np.array(hist), k
         lu = spla.splu((C + coarse_stiffness(fe, U, lin)).tocsc())

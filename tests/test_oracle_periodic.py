@@ -190,6 +190,46 @@ def test_ppic_reaches_the_same_solution_more_slowly():
     assert ki > kp
 
 
+def test_ppic_with_coincident_propagators_steps_one_period_per_iteration():
+    """Linear problem with one fine step per subinterval (m = 1): the fine propagator and
+    the implicit-Euler coarse propagator of eq. (8) are the same map, so the update of
+    eq. (4) collapses to U_n^{k+1} = G(U_{n-1}^{k+1}) from U_0^{k+1} = U_N^k (eq. (5)).
+    Every PP-IC iteration then advances classical time stepping by exactly one period:
+    U^k_n = u((k-1) T + n dT) for the sequence started at u(0) = U^0_0."""
+    prob = coax.tiny(nr=5, ntheta=10, N=8, m=1)
+    fe = FE(prob)
+    N, dT = prob.N, prob.T / prob.N
+    seen = {}
+
+    class Enough(Exception):
+        pass
+
+    def keep(k, U, Fs, eps):
+        seen[k] = (U.copy(), eps)
+        if k == 4:
+            raise Enough
+
+    # from rest: the coarse periodic start would already be the fixed point when F = G
+    with pytest.raises(Enough):
+        periodic.ppic(fe, tol=0.0, U_init=np.zeros((N, fe.n)), callback=keep)
+    # the sequence of classical implicit-Euler steps of size dT, one direct solve each
+    A = (fe.M / dT + fe.jacobian_curl(np.zeros(fe.n))).tocsc()
+    lu = spla.splu(A)
+    u = seen[0][0][0].copy()
+    for k in range(1, 5):
+        rows = [u.copy()]
+        for n in range(1, N + 1):
+            u = lu.solve(fe.M @ u / dT + fe.f(((k - 1) * N + n) * dT))
+            rows.append(u.copy())
+        Uk = seen[k][0]
+        assert rel(Uk, np.array(rows[:N])) <= 1e-11, k
+        # eps^k is the periodicity defect of that period: ||u(kT) - u((k-1)T)|| / ||U^k||_F
+        assert seen[k][1] == pytest.approx(np.linalg.norm(rows[N] - rows[0]) / np.linalg.norm(Uk), rel=1e-9)
+    # the first period from rest still carries the transient (it has died out by the
+    # second), so the first two iterates differ and a wrong start row shows
+    assert seen[1][1] > 1e-3 and rel(seen[1][0], seen[2][0]) > 1e-3
+
+
 def test_epsilon_definition():
     U = np.ones((2, 3))
     assert periodic.periodicity_residual(U, 0.5 * U) == pytest.approx(0.5)
