@@ -127,7 +127,14 @@ typedef struct {
     int32_t graph;          /* single-design solves: 1 = each PP-PC iteration replays two HIP
                                graphs (fine sweep + jumps; coarse correction), captured at the
                                second iteration; 0 = eager launches.  Same kernels, same results */
-    int32_t reserved[3];
+    int32_t method;         /* 0 = PP-PC: eq. (4) with the periodic coarse problem of eqs.
+                               (9)-(14), solved per harmonic; 1 = PP-IC: eq. (4) with the
+                               periodicity of eq. (5), U_0^{k+1} = U_N^k, and the sequential
+                               implicit-Euler coarse propagator of eq. (8) on the frozen coarse
+                               stiffness at U^k (N real shifted solves per iteration, one after
+                               the other; lin_point and shift_mode do not apply).  PP-IC is for
+                               single-design solves without b_cap */
+    int32_t reserved[2];
     double b_cap;           /* coarse-correction safeguard (T): 0 = off; > 0 = apply
                                U += theta dU with the largest theta <= 1 that keeps |B| <= b_cap
                                in every Brauer element and sample, when the full correction
@@ -139,7 +146,8 @@ typedef struct {
     int32_t status;
     int32_t iterations;          /* coarse corrections applied (fine sweeps = iterations+1) */
     int32_t fine_launches;       /* fine-sweep kernel launches */
-    int32_t coarse_solves;       /* harmonic COCG launches */
+    int32_t coarse_solves;       /* COCG launches (PP-PC: one per correction over all
+                                    harmonics; PP-IC: N per correction) */
     int64_t newton_total;        /* Newton iterations over every chain and step */
     int64_t lin_total;           /* PCG iterations over every chain */
     int64_t cocg_total;          /* COCG iterations summed over harmonics */
@@ -164,7 +172,7 @@ int ppc_version(void);
 /* Defaults: T = 0.02, N = 10, m = 20, shift 0, lin 0, init 0, FP64, tol_ppc 1e-12,
  * max_iters 60, tol_newton 1e-13, max_newton 50, tol_lin 1e-8, max_lin 20000,
  * tol_cocg 1e-10, max_cocg 20000, block 0, predictor on, lin_point 1 (fine results),
- * coarse_precision -1, graph 1, b_cap 0.
+ * coarse_precision -1, graph 1, method 0, b_cap 0.
  * Returns PPC_ERR_ARG on a null pointer. */
 int ppc_params_default(ppc_params* p);
 
@@ -249,7 +257,7 @@ int ppc_solve_device(ppc_handle* h, ppc_problem* pr, const ppc_params* p,
  * from the checkpoint U_{n-1}) inside a PP-PC iteration whose coarse correction is the
  * harmonic solve of Section 3 applied to the time-reversed jumps.  The adjoint solves
  * are FP64 (relative tolerance 1e-12) whatever params->precision says; the adjoint
- * iteration stops at ||jumps|| / ||Lambda|| <= tol_ppc.
+ * iteration stops at ||jumps|| / ||Lambda|| <= tol_ppc (params->method does not apply).
  *   U_periodic  host, [N * n_nodes]: the converged coarse samples (checkpoints)
  *   loss        host scalar or null
  *   dsigma      host [n_tri] or null: dP/dsigma_e (per element)

@@ -90,7 +90,7 @@ float elapsed(hipEvent_t a, hipEvent_t b) {
 
 void workspace_free(Workspace& w) {
     void* ptrs[] = {w.fvec, w.fpcg, w.fjac, w.felem, w.jbase, w.ckm, w.fcount, w.U, w.F, w.J, w.R, w.kbar, w.kbar32,
-                    w.nubar, w.rhat, w.cwork, w.sig, w.ccount, w.twiddle, w.partial, w.scal};
+                    w.nubar, w.rhat, w.cwork, w.sig, w.ccount, w.twiddle, w.partial, w.scal, w.ic_e, w.ic_un};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (w.host_scal) (void)hipHostFree(w.host_scal);
@@ -128,7 +128,9 @@ void ensure_workspace(ppc_problem* pr, const ppc_params* p) {
     w.cwork = dalloc<double2>(H * 4 * w.n_pad);
     w.ckm = dalloc<double2>(w.vals_pad);
     w.sig = dalloc<double2>(H);
-    w.ccount = dalloc<int>(H * 4);
+    w.ccount = dalloc<int>(N * 4);
+    w.ic_e = dalloc<double>(d.n_free);
+    w.ic_un = dalloc<double>(d.n_free);
     w.twiddle = dalloc<double2>(N);
     w.partial = dalloc<double>(256 * 3);
     w.scal = dalloc<double>(16);
@@ -137,7 +139,7 @@ void ensure_workspace(ppc_problem* pr, const ppc_params* p) {
     w.host_scal = static_cast<double*>(hp);
     PPC_HIP(hipHostMalloc(&hp, 8 * N * sizeof(int), hipHostMallocDefault));
     w.host_fcount = static_cast<int*>(hp);
-    PPC_HIP(hipHostMalloc(&hp, 4 * H * sizeof(int), hipHostMallocDefault));
+    PPC_HIP(hipHostMalloc(&hp, 4 * N * sizeof(int), hipHostMallocDefault));
     w.host_ccount = static_cast<int*>(hp);
     w.N = p->N;
 }
@@ -305,6 +307,10 @@ int solve_device(ppc_handle* h, ppc_problem* pr, const ppc_params* p, const doub
     // its second use, and replayed; the first iteration runs eagerly (it also sets the
     // kernels' attributes and the base Jacobian, which capture must not do).
     const bool use_graph = p->graph != 0;
+    const bool ic = p->method == 1;
+    const int n_solves = ic ? N : H;   // coarse solves (counter rows) per correction
+    // PP-IC: the first propagation starts from U_N = U^0_0
+    if (ic) PPC_HIP(hipMemcpyAsync(w.ic_un, w.U, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
     GraphExec g_fine, g_coarse;
     auto fine_ops = [&]() {
         launch_fine_sweep(pr, p, w.U, w.F, s);
@@ -314,7 +320,9 @@ int solve_device(ppc_handle* h, ppc_problem* pr, const ppc_params* p, const doub
     };
     auto coarse_ops = [&]() {
         const double* lin = p->lin_point == 1 ? w.F : w.U;
-        if (p->b_cap > 0.0) {
+        if (ic) {
+            launch_ic_propagation(pr, p, s);
+        } else if (p->b_cap > 0.0) {
             // correction into w.R (free after the DFT), then the safeguarded update
             launch_coarse(pr, p, lin, w.J, w.R, false, false, s);
             launch_safeguarded_update(pr, N, p->b_cap, w.R, w.U, w.scal + 8, s);
@@ -322,7 +330,8 @@ int solve_device(ppc_handle* h, ppc_problem* pr, const ppc_params* p, const doub
         } else {
             launch_coarse(pr, p, lin, w.J, w.U, true, false, s);
         }
-        PPC_HIP(hipMemcpyAsync(w.host_ccount, w.ccount, 4 * (size_t)H * sizeof(int), hipMemcpyDeviceToHost, s));
+        PPC_HIP(hipMemcpyAsync(w.host_ccount, w.ccount, 4 * (size_t)n_solves * sizeof(int),
+                               hipMemcpyDeviceToHost, s));
     };
     auto run = [&](GraphExec& g, int k, auto& ops) {
         if (!use_graph || k == 0) {
@@ -365,10 +374,10 @@ int solve_device(ppc_handle* h, ppc_problem* pr, const ppc_params* p, const doub
         run(g_coarse, k, coarse_ops);
         PPC_HIP(hipEventRecord(ev[3], s));
         PPC_HIP(hipStreamSynchronize(s));
-        parse_cocg(w.host_ccount, H, nullptr, &S.cocg_total, &S.cocg_max);
-        if (p->b_cap > 0.0 && w.host_scal[8] < 1.0) S.damped++;
+        parse_cocg(w.host_ccount, n_solves, nullptr, &S.cocg_total, &S.cocg_max);
+        if (!ic && p->b_cap > 0.0 && w.host_scal[8] < 1.0) S.damped++;
         S.coarse_ms += elapsed(ev[2], ev[3]);
-        S.coarse_solves++;
+        S.coarse_solves += ic ? N : 1;
     }
     S.iterations = std::min(k, p->max_iters);
     if (U_out_dev) launch_to_nodal(pr, N, w.U, U_out_dev, s);
@@ -401,6 +410,7 @@ int solve_batch_device(ppc_handle* h, ppc_problem* bp, const ppc_params* p, cons
                        double* U_out_dev, double* resid_out, int32_t* iters_out, ppc_stats* st,
                        hipStream_t s) {
     PPC_HIP(hipSetDevice(h->device));
+    if (p->method != 0) fail(PPC_ERR_ARG, "PP-IC (method 1) runs single-design problems only");
     auto& parts = bp->parts;
     const int D = (int)parts.size();
     const int N = p->N, H = N / 2 + 1, R1 = p->max_iters + 1;
@@ -711,6 +721,7 @@ int ppc_params_default(ppc_params* p) {
     p->lin_point = 1;
     p->coarse_precision = -1;
     p->graph = 1;
+    p->method = 0;
     p->b_cap = 0.0;
     return PPC_OK;
 }

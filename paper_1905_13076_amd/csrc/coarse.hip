@@ -172,6 +172,44 @@ __global__ void k_coarse_rhs(int n, int N, const int* __restrict__ rowptr, const
     R[(long)s * n + i] = acc;
 }
 
+// PP-IC start of a propagation (eq. (5)): e = U_N - U^k_0, then U_0 = U_N; thread 0 also
+// sets the single shift 1/dT of the propagation's solves.
+__global__ void k_ic_start(int n, double inv_dT, const double* __restrict__ un, double* __restrict__ u0,
+                           double* __restrict__ e, double2* __restrict__ sig) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) sig[0] = make_double2(inv_dT, 0.0);
+    if (i >= n) return;
+    const double v = un[i];
+    e[i] = v - u0[i];
+    u0[i] = v;
+}
+
+// PP-IC right-hand side C e = M e / dT, as a complex vector with zero imaginary part
+__global__ void k_ic_rhs(int n, const int* __restrict__ rowptr, const int* __restrict__ colidx,
+                         const double* __restrict__ mval, double inv_dT, const double* __restrict__ e,
+                         double2* __restrict__ b) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double acc = 0.0;
+    for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) acc += mval[k] * e[colidx[k]];
+    b[i] = make_double2(acc * inv_dT, 0.0);
+}
+
+// PP-IC step: v = F_n + x (x = Q^{-1} C e); rows n < N: e = v - U^k_n and U_n = v; row N
+// (u == null): U_N = v, the next iteration's U_0.
+__global__ void k_ic_update(int n, const double2* __restrict__ x, const double* __restrict__ f,
+                            double* __restrict__ u, double* __restrict__ e, double* __restrict__ un) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double v = f[i] + x[i].x;
+    if (u) {
+        e[i] = v - u[i];
+        u[i] = v;
+    } else {
+        un[i] = v;
+    }
+}
+
 // R[s][i] = i(T_s) F_i with row 0 carrying T_N = T (the coarse excitation rows of eq. (9))
 __global__ void k_excitation_rows(int n, int N, double T, const double* __restrict__ fload,
                                   const double* __restrict__ wav, int n_h, double f0,
@@ -953,21 +991,34 @@ void launch_jumps(ppc_problem* pr, int N, const double* U, const double* F, doub
 
 // Linearisation, coarse right-hand side, DFT along time and the shifts: everything of the
 // correction before the harmonic solves.
-void launch_coarse_pre(ppc_problem* pr, const ppc_params* p, const double* U, const double* J,
-                       bool excitation_rhs, hipStream_t s) {
+namespace {
+
+// Frozen coarse stiffness Kbar over the samples U (null: at u = 0), in CSR order (FP64 and
+// FP32) and as (Kbar, M) pairs in ELL order.
+void launch_linearisation(ppc_problem* pr, const ppc_params* p, const double* U, hipStream_t s) {
     const DeviceMesh& d = pr->mesh;
     Workspace& w = pr->ws;
-    const int n = d.n_free, ne = d.n_tri, N = p->N, H = N / 2 + 1;
-    const double dT = p->T / N;
+    const int n = d.n_free, ne = d.n_tri;
     const int eb = 256;
     const int eg = std::max(1, std::min((ne + eb - 1) / eb, 4096));
-    hipLaunchKernelGGL(k_linearise, dim3(eg), dim3(eb), 0, s, ne, n, N, excitation_rhs ? nullptr : U,
-                       d.efree, d.gx, d.gy, d.area, d.k0, d.mat, pr->lawtab, p->lin_mode, w.nubar);
+    hipLaunchKernelGGL(k_linearise, dim3(eg), dim3(eb), 0, s, ne, n, p->N, U, d.efree, d.gx, d.gy, d.area,
+                       d.k0, d.mat, pr->lawtab, p->lin_mode, w.nubar);
     const int sg = std::max(1, std::min((d.nnz + eb - 1) / eb, 4096));
     hipLaunchKernelGGL(k_kbar, dim3(sg), dim3(eb), 0, s, d.nnz, ne, d.slot_ptr, d.slot_src, d.area, d.gx,
                        d.gy, w.nubar, w.kbar, w.kbar32);
     const int vg = std::max(1, std::min((d.n_vals + eb - 1) / eb, 4096));
     hipLaunchKernelGGL(k_km, dim3(vg), dim3(eb), 0, s, d.n_vals, d.vslot, w.kbar, d.mval, w.ckm);
+}
+
+}  // namespace
+
+void launch_coarse_pre(ppc_problem* pr, const ppc_params* p, const double* U, const double* J,
+                       bool excitation_rhs, hipStream_t s) {
+    const DeviceMesh& d = pr->mesh;
+    Workspace& w = pr->ws;
+    const int n = d.n_free, N = p->N, H = N / 2 + 1;
+    const double dT = p->T / N;
+    launch_linearisation(pr, p, excitation_rhs ? nullptr : U, s);
     const dim3 rg((n + 255) / 256, N);
     if (excitation_rhs)
         hipLaunchKernelGGL(k_excitation_rows, rg, dim3(256), 0, s, n, N, p->T, d.fload, pr->wavtab,
@@ -1068,10 +1119,10 @@ void launch_coarse_post(ppc_problem* pr, const ppc_params* p, double* dU, bool a
     PPC_HIP(hipGetLastError());
 }
 
-void launch_coarse(ppc_problem* pr, const ppc_params* p, const double* U, const double* J,
-                   double* dU, bool accumulate, bool excitation_rhs, hipStream_t s) {
-    launch_coarse_pre(pr, p, U, J, excitation_rhs, s);
-    const CocgArgs a = make_cocg_args(pr, p);
+namespace {
+
+// One COCG launch over the a.H systems of a (one workgroup each), in the form the mesh takes.
+void launch_cocg_solves(const ppc_problem* pr, const CocgArgs& a, hipStream_t s) {
     size_t lds = 0;
     switch (cocg_ell_rows(pr, a, lds)) {
         case 1: launch_cocg_ell<1>(a, lds, s); break;
@@ -1081,7 +1132,39 @@ void launch_coarse(ppc_problem* pr, const ppc_params* p, const double* U, const 
         default: hipLaunchKernelGGL(k_cocg, dim3(a.H), dim3(kCocgBlock), 0, s, a);
     }
     PPC_HIP(hipGetLastError());
+}
+
+}  // namespace
+
+void launch_coarse(ppc_problem* pr, const ppc_params* p, const double* U, const double* J,
+                   double* dU, bool accumulate, bool excitation_rhs, hipStream_t s) {
+    launch_coarse_pre(pr, p, U, J, excitation_rhs, s);
+    launch_cocg_solves(pr, make_cocg_args(pr, p), s);
     launch_coarse_post(pr, p, dU, accumulate, s);
+}
+
+void launch_ic_propagation(ppc_problem* pr, const ppc_params* p, hipStream_t s) {
+    const DeviceMesh& d = pr->mesh;
+    Workspace& w = pr->ws;
+    const int n = d.n_free, N = p->N;
+    const double inv_dT = N / p->T;
+    launch_linearisation(pr, p, w.U, s);
+    const dim3 g((n + 255) / 256), b(256);
+    hipLaunchKernelGGL(k_ic_start, g, b, 0, s, n, inv_dT, w.ic_un, w.U, w.ic_e, w.sig);
+    // one real shifted system (Kbar + M/dT) x = C e per step: the harmonic solver with a
+    // single system and the real shift 1/dT, right-hand side in rhat[0], solution in rhat[1]
+    CocgArgs a = make_cocg_args(pr, p);
+    a.H = 1;
+    a.X = w.rhat + n;
+    for (int step = 1; step <= N; ++step) {
+        hipLaunchKernelGGL(k_ic_rhs, g, b, 0, s, n, d.rowptr, d.colidx, d.mval, inv_dT, w.ic_e, w.rhat);
+        a.count = w.ccount + 4 * (step - 1);
+        launch_cocg_solves(pr, a, s);
+        const int row = step % N;
+        hipLaunchKernelGGL(k_ic_update, g, b, 0, s, n, w.rhat + n, w.F + (long)row * n,
+                           step < N ? w.U + (long)step * n : nullptr, w.ic_e, w.ic_un);
+    }
+    PPC_HIP(hipGetLastError());
 }
 
 // Harmonic solves of the designs in list (descriptors d_args, one per design): the

@@ -139,13 +139,15 @@ struct Workspace {
     double2* cwork = nullptr;  // [H][4][n_pad] COCG vectors r p q dinv
     double2* ckm = nullptr;    // [vals_pad] (Kbar, M) pairs in ELL order
     double2* sig = nullptr;    // [H] shifts sigma_p
-    int* ccount = nullptr;     // [H][4]
+    int* ccount = nullptr;     // [N][4] (PP-PC uses the first H rows, PP-IC one row per step)
+    double* ic_e = nullptr;    // [n_free] PP-IC: U^{k+1}_{n-1} - U^k_{n-1} of the current step
+    double* ic_un = nullptr;   // [n_free] PP-IC: U_N of the last propagation (next U_0)
     double2* twiddle = nullptr;// [N]
     double* partial = nullptr; // reduction partials
     double* scal = nullptr;    // small scalars
     double* host_scal = nullptr; // pinned host mirror
     int* host_fcount = nullptr;  // pinned [N][8] chain counters of the last sweep
-    int* host_ccount = nullptr;  // pinned [H][4] harmonic-solve counters
+    int* host_ccount = nullptr;  // pinned [N][4] coarse-solve counters
     size_t n_pad = 0, nnz_pad = 0, ne_pad = 0, vals_pad = 0, nl_pad = 0;
 };
 
@@ -332,6 +334,11 @@ CocgArgs make_cocg_args(ppc_problem* pr, const ppc_params* p);
 void launch_cocg_batch(const std::vector<ppc_problem*>& parts, const std::vector<int>& list,
                        const ppc_params* p, const CocgArgs* d_args, int2* d_work, std::vector<int2>& cw,
                        hipStream_t s);
+// PP-IC coarse propagation (eq. (5) with the update of eq. (4)): frozen coarse stiffness at
+// the current iterate U, then U_0 = U_N of the last propagation and, for n = 1..N in order,
+// U^{k+1}_n = F_n + Q^{-1} C (U^{k+1}_{n-1} - U^k_{n-1}), Q = C + Kbar, C = M/dT; the value
+// at n = N is kept for the next iteration's U_0.  Counters of step n in ccount row n-1.
+void launch_ic_propagation(ppc_problem* pr, const ppc_params* p, hipStream_t s);
 void launch_coarse_post(ppc_problem* pr, const ppc_params* p, double* dU, bool accumulate,
                         hipStream_t s);
 void launch_to_nodal(const ppc_problem* pr, int N, const double* Ufree, double* Unodal,

@@ -5,9 +5,10 @@ Calls only the CPU oracle (``oracle/``) and the seeded input generator
 
     python tests/golden/make_reference.py [c2] [c5small] [--procs 8]
 
-Each output ``<name>_oracle.npz`` holds the PP-PC fixed point U (rows n = 0..N-1,
-columns = free nodes in ascending node order), the eps history, the iteration count
-and the generator arguments that define the workload.
+Each output ``<name>_oracle.npz`` holds the fixed point U (rows n = 0..N-1, columns =
+free nodes in ascending node order), the eps history, the iteration count and the
+generator arguments that define the workload.  Cases ending in ``_ppic`` run PP-IC
+(eq. (5)) from the fine sweep from rest instead of PP-PC.
 """
 from __future__ import annotations
 
@@ -30,6 +31,7 @@ CASES = {
     # name: (generator, kwargs, PP-PC tolerance)
     "c2": (coax.c2, {}, 1e-12),
     "c5small": (coax.c5_small, {}, 1e-12),
+    "c5small_ppic": (coax.c5_small, {}, 1e-12),
 }
 
 
@@ -46,7 +48,11 @@ def make(name, procs):
         print(f"  [{name}] k={k} eps={eps:.3e} t={time.time() - t:.1f}s", flush=True)
 
     try:
-        U, hist, k = periodic.ppc(fe, tol=tol, pool=pool, callback=cb)
+        if name.endswith("_ppic"):
+            U0 = periodic.initial_iterate(fe, mode="fine", pool=pool)
+            U, hist, k = periodic.ppic(fe, tol=tol, U_init=U0, pool=pool, callback=cb)
+        else:
+            U, hist, k = periodic.ppc(fe, tol=tol, pool=pool, callback=cb)
     finally:
         if pool is not None:
             pool.close()
