@@ -59,10 +59,17 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c5small", "c4reg"],
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c2lin", "c5small", "c4reg"],
                     help="c4reg: the batched-designs generator's designs with nr <= 66 among its "
-                         "first 64 (21 designs, full 40 x 50 grid), one batched solve per step")
+                         "first 64 (21 designs, full 40 x 50 grid), one batched solve per step; "
+                         "c2lin: C2 with the steel linearised at its unsaturated reluctivity")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed", "mixed-fine"])
+    ap.add_argument("--method", default="ppc", choices=["ppc", "ppic"],
+                    help="ppc: PP-PC, eq. (4) with the periodic coarse problem; ppic: PP-IC, "
+                         "eq. (5), U_0^{k+1} = U_N^k with sequential coarse propagation")
+    ap.add_argument("--init", default="auto", choices=["auto", "rest"],
+                    help="U^0: auto (zero for nonlinear, coarse periodic for linear) or rest "
+                         "(one fine sweep from zero, U^0_n = F_n(0))")
     ap.add_argument("--tol", type=float, default=1e-8, help="PP-PC stopping tolerance on eps")
     ap.add_argument("--tol-cocg", type=float, default=1e-6,
                     help="relative tolerance of the harmonic solves (a correction only needs to be "
@@ -78,7 +85,7 @@ def parse():
 
 def workload(name):
     from workloads import coax
-    return {"c1": coax.c1, "c2": coax.c2, "c5small": coax.c5_small}[name]()
+    return {"c1": coax.c1, "c2": coax.c2, "c2lin": coax.c2lin, "c5small": coax.c5_small}[name]()
 
 
 def load_reference(name):
@@ -235,7 +242,7 @@ def main():
     if a.probe == "fine":
         return probe_fine(a, prob, ref)
     cpu = None
-    if a.cpu and ref is not None:
+    if a.cpu and ref is not None and a.method == "ppc" and a.init == "auto":
         # before any GPU initialisation: the oracle's worker pool forks this process
         cpu = cpu_baseline(prob, ref, a.cpu_procs)
     import numpy as np
@@ -252,6 +259,10 @@ def main():
     extra = {"tol_lin": 1e-4} if prec == 1 else {}
     if a.precision == "mixed-fine":          # FP32 PCG fine solves, FP64 harmonic solves
         extra["coarse_precision"] = 0
+    extra["method"] = 1 if a.method == "ppic" else 0
+    extra["init_mode"] = 3 if a.init == "rest" else 0
+    if a.method == "ppic":
+        extra["max_iters"] = 300
     prm = P.problem_params(prob, tol_ppc=a.tol, precision=prec, tol_cocg=a.tol_cocg, **extra)
     out = torch.empty((prob.N, pr.n_nodes), dtype=torch.float64, device="cuda")
     for _ in range(a.warmup):
@@ -300,6 +311,8 @@ def main():
                         f"({st['n_free']} free nodes, {st['nnz']} nnz), N={prob.N} x m={prob.m}, "
                         f"{prob.N // 2 + 1} harmonics, amplitude {prob.amps[0]:.1f} A",
             "precision": a.precision,
+            "method": a.method,
+            "init": a.init,
             "tol_ppc": a.tol,
             "tol_cocg": a.tol_cocg,
             "iterations": k,
@@ -308,6 +321,7 @@ def main():
             "newton_per_step": tot["newton_total"] / max(1, tot["steps_total"]),
             "pcg_per_newton": tot["lin_total"] / max(1, tot["newton_total"]),
             "cocg_total_per_state": sum(s["cocg_total"] for s in stats) / a.steps,
+            "coarse_solves_per_state": sum(s["coarse_solves"] for s in stats) / a.steps,
             "fine_ms_per_state": fine_ms / a.steps,
             "coarse_ms_per_state": sum(s["coarse_ms"] for s in stats) / a.steps,
             "setup_s": setup_s,

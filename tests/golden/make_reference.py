@@ -8,7 +8,7 @@ Calls only the CPU oracle (``oracle/``) and the seeded input generator
 Each output ``<name>_oracle.npz`` holds the fixed point U (rows n = 0..N-1, columns =
 free nodes in ascending node order), the eps history, the iteration count and the
 generator arguments that define the workload.  Cases ending in ``_ppic`` run PP-IC
-(eq. (5)) from the fine sweep from rest instead of PP-PC.
+(eq. (5)) instead of PP-PC (c5small from the fine sweep from rest).
 """
 from __future__ import annotations
 
@@ -32,6 +32,8 @@ CASES = {
     "c2": (coax.c2, {}, 1e-12),
     "c5small": (coax.c5_small, {}, 1e-12),
     "c5small_ppic": (coax.c5_small, {}, 1e-12),
+    "c2lin_small": (coax.c2lin, dict(nr=20, ntheta=40, N=10, m=20), 1e-12),
+    "c2lin_small_ppic": (coax.c2lin, dict(nr=20, ntheta=40, N=10, m=20), 1e-12),
 }
 
 
@@ -48,9 +50,11 @@ def make(name, procs):
         print(f"  [{name}] k={k} eps={eps:.3e} t={time.time() - t:.1f}s", flush=True)
 
     try:
-        if name.endswith("_ppic"):
+        if name == "c5small_ppic":     # from rest: a coarse start from zero overshoots
             U0 = periodic.initial_iterate(fe, mode="fine", pool=pool)
             U, hist, k = periodic.ppic(fe, tol=tol, U_init=U0, pool=pool, callback=cb)
+        elif name.endswith("_ppic"):
+            U, hist, k = periodic.ppic(fe, tol=tol, pool=pool, callback=cb)
         else:
             U, hist, k = periodic.ppc(fe, tol=tol, pool=pool, callback=cb)
     finally:

@@ -84,3 +84,26 @@ def test_ppic_rejected_for_batches():
     bp = P.BatchProblem(handle(), probs)
     with pytest.raises(P.PPCError, match="PP-IC"):
         bp.solve(P.problem_params(probs[0], method=1))
+
+
+def test_c2lin_small_ppic_and_ppc_match_oracle():
+    """Linearised C2 (steel at its unsaturated reluctivity; 20 x 40, N = 10 x 20): the
+    sheath's time constant makes PP-IC slow, PP-PC fast -- the contrast of the paper's
+    Section 4 -- and both GPU runs follow the oracle's iteration counts to its fixed point."""
+    import paper_1905_13076_amd as P
+    from oracle.fe import FE
+    prob = coax.c2lin(nr=20, ntheta=40, N=10, m=20)
+    fe = FE(prob)
+    pr = P.Problem(handle(), prob)
+    res = {}
+    for name, kw in (("c2lin_small", {}), ("c2lin_small_ppic", dict(method=1, max_iters=300))):
+        g = load_golden(name)
+        banner(f"{name}")
+        U, eps, k, st, rc = pr.solve(P.problem_params(prob, **kw))
+        assert rc == 0, st
+        e = rel(free_rows(U.cpu().numpy(), fe.free), g["U"])
+        banner(f"{name}: iters={k} (oracle {int(g['iterations'])}) rel={e:.2e}")
+        assert e <= 1e-10
+        assert abs(k - int(g["iterations"])) <= 1
+        res[name] = k
+    assert res["c2lin_small_ppic"] >= 5 * res["c2lin_small"]

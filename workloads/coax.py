@@ -200,6 +200,20 @@ def c2(nr=60, ntheta=120, N=40, m=50, seed=2, sheath_sigma=2e6):
                         [amp], [0.0], 0.02, N, m, meta=dict(seed=seed))
 
 
+def c2lin(nr=60, ntheta=120, N=40, m=50, seed=2, f_scale=1.0):
+    """C2 with the sheath's Brauer law replaced by a linear material at the steel's
+    unsaturated reluctivity nu(0) = k1 + k3; frequency and period scaled by f_scale
+    (f0 = 50 f_scale Hz, T = 0.02 / f_scale).  The sheath's magnetic time constant then
+    sets how many periods classical time stepping needs, without saturation."""
+    amp = 200.0 + 600.0 * np.random.default_rng(seed).random()
+    k1, _, k3 = 3.8, 2.17, 396.2
+    layers = [Layer(1e-3, SIGMA_CU, 0, +1), Layer(2e-3, 0.0, 0),
+              Layer(2.5e-3, SIGMA_CU, 0), Layer(3e-3, 2e6, 1)]
+    return layered_coax("C2-linearised", layers, [AIR, (LINEAR, k1 + k3, 0.0, 0.0, 0.0)], nr, ntheta,
+                        50.0 * f_scale, [1], [amp], [0.0], 0.02 / f_scale, N, m,
+                        meta=dict(seed=seed, f_scale=f_scale))
+
+
 def c3(nr=400, ntheta=800, N=200, m=100, seed=3):
     """Large nonlinear coax: fundamental plus a 20% third harmonic with a seeded phase."""
     rng = np.random.default_rng(seed)
