@@ -33,7 +33,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 COUNTERS = os.path.join(ROOT, "profiles", "fine_sweep_c2_fp64_counters.md")
-FINE_SRC = os.path.join(ROOT, "paper_1905_13076_amd", "csrc", "fine.hip")
+FINE_SRC = os.path.join(ROOT, "paper_1905_13076_amd", "csrc", "fine_chain.hpp")
 
 
 def measured_traffic():
@@ -44,7 +44,7 @@ def measured_traffic():
     if not os.path.exists(COUNTERS):
         return None
     text = open(COUNTERS).read()
-    m = re.search(r"fine.hip sha1: ([0-9a-f]{40})", text)
+    m = re.search(r"fine_chain.hpp sha1: ([0-9a-f]{40})", text)
     t = re.search(r"traffic_bytes_per_launch: (\d+)", text)
     g = re.search(r"algorithmic_bytes_per_launch: (\d+)", text)
     if not (m and t and g):
@@ -74,6 +74,9 @@ def parse():
     ap.add_argument("--tol-cocg", type=float, default=1e-6,
                     help="relative tolerance of the harmonic solves (a correction only needs to be "
                          "accurate relative to the current jumps)")
+    ap.add_argument("--autotune", dest="autotune", action="store_true", default=True,
+                    help="tune the fine-sweep workgroup size before timing (untimed set-up)")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false")
     ap.add_argument("--cpu-baseline", dest="cpu", action="store_true", default=True)
     ap.add_argument("--no-cpu-baseline", dest="cpu", action="store_false")
     ap.add_argument("--cpu-procs", type=int, default=16)
@@ -199,6 +202,13 @@ def bench_batch(a):
         extra["coarse_precision"] = 0
     prm = P.problem_params(designs[0], tol_ppc=a.tol, precision=prec, tol_cocg=a.tol_cocg, max_newton=200,
                            init_mode=3, b_cap=3.0, **extra)
+    tuned = None
+    if a.autotune:
+        # untimed set-up: the fine-sweep workgroup size per size class
+        t0 = time.perf_counter()
+        blocks, _ = bp.autotune(prm)
+        tuned = {"seconds": time.perf_counter() - t0,
+                 "designs_per_block": {str(b): int(np.sum(blocks == b)) for b in (256, 512, 1024)}}
     for _ in range(a.warmup):
         bp.solve(prm)
     torch.cuda.synchronize()
@@ -224,7 +234,8 @@ def bench_batch(a):
                    "precision": a.precision, "tol_ppc": a.tol, "tol_cocg": a.tol_cocg,
                    "iterations_max": int(max(iters)), "damped_corrections": st["damped"],
                    "fine_ms_per_step": st["fine_ms"], "coarse_ms_per_step": st["coarse_ms"],
-                   "newton_per_step": st["newton_total"] / max(1, st["steps_total"])},
+                   "newton_per_step": st["newton_total"] / max(1, st["steps_total"]),
+                   "autotune": tuned},
         "roofline": None, "cpu_baseline": None}))
     return 0
 
@@ -264,6 +275,12 @@ def main():
     if a.method == "ppic":
         extra["max_iters"] = 300
     prm = P.problem_params(prob, tol_ppc=a.tol, precision=prec, tol_cocg=a.tol_cocg, **extra)
+    tuned = None
+    if a.autotune:
+        t0 = time.perf_counter()
+        b, ms = pr.autotune(prm)
+        tuned = {"seconds": time.perf_counter() - t0, "block": b,
+                 "sweep_ms": {str(k): (None if np.isnan(v) else float(v)) for k, v in zip((256, 512, 1024), ms)}}
     out = torch.empty((prob.N, pr.n_nodes), dtype=torch.float64, device="cuda")
     for _ in range(a.warmup):
         pr.solve(prm, out=out)
@@ -325,6 +342,7 @@ def main():
             "fine_ms_per_state": fine_ms / a.steps,
             "coarse_ms_per_state": sum(s["coarse_ms"] for s in stats) / a.steps,
             "setup_s": setup_s,
+            "autotune": tuned,
         },
         "roofline": {
             "kernel": "k_fine_sweep",

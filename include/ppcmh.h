@@ -134,7 +134,11 @@ typedef struct {
                                stiffness at U^k (N real shifted solves per iteration, one after
                                the other; lin_point and shift_mode do not apply).  PP-IC is for
                                single-design solves without b_cap */
-    int32_t reserved[2];
+    int32_t fine_block;     /* register-row fine kernel workgroup: 0 = the size ppc_autotune
+                               chose for this problem and precision, else 1024; 256, 512 or
+                               1024 = that size (PPC_ERR_ARG when the mesh's rows do not fit:
+                               R rows per thread, R <= 8, R * fine_block >= free nodes) */
+    int32_t reserved[1];
     double b_cap;           /* coarse-correction safeguard (T): 0 = off; > 0 = apply
                                U += theta dU with the largest theta <= 1 that keeps |B| <= b_cap
                                in every Brauer element and sample, when the full correction
@@ -172,7 +176,7 @@ int ppc_version(void);
 /* Defaults: T = 0.02, N = 10, m = 20, shift 0, lin 0, init 0, FP64, tol_ppc 1e-12,
  * max_iters 60, tol_newton 1e-13, max_newton 50, tol_lin 1e-8, max_lin 20000,
  * tol_cocg 1e-10, max_cocg 20000, block 0, predictor on, lin_point 1 (fine results),
- * coarse_precision -1, graph 1, method 0, b_cap 0.
+ * coarse_precision -1, graph 1, method 0, fine_block 0, b_cap 0.
  * Returns PPC_ERR_ARG on a null pointer. */
 int ppc_params_default(ppc_params* p);
 
@@ -246,6 +250,24 @@ int ppc_solve(ppc_handle* h, ppc_problem* pr, const ppc_params* p, const double*
 int ppc_solve_device(ppc_handle* h, ppc_problem* pr, const ppc_params* p,
                      const double* U_init_dev, double* U_out_dev, double* resid_out,
                      int32_t* iters_out, ppc_stats* stats, void* stream);
+
+/* Autotuner of the fine sweep's register-row workgroup size (256, 512 or 1024 threads; a
+ * smaller workgroup takes more rows per thread).  For each size whose rows fit the mesh it
+ * times one fine sweep from U = 0 in the problem's workspace (overwriting the workspace
+ * state; the next solve starts afresh), best of two after a warm-up, and keeps the fastest
+ * for params->precision: later sweeps and solves with params->fine_block = 0 use it.
+ * Meshes that take the memory path (rows beyond registers and LDS) have nothing to tune
+ * and report 0.  A batched problem is tuned on its batched sweep: policy b (256, 512,
+ * 1024) puts every design at b threads or at the next larger size its rows fit, and the
+ * fastest policy is kept (designs of one size class share a size).  The adjoint sweep
+ * keeps 1024 threads.
+ *   block_out  host [1] (single) or [n_designs] (batch), or null: the chosen size (0 =
+ *              memory path)
+ *   ms_out     host [3] or [3 n_designs], or null: sweep ms at 256, 512, 1024 threads
+ *              (single: NaN = does not fit); a batch gives every design the three policy
+ *              times of the whole batched sweep
+ * PPC_ERR_ARG when params->fine_block is set. */
+int ppc_autotune(ppc_handle* h, ppc_problem* pr, const ppc_params* p, int32_t* block_out, double* ms_out);
 
 /* Adjoint gradients of the period-averaged eddy-current loss at a periodic steady state
  * (the state of eq. (1) that ppc_solve returns).  With the periodic implicit-Euler fine

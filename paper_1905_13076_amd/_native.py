@@ -51,7 +51,8 @@ class Params(ctypes.Structure):
                 ("max_newton", c_int32), ("tol_lin", c_double), ("max_lin", c_int32),
                 ("tol_cocg", c_double), ("max_cocg", c_int32), ("block", c_int32),
                 ("no_predictor", c_int32), ("lin_point", c_int32), ("coarse_precision", c_int32),
-                ("graph", c_int32), ("method", c_int32), ("reserved", c_int32 * 2), ("b_cap", c_double)]
+                ("graph", c_int32), ("method", c_int32), ("fine_block", c_int32), ("reserved", c_int32 * 1),
+                ("b_cap", c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -91,6 +92,7 @@ SIGNATURES = {
     "ppc_fine_sweep_device": (c_int, [c_void_p, c_void_p, POINTER(Params), c_void_p, c_void_p, PI, PI,
                                       c_void_p]),
     "ppc_fine_counts": (c_int, [c_void_p, c_int32, PI]),
+    "ppc_autotune": (c_int, [c_void_p, c_void_p, c_void_p, PI, PD]),
     "ppc_coarse_correction_device": (c_int, [c_void_p, c_void_p, POINTER(Params), c_void_p, c_void_p,
                                              c_void_p, PI, c_void_p]),
 }

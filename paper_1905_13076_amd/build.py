@@ -39,15 +39,30 @@ def build(debug: bool = False, verbose: bool = False) -> str:
     flags += ["-O0", "-g"] if debug else ["-O3"]
     fd, tmp = tempfile.mkstemp(prefix="libppcmh.", suffix=".so.tmp", dir=HERE)
     os.close(fd)
-    cmd = [cc, *flags, *sources(), "-o", tmp]
-    if verbose:
-        print(" ".join(cmd), flush=True)
+    objdir = tempfile.mkdtemp(prefix="ppcmh_obj.")
+    srcs = sources()
+    objs = [os.path.join(objdir, os.path.basename(f) + ".o") for f in srcs]
+    compile_flags = [f for f in flags if f != "-shared"]
+    cmds = [[cc, *compile_flags, "-c", f, "-o", o] for f, o in zip(srcs, objs)]
+    link = [cc, *flags, *objs, "-o", tmp]
     try:
-        subprocess.run(cmd, check=True)
+        # translation units compile in parallel (the fine-sweep kernels dominate), then link
+        procs = []
+        for c in cmds:
+            if verbose:
+                print(" ".join(c), flush=True)
+            procs.append(subprocess.Popen(c))
+        failed = [c for c, p in zip(cmds, procs) if p.wait() != 0]
+        if failed:
+            raise subprocess.CalledProcessError(1, failed[0])
+        if verbose:
+            print(" ".join(link), flush=True)
+        subprocess.run(link, check=True)
         os.replace(tmp, LIB)
     finally:
         if os.path.exists(tmp):
             os.remove(tmp)
+        shutil.rmtree(objdir, ignore_errors=True)
     return LIB
 
 

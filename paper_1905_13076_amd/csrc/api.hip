@@ -144,6 +144,38 @@ void ensure_workspace(ppc_problem* pr, const ppc_params* p) {
     w.N = p->N;
 }
 
+int autotune_fine(ppc_problem* pr, const ppc_params* p, double ms[3], hipEvent_t e0, hipEvent_t e1,
+                  hipStream_t s) {
+    ensure_workspace(pr, p);
+    Workspace& w = pr->ws;
+    const int n = pr->mesh.n_free;
+    int best = 0;
+    double best_ms = INFINITY;
+    for (int i = 0; i < 3; ++i) {
+        ms[i] = NAN;
+        ppc_params q = *p;
+        q.fine_block = kRowBlocks[i];
+        if (q.block == kFineBlock || rows_shape(pr, &q, kRowBlocks[i]).R == 0) continue;
+        double t = INFINITY;
+        for (int rep = 0; rep < 3; ++rep) {
+            fill(w.U, (long)p->N * n, 0.0, s);
+            PPC_HIP(hipEventRecord(e0, s));
+            launch_fine_sweep(pr, &q, w.U, w.F, s);
+            PPC_HIP(hipEventRecord(e1, s));
+            PPC_HIP(hipEventSynchronize(e1));
+            float f = 0.0f;
+            PPC_HIP(hipEventElapsedTime(&f, e0, e1));
+            if (rep > 0) t = std::min(t, (double)f);
+        }
+        ms[i] = t;
+        if (t < best_ms) {
+            best_ms = t;
+            best = kRowBlocks[i];
+        }
+    }
+    return best;
+}
+
 namespace {
 
 struct SweepCounts {
@@ -994,6 +1026,76 @@ int ppc_fine_sweep_device(ppc_handle* h, ppc_problem* pr, const ppc_params* p, c
         check_sweep(c);
         launch_to_nodal(pr, p->N, pr->ws.F, F_out_dev, s);
         PPC_HIP(hipStreamSynchronize(s));
+        return PPC_OK;
+    });
+}
+
+int ppc_autotune(ppc_handle* h, ppc_problem* pr, const ppc_params* p, int32_t* block_out, double* ms_out) {
+    return guarded(h, [&]() -> int {
+        check_handle_problem(h, pr);
+        check_params(p);
+        if (p->fine_block != 0) fail(PPC_ERR_ARG, "autotune with fine_block forced");
+        PPC_HIP(hipSetDevice(h->device));
+        hipStream_t s = h->stream;
+        const int slot = p->precision != 0 ? 1 : 0;
+        if (!pr->batch) {
+            double ms[3];
+            const int b = autotune_fine(pr, p, ms, h->ev[6], h->ev[7], s);
+            pr->tuned_block[slot] = b;
+            if (block_out) block_out[0] = b;
+            if (ms_out) std::copy(ms, ms + 3, ms_out);
+            return PPC_OK;
+        }
+        // The batched sweep is what runs, so it is what is timed: policy b puts every design
+        // at b threads, or at the next larger size its rows fit (designs of one size class
+        // thereby share a size).  A design timed alone owns its CUs, which the batch's
+        // workgroups share, so single-design timings would not rank sizes for the batch.
+        const int D = (int)pr->parts.size();
+        for (auto* q : pr->parts) ensure_workspace(q, p);
+        auto policy = [&](int b) {
+            std::vector<int> out(D, 0);
+            for (int d = 0; d < D; ++d)
+                for (int rb : kRowBlocks)
+                    if (rb >= b && rows_shape(pr->parts[d], p, rb).R > 0) {
+                        out[d] = rb;
+                        break;
+                    }
+            return out;
+        };
+        const std::vector<char> active(D, 1);
+        std::vector<std::vector<int>> assign;
+        double ms[3];
+        int best = -1;
+        for (int i = 0; i < 3; ++i) {
+            assign.push_back(policy(kRowBlocks[i]));
+            ms[i] = NAN;
+            int same = -1;
+            for (int j = 0; j < i; ++j)
+                if (assign[j] == assign[i]) same = j;
+            if (same >= 0) {
+                ms[i] = ms[same];
+                continue;
+            }
+            for (int d = 0; d < D; ++d) pr->parts[d]->tuned_block[slot] = assign[i][d];
+            FineBatch fb;
+            fine_batch_prepare(fb, pr->parts, p, s);
+            double t = INFINITY;
+            for (int rep = 0; rep < 3; ++rep) {
+                for (auto* q : pr->parts) fill(q->ws.U, (long)p->N * q->mesh.n_free, 0.0, s);
+                PPC_HIP(hipEventRecord(h->ev[6], s));
+                fine_batch_launch(fb, active, s);
+                PPC_HIP(hipEventRecord(h->ev[7], s));
+                PPC_HIP(hipEventSynchronize(h->ev[7]));
+                if (rep > 0) t = std::min(t, (double)elapsed(h->ev[6], h->ev[7]));
+            }
+            ms[i] = t;
+            if (best < 0 || t < ms[best]) best = i;
+        }
+        for (int d = 0; d < D; ++d) {
+            pr->parts[d]->tuned_block[slot] = assign[best][d];
+            if (block_out) block_out[d] = assign[best][d];
+            if (ms_out) std::copy(ms, ms + 3, ms_out + 3 * (size_t)d);
+        }
         return PPC_OK;
     });
 }

@@ -1,840 +1,23 @@
-// Fine sweep: all N fine propagators F_n (Section 2, eqs. (2)-(3)) in one launch.
-//
-// One workgroup owns one chain n = 1..N: it starts from U_{n-1} at T_{n-1} and takes
-// m implicit-Euler steps of size dt = T/(N m).  Each step solves
-//     R(u) = M (u - u_prev)/dt + K(u) u - i(t_j) F = 0,   t_j = T_{n-1} + j dt,
-// by damped Newton with the exact Jacobian
-//     J = M/dt + sum_e [ nu_e K0_e + (2 nu'_e / A_e) (K0_e u_e)(K0_e u_e)^T ],
-// (nu' = d nu / d|B|^2) solved by Jacobi-PCG.  Linear elements make J and R affine in u,
-// so both are split into a base matrix Jb = M/dt + sum over linear e of nu_e K0_e, built
-// once per sweep, and a Brauer part: a Newton iteration re-evaluates only the Brauer
-// elements, the value positions they reach (a deterministic gather over a position ->
-// contribution list, no atomics) and R = Jb u - M u_prev/dt + Brauer forces - i F.
-//
-// Mapping to CDNA: the chain's vectors and Jacobian values live in HBM (L2 / MALL
-// resident for small meshes), the PCG keeps p (and for meshes that fit, r and the FP32
-// Jacobi diagonal) in LDS and its rows in registers; the ELL SpMV streams values and
-// 16-bit columns with raw buffer loads (a static count in flight, out-of-range lanes
-// read zero) and gathers p from LDS.  Dot products are DPP wave sums followed by a
-// fixed-order sum over the waves, so results are bitwise reproducible.  The PCG scalar
-// type S is double (FP64 form) or float (mixed form: FP32 Jacobian and PCG, FP64 Newton
-// residual refining it).
-#include <cfloat>
-#include <cmath>
-
-#include "internal.hpp"
-#include "wave.hpp"
+// Fine sweep host side: kernel shapes, launchers, the base Jacobian and batched launches.
+// The device code (Section 2, eqs. (2)-(3)) is in fine_chain.hpp.
+#include "fine_chain.hpp"
 
 namespace ppc {
-
-
-
-// Imposed current i(t) = sum_h amp_h sin(2 pi order_h f0 t + phase_h).
-__device__ inline double current(double t, double f0, int n_h, const double* __restrict__ w) {
-    double s = 0.0;
-    for (int h = 0; h < n_h; ++h) s = s + w[3 * h + 1] * sin(2.0 * M_PI * w[3 * h] * f0 * t + w[3 * h + 2]);
-    return s;
-}
-
-// Brauer / linear reluctivity and its derivative with respect to b2 = |B|^2.
-__device__ inline void reluct(const double* __restrict__ lawtab, int mid, double b2, double& nu,
-                              double& dnu) {
-    const double* L = lawtab + 5 * mid;
-    if (L[0] == 0.0) {
-        nu = L[1];
-        dnu = 0.0;
-    } else {
-        const double e = exp(L[3] * b2);
-        nu = L[2] * e + L[4];
-        dnu = L[2] * L[3] * e;
-    }
-}
-
-enum { E_F0 = 0, E_W0 = 3, E_NU = 6, E_SF = 7 };
-
-// Newton accepts a residual that stops halving (or a stalled line search) once it is
-// below kFloorCap * scale: it then sits at the rounding floor of its evaluation.
-constexpr double kFloorCap = 1e-9;
-enum { V_U = 0, V_UP = 1, V_R = 2, V_RT = 3, V_UPP = 4, V_UT = 5, V_CP = 6, V_UP3 = 7 };
-enum { P_R = 0, P_P = 1, P_Q = 2, P_X = 3, P_D = 4 };
-enum { C_STATUS = 0, C_NEWTON = 1, C_LIN = 2, C_NEWTON_MAX = 3, C_LIN_MAX = 4, C_CAPPED = 5,
-       C_FAILSTEP = 6, C_RESID = 7 };
-
-// The Jacobian and residual split into a state-independent base and a Brauer part:
-//     J(u) = Jb + sum over Brauer e [ nu_e K0_e + (2 nu'_e / A_e) w_e w_e^T ],
-//     R(u) = Jb u - M u_prev / dt + sum over Brauer e nu_e K0_e u_e - i(t) F,
-// with Jb = M/dt + sum over linear e nu_e K0_e built once per sweep (k_jbase), so a
-// Newton iteration touches only the Brauer elements and the value positions they reach.
-
-// Brauer element pass at the state ut: w = K0 ut_e, b2 = ut_e.w / A, nu, nu' and the
-// element force nu w (scratch el, planes of nl_pad).
-__device__ inline void nl_element_pass(const FineArgs& a, const double* __restrict__ ut,
-                                       double* __restrict__ el) {
-    const int nl = a.n_nl;
-    const long P = a.nl_pad;
-    for (int j = threadIdx.x; j < nl; j += blockDim.x) {
-        double x[3];
-#pragma unroll
-        for (int q = 0; q < 3; ++q) {
-            const int g = a.nl_efree[q * nl + j];
-            x[q] = g >= 0 ? ut[g] : 0.0;
-        }
-        const double k00 = a.nl_k0[j], k01 = a.nl_k0[nl + j], k02 = a.nl_k0[2 * nl + j];
-        const double k11 = a.nl_k0[3 * nl + j], k12 = a.nl_k0[4 * nl + j], k22 = a.nl_k0[5 * nl + j];
-        const double w0 = k00 * x[0] + k01 * x[1] + k02 * x[2];
-        const double w1 = k01 * x[0] + k11 * x[1] + k12 * x[2];
-        const double w2 = k02 * x[0] + k12 * x[1] + k22 * x[2];
-        const double A = a.nl_area[j];
-        const double b2 = (x[0] * w0 + x[1] * w1 + x[2] * w2) / A;
-        double nu, dnu;
-        reluct(a.lawtab, a.nl_mat[j], b2, nu, dnu);
-        el[(E_F0 + 0) * P + j] = nu * w0;
-        el[(E_F0 + 1) * P + j] = nu * w1;
-        el[(E_F0 + 2) * P + j] = nu * w2;
-        el[(E_W0 + 0) * P + j] = w0;
-        el[(E_W0 + 1) * P + j] = w1;
-        el[(E_W0 + 2) * P + j] = w2;
-        el[E_NU * P + j] = nu;
-        el[E_SF * P + j] = 2.0 * dnu / A;
-    }
-}
-
-// Brauer element forces of row i (node order)
-__device__ inline double nl_force(const FineArgs& a, const double* __restrict__ el, int i) {
-    const long P = a.nl_pad;
-    double acc = 0.0;
-    for (int k = a.nlf_ptr[i]; k < a.nlf_ptr[i + 1]; ++k) {
-        const int code = a.nlf_src[k];
-        const int j = code / 3, q = code - 3 * j;
-        acc += el[(E_F0 + q) * P + j];
-    }
-    return acc;
-}
-
-// R = Jb ut - cp + (Brauer forces) - cur F over all rows, cp = M u_prev / dt; returns the
-// partial ||R||^2 of this thread.  ELL rows load all their slots before the gathers; the
-// tail rows are summed by one wave each.
-__device__ inline double resid_rows(const FineArgs& a, const double* __restrict__ ut,
-                                    const double* __restrict__ cp, const double* __restrict__ el,
-                                    double cur, double* __restrict__ R) {
-    const long NP = a.ell_pad;
-    const int n = a.n, W = a.W;
-    double part = 0.0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        int col[kEllMaxWidth];
-        double val[kEllMaxWidth];
-#pragma unroll
-        for (int w = 0; w < kEllMaxWidth; ++w) {
-            col[w] = w < W ? a.ecol[w * NP + i] : 0;
-            val[w] = w < W ? a.jbase[w * NP + i] : 0.0;
-        }
-        if (col[0] < 0) continue;                 // tail row
-        double acc = 0.0;
-#pragma unroll
-        for (int w = 0; w < kEllMaxWidth; ++w)
-            if (w < W) acc += val[w] * ut[col[w]];
-        acc = acc - cp[i] + nl_force(a, el, i) - cur * a.fload[i];
-        R[i] = acc;
-        part += acc * acc;
-    }
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    const long base = (long)W * NP;
-    for (int t = wave; t < a.ntail; t += nw) {
-        double acc = 0.0;
-        const int j1 = a.tail_ptr[t + 1];
-        for (int j = a.tail_ptr[t] + lane; j < j1; j += 64) acc += a.jbase[base + j] * ut[a.tail_col[j]];
-        acc = wave_sum(acc);
-        if (lane == 0) {
-            const int i = a.tail_row[t];
-            acc = acc - cp[i] + nl_force(a, el, i) - cur * a.fload[i];
-            R[i] = acc;
-            part += acc * acc;
-        }
-    }
-    return part;
-}
-
-// Jacobian values of the Brauer-touched positions: Jb plus, per contribution of slot
-// order, nu K0_ab + (2nu'/A) w_a w_b; every other position keeps its base value.
-template <typename S>
-__device__ inline void assemble_nl(const FineArgs& a, const double* __restrict__ el, S* __restrict__ jv) {
-    const long P = a.nl_pad;
-    const int nl = a.n_nl;
-    for (int t = threadIdx.x; t < a.n_nlv; t += blockDim.x) {
-        const int v = a.nlv_val[t];
-        double acc = a.jbase[v];
-        for (int k = a.nlv_ptr[t]; k < a.nlv_ptr[t + 1]; ++k) {
-            const int code = a.nlv_src[k];
-            const int j = code / 9, ab = code - 9 * j;
-            const int qa = ab / 3, qb = ab - 3 * qa;
-            const int lo = qa < qb ? qa : qb, hi = qa < qb ? qb : qa;
-            const int kidx = lo == 0 ? hi : (lo == 1 ? 2 + hi : 5);
-            acc += el[E_NU * P + j] * a.nl_k0[kidx * nl + j] +
-                   el[E_SF * P + j] * el[(E_W0 + qa) * P + j] * el[(E_W0 + qb) * P + j];
-        }
-        jv[v] = (S)acc;
-    }
-}
-
-// every value position takes its base value (start of a chain)
-template <typename S>
-__device__ inline void init_jac(const FineArgs& a, S* __restrict__ jv) {
-    for (int v = threadIdx.x; v < a.nvals; v += blockDim.x) jv[v] = (S)a.jbase[v];
-}
-
-// cp = M u_prev / dt (CSR, kRowGroup lanes per row, once per time step); returns the
-// partial ||cp||^2.
-__device__ inline double mass_prev(const FineArgs& a, const double* __restrict__ up, double inv_dt,
-                                   double* __restrict__ cp) {
-    constexpr int G = kRowGroup;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    const int sub = lane % G, grp = lane / G;
-    constexpr int RPW = 64 / G;
-    double part = 0.0;
-    for (int base = wave * RPW; base < a.n; base += nw * RPW) {
-        const int i = base + grp;
-        double acc = 0.0;
-        if (i < a.n) {
-            const int k1 = a.rowptr[i + 1];
-            for (int k = a.rowptr[i] + sub; k < k1; k += G) acc += a.mval[k] * up[a.colidx[k]];
-        }
-#pragma unroll
-        for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-        if (i < a.n && sub == 0) {
-            const double v = acc * inv_dt;
-            cp[i] = v;
-            part += v * v;
-        }
-    }
-    return part;
-}
-
-// Row-sum of one tail (long) row by a whole wave; returns the sum on every lane.
-template <typename S, typename PV>
-__device__ inline S tail_row_sum(const FineArgs& a, const S* __restrict__ jv, PV p, int t, int lane) {
-    const long base = (long)a.W * a.ell_pad;
-    S acc = 0;
-    const int j1 = a.tail_ptr[t + 1];
-    for (int j = a.tail_ptr[t] + lane; j < j1; j += 64) acc += jv[base + j] * p[a.tail_col[j]];
-    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-    return acc;
-}
-
-// Jacobi-PCG on J x = -R for meshes that fit the CU: the rows of each thread
-// (i = tid + k B, k < R) keep x and q in registers; p, r and the inverse diagonal (FP32:
-// it only shapes the preconditioner) live in LDS, so the SpMV gathers and every vector
-// pass stay on the CU and only the ELL values and columns stream from memory.
-template <typename S, int R, int B>
-__device__ int pcg_regs(const FineArgs& a, const S* __restrict__ jv, S* __restrict__ p_l,
-                        S* __restrict__ r_l, const float* __restrict__ d_l, S* __restrict__ tq_l,
-                        const double* __restrict__ Rres, double rs, S* __restrict__ xout, double tgt,
-                        S* lds_s, int& ph) {
-    const int tid = threadIdx.x, n = a.n;
-    const int lane = tid & 63, wave = tid >> 6, nw = B >> 6;
-    const long NP = a.ell_pad;
-    const int W = a.W;
-    S x[R], q[R];
-    unsigned tailmask = 0;
-    const __amdgpu_buffer_rsrc_t rv_j = buffer_rsrc(jv, (unsigned)(W * NP * sizeof(S)));
-    const __amdgpu_buffer_rsrc_t rv_c = buffer_rsrc(a.ecol16, (unsigned)(W * NP * 2));
-    const __amdgpu_buffer_rsrc_t rv_cp = buffer_rsrc(a.ecolp, (unsigned)(((W + 1) / 2) * NP * 4));
-    // One tail row of at most B entries (the usual case): every thread takes one of its
-    // entries and the first block reduction of an iteration carries the row's product
-    // with p.q, so no wave runs a serial row sum.  Otherwise one wave per tail row.
-    const bool tail1 = a.ntail == 1 && a.tail_ptr[1] - a.tail_ptr[0] <= B;
-    const int t_beg = tail1 ? a.tail_ptr[0] : 0;
-    const int t_len = tail1 ? a.tail_ptr[1] - t_beg : 0;
-    const int t_row = tail1 ? a.tail_row[0] : 0;
-    const __amdgpu_buffer_rsrc_t rv_tv = buffer_rsrc(jv + W * NP + t_beg, (unsigned)(t_len * sizeof(S)));
-    const __amdgpu_buffer_rsrc_t rv_tc = buffer_rsrc(a.tail_col + t_beg, (unsigned)(t_len * 4));
-    S loc[2] = {0, 0};
-#pragma unroll
-    for (int k = 0; k < R; ++k) {
-        const int i = tid + k * B;
-        x[k] = 0;
-        q[k] = 0;
-        if (i < n) {
-            const S rv = (S)(-Rres[i] * rs);
-            const S z = (S)d_l[i] * rv;
-            r_l[i] = rv;
-            p_l[i] = z;
-            loc[0] += rv * z;
-            loc[1] += rv * rv;
-            if (a.ecol[i] < 0) tailmask |= 1u << k;
-        }
-    }
-    block_sum<S, 2, B / 64>(loc, lds_s, ph);
-    S rz = loc[0];
-    double rr = (double)loc[1];
-    int it = 0;
-    while (rr > tgt * tgt && it < a.max_lin) {
-        // this thread's tail entry: loads issued first, used after the ELL rounds
-        const S tv = buffer_load<S>(rv_tv, tid < t_len ? tid * (unsigned)sizeof(S) : kBufferNone);
-        const unsigned tc = (unsigned)__builtin_amdgcn_raw_buffer_load_b32(rv_tc, tid < t_len ? tid * 4u : kBufferNone, 0, 0);
-        // ELL rows, slot-major, all LDS gathers of a round issued before its FMAs.  Every
-        // load is issued: rows >= n load nothing and slots >= W fall past the ELL arrays,
-        // both reading value 0 and column 0; tail rows hold zero values and column 0.
-        // Every row adds its slots in order 0..W-1, then exact zeros.
-#pragma unroll
-        for (int k = 0; k < R; ++k) q[k] = 0;
-        if constexpr (sizeof(S) == 4) {
-            // FP32: slot pairs, one 32-bit load bringing the columns of slots 2w (low half)
-            // and 2w+1 (high half), so a pair costs two value loads and one column load
-            // per row; UP pairs of all R row groups per round (at most 4 pairs in flight).
-            constexpr int UP = R >= 4 ? 1 : 4 / R;
-            const int W2 = (W + 1) / 2;
-            for (int w2 = 0; w2 < W2; w2 += UP) {
-                S v0[UP][R], v1[UP][R], g0[UP][R], g1[UP][R];
-                unsigned cw[UP][R];
-#pragma unroll
-                for (int u = 0; u < UP; ++u)
-#pragma unroll
-                    for (int k = 0; k < R; ++k) {
-                        const int i = tid + k * B;
-                        const unsigned e0 = (unsigned)((2 * (w2 + u)) * NP + i);
-                        const unsigned ep = (unsigned)((w2 + u) * NP + i);
-                        v0[u][k] = buffer_load<S>(rv_j, i < n ? e0 * (unsigned)sizeof(S) : kBufferNone);
-                        v1[u][k] = buffer_load<S>(rv_j, i < n ? (e0 + (unsigned)NP) * (unsigned)sizeof(S) : kBufferNone);
-                        cw[u][k] = (unsigned)__builtin_amdgcn_raw_buffer_load_b32(rv_cp, i < n ? ep * 4u : kBufferNone, 0, 0);
-                    }
-                __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-                for (int u = 0; u < UP; ++u)
-#pragma unroll
-                    for (int k = 0; k < R; ++k) {
-                        g0[u][k] = p_l[cw[u][k] & 0xffffu];
-                        g1[u][k] = p_l[cw[u][k] >> 16];
-                    }
-                __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-                for (int u = 0; u < UP; ++u)
-#pragma unroll
-                    for (int k = 0; k < R; ++k) {
-                        q[k] += v0[u][k] * g0[u][k];
-                        q[k] += v1[u][k] * g1[u][k];
-                    }
-            }
-        } else {
-            // FP64: one slot of 16-bit columns at a time, U slots of all R row groups per
-            // round (U R = 8 loads of each stream in flight).  Packed column pairs measure
-            // no faster here: the FP64 value stream dominates and the wider rounds cost
-            // registers.
-            constexpr int U = R >= 8 ? 1 : 8 / R;
-            for (int w0 = 0; w0 < W; w0 += U) {
-                S v[U][R], pg[U][R];
-                unsigned col[U][R];
-#pragma unroll
-                for (int u = 0; u < U; ++u)
-#pragma unroll
-                    for (int k = 0; k < R; ++k) {
-                        const int i = tid + k * B;
-                        const unsigned e = (unsigned)((w0 + u) * NP + i);
-                        v[u][k] = buffer_load<S>(rv_j, i < n ? e * (unsigned)sizeof(S) : kBufferNone);
-                        col[u][k] = __builtin_amdgcn_raw_buffer_load_b16(rv_c, i < n ? e * 2u : kBufferNone, 0, 0);
-                    }
-                __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-                for (int u = 0; u < U; ++u)
-#pragma unroll
-                    for (int k = 0; k < R; ++k) pg[u][k] = p_l[col[u][k]];
-                __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-                for (int u = 0; u < U; ++u)
-#pragma unroll
-                    for (int k = 0; k < R; ++k) q[k] += v[u][k] * pg[u][k];
-            }
-        }
-        S dot[2] = {0, 0};
-#pragma unroll
-        for (int k = 0; k < R; ++k) {
-            const int i = tid + k * B;
-            if (i < n && !((tailmask >> k) & 1u)) dot[0] += p_l[i] * q[k];
-        }
-        if (tail1) {
-            const S qt = tv * p_l[tc];
-            dot[1] = qt;
-            dot[0] += p_l[t_row] * qt;
-        } else {
-            for (int t = wave; t < a.ntail; t += nw) {
-                const S acc = tail_row_sum<S>(a, jv, p_l, t, lane);
-                if (lane == 0) {
-                    tq_l[t] = acc;
-                    dot[0] += p_l[a.tail_row[t]] * acc;
-                }
-            }
-        }
-        block_sum<S, 2, B / 64>(dot, lds_s, ph);
-        const S pq = dot[0];
-        if (!(pq > (S)0)) break;                 // loss of positivity: Newton decides
-        const S alpha = rz / pq;
-        S l2[2] = {0, 0};
-#pragma unroll
-        for (int k = 0; k < R; ++k) {
-            const int i = tid + k * B;
-            if (i < n) {
-                if ((tailmask >> k) & 1u) q[k] = tail1 ? dot[1] : tq_l[a.ecol[NP + i]];
-                x[k] += alpha * p_l[i];
-                const S rv = r_l[i] - alpha * q[k];
-                r_l[i] = rv;
-                const S z = (S)d_l[i] * rv;
-                l2[0] += rv * z;
-                l2[1] += rv * rv;
-            }
-        }
-        block_sum<S, 2, B / 64>(l2, lds_s, ph);
-        ++it;
-        rr = (double)l2[1];
-        if (rr <= tgt * tgt) break;
-        const S beta = l2[0] / rz;
-        rz = l2[0];
-#pragma unroll
-        for (int k = 0; k < R; ++k) {
-            const int i = tid + k * B;
-            if (i < n) p_l[i] = (S)d_l[i] * r_l[i] + beta * p_l[i];
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int k = 0; k < R; ++k) {
-        const int i = tid + k * B;
-        if (i < n) xout[i] = x[k];
-    }
-    return it;
-}
-
-// Same algorithm with the vectors in memory: r, q, x in global memory; p in LDS when
-// LP >= 1 (the SpMV gathers then stay on the CU), the inverse diagonal in LDS when
-// LP == 2.  pl / dl are the LDS arrays (unused otherwise).
-template <typename S, int LP>
-__device__ int pcg_mem(const FineArgs& a, const S* __restrict__ jv, S* __restrict__ pv,
-                       S* __restrict__ pl, S* __restrict__ dl, const double* __restrict__ Rres,
-                       double rs, double tgt, S* lds_s, int& ph) {
-    const int B = blockDim.x, tid = threadIdx.x, n = a.n;
-    const int lane = tid & 63, wave = tid >> 6, nw = B >> 6;
-    const long NP = a.ell_pad;
-    const long VP = a.n_pad;
-    const int W = a.W;
-    S* pr = pv + P_R * VP;
-    S* pp = LP >= 1 ? pl : pv + P_P * VP;
-    S* pq = pv + P_Q * VP;
-    S* px = pv + P_X * VP;
-    const S* pd = LP == 2 ? dl : pv + P_D * VP;
-    S loc[2] = {0, 0};
-    for (int i = tid; i < n; i += B) {
-        const S rv = (S)(-Rres[i] * rs);
-        const S z = pd[i] * rv;
-        pr[i] = rv;
-        pp[i] = z;
-        px[i] = 0;
-        loc[0] += rv * z;
-        loc[1] += rv * rv;
-    }
-    block_sum<S, 2>(loc, lds_s, ph);
-    S rz = loc[0];
-    double rr = (double)loc[1];
-    int it = 0;
-    while (rr > tgt * tgt && it < a.max_lin) {
-        S dot[1] = {0};
-#pragma unroll 2
-        for (int i = tid; i < n; i += B) {
-            int col[kEllMaxWidth];
-            S val[kEllMaxWidth];
-#pragma unroll
-            for (int w = 0; w < kEllMaxWidth; ++w) {
-                col[w] = w < W ? a.ecol[w * NP + i] : 0;
-                val[w] = w < W ? jv[w * NP + i] : (S)0;
-            }
-            if (col[0] >= 0) {
-                S acc = 0;
-#pragma unroll
-                for (int w = 0; w < kEllMaxWidth; ++w)
-                    if (w < W) acc += val[w] * pp[col[w]];
-                pq[i] = acc;
-                dot[0] += pp[i] * acc;
-            }
-        }
-        for (int t = wave; t < a.ntail; t += nw) {
-            const S acc = tail_row_sum<S>(a, jv, pp, t, lane);
-            if (lane == 0) {
-                const int row = a.tail_row[t];
-                pq[row] = acc;
-                dot[0] += pp[row] * acc;
-            }
-        }
-        block_sum<S, 1>(dot, lds_s, ph);
-        const S pqv = dot[0];
-        if (!(pqv > (S)0)) break;
-        const S alpha = rz / pqv;
-        S l2[2] = {0, 0};
-#pragma unroll 2
-        for (int i = tid; i < n; i += B) {
-            px[i] += alpha * pp[i];
-            const S rv = pr[i] - alpha * pq[i];
-            pr[i] = rv;
-            l2[0] += rv * (pd[i] * rv);
-            l2[1] += rv * rv;
-        }
-        block_sum<S, 2>(l2, lds_s, ph);
-        ++it;
-        rr = (double)l2[1];
-        if (rr <= tgt * tgt) break;
-        const S beta = l2[0] / rz;
-        rz = l2[0];
-#pragma unroll 2
-        for (int i = tid; i < n; i += B) pp[i] = pd[i] * pr[i] + beta * pp[i];
-        __syncthreads();
-    }
-    return it;
-}
-
-// R > 0: PCG rows in registers, p / diagonal / tail sums in dynamic LDS;
-// R == 0: PCG vectors in memory, with p (LP >= 1) and the diagonal (LP == 2) in LDS.
-template <typename S, int R, int BLOCK, int LP>
-__device__ __forceinline__ void fine_chain(const FineArgs& a, const int c, unsigned char* dyn_lds,
-                                           double* lds_d, S* lds_s) {
-    int ph_d = 0, ph_s = 0;                   // chain n = c + 1
-    const int n = a.n;
-    const long NP = a.n_pad;
-    double* vec = a.vec + (long)c * kFineVec * NP;
-    double* u = vec + V_U * NP;
-    double* up = vec + V_UP * NP;
-    double* R_ = vec + V_R * NP;
-    double* Rt = vec + V_RT * NP;
-    double* upp = vec + V_UPP * NP;
-    double* up3 = vec + V_UP3 * NP;           // u_{j-3}
-    double* ut = vec + V_UT * NP;             // trial state of the line search
-    double* cp = vec + V_CP * NP;             // M u_prev / dt
-    S* pv = reinterpret_cast<S*>(a.pcg) + (long)c * kPcgVec * NP;
-    S* px = pv + P_X * NP;
-    S* jv = reinterpret_cast<S*>(a.jac) + (long)c * a.vals_pad;
-    double* el = a.elem + (long)c * 8 * a.nl_pad;
-    S* p_l = reinterpret_cast<S*>(dyn_lds);
-    S* d_l = p_l + NP;                        // memory path: inverse diagonal (LP == 2)
-    S* r_l = p_l + NP;                        // register path: r
-    float* df_l = reinterpret_cast<float*>(r_l + NP);   // register path: FP32 diagonal
-    S* tq_l = reinterpret_cast<S*>(df_l + NP);
-    S* dinv = LP == 2 ? d_l : pv + P_D * NP;
-
-    const double* U0 = a.U + (long)c * n;
-    double* Tc = a.traj ? a.traj + (long)c * (a.m + 1) * n : nullptr;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        u[i] = U0[i];
-        if (Tc) Tc[i] = U0[i];
-    }
-    init_jac<S>(a, jv);
-    __syncthreads();
-
-    const double t0 = (double)c * (a.T / a.N);
-    const double inv_dt = 1.0 / a.dt;
-    int status = 0, fail_step = -1;
-    int newton_total = 0, lin_total = 0, newton_max = 0, lin_max = 0, capped = 0, resid_evals = 0;
-
-    for (int j = 1; j <= a.m && status == 0; ++j) {
-        const double t = t0 + j * a.dt;
-        // u_{j-1} -> u_prev (u_{j-2}, u_{j-3} kept for the predictor)
-        for (int i = threadIdx.x; i < n; i += blockDim.x) {
-            up3[i] = upp[i];
-            upp[i] = up[i];
-            up[i] = u[i];
-        }
-        __syncthreads();
-        const double cur = current(t, a.f0, a.n_h, a.wavtab);
-        double v1[1] = {mass_prev(a, up, inv_dt, cp)};
-        block_sum<double, 1>(v1, lds_d, ph_d);
-        const double scale = fabs(cur) * a.fnorm + sqrt(v1[0]);
-        const double target = a.tol_newton * scale;
-
-        nl_element_pass(a, u, el);
-        ++resid_evals;
-        __syncthreads();
-        double v2[1] = {resid_rows(a, u, cp, el, cur, R_)};
-        block_sum<double, 1>(v2, lds_d, ph_d);
-        double rn = sqrt(v2[0]);
-        if (!isfinite(rn)) { status = PPC_ERR_NONFINITE; fail_step = j; break; }
-        // Newton starts from the extrapolation of the previous steps (quadratic
-        // 3 u_{j-1} - 3 u_{j-2} + u_{j-3} from the third step on, linear 2 u_{j-1} - u_{j-2}
-        // at the second) when that has the smaller residual; it changes only the iteration
-        // count, not the step's solution
-        if (j >= 2 && a.predictor && rn > target) {
-            if (j >= 3)
-                for (int i = threadIdx.x; i < n; i += blockDim.x) ut[i] = 3.0 * (up[i] - upp[i]) + up3[i];
-            else
-                for (int i = threadIdx.x; i < n; i += blockDim.x) ut[i] = 2.0 * up[i] - upp[i];
-            __syncthreads();
-            nl_element_pass(a, ut, el);
-            ++resid_evals;
-            __syncthreads();
-            double v4[1] = {resid_rows(a, ut, cp, el, cur, Rt)};
-            block_sum<double, 1>(v4, lds_d, ph_d);
-            const double rp = sqrt(v4[0]);
-            if (rp < rn) {
-                double* tmp = R_;
-                R_ = Rt;
-                Rt = tmp;
-                tmp = u;
-                u = ut;
-                ut = tmp;
-                rn = rp;
-            } else {
-                nl_element_pass(a, u, el);
-                ++resid_evals;
-                __syncthreads();
-            }
-        }
-
-        int it = 0;
-        for (;; ++it) {
-            if (rn <= target) break;
-            if (it == a.max_newton) { status = PPC_ERR_NEWTON; fail_step = j; break; }
-            assemble_nl<S>(a, el, jv);
-            __syncthreads();
-            if constexpr (R > 0) {
-                for (int i = threadIdx.x; i < n; i += blockDim.x) df_l[i] = (float)(1.0 / (double)jv[a.dpos[i]]);
-            } else {
-                for (int i = threadIdx.x; i < n; i += blockDim.x) dinv[i] = (S)1 / jv[a.dpos[i]];
-            }
-            __syncthreads();
-            const double ltarget = fmax(a.tol_lin * rn, 0.5 * target);
-            // FP32 PCG solves for the unit right-hand side -R/||R|| (near convergence the
-            // residual and its products would fall below FP32's range); the step px * xs
-            // is formed in FP64.  FP64 solves use R itself.
-            const double rs = (sizeof(S) == 4 && rn > 0.0) ? 1.0 / rn : 1.0;
-            const double xs = (sizeof(S) == 4 && rn > 0.0) ? rn : 1.0;
-            int k;
-            if constexpr (R > 0)
-                k = pcg_regs<S, R, BLOCK>(a, jv, p_l, r_l, df_l, tq_l, R_, rs, px, ltarget * rs, lds_s, ph_s);
-            else
-                k = pcg_mem<S, LP>(a, jv, pv, p_l, d_l, R_, rs, ltarget * rs, lds_s, ph_s);
-            __syncthreads();
-            lin_total += k;
-            lin_max = k > lin_max ? k : lin_max;
-            if (k == a.max_lin) ++capped;
-            // ---- Newton update with backtracking -------------------------------------------
-            double nrm[2] = {0.0, 0.0};
-            for (int i = threadIdx.x; i < n; i += blockDim.x) {
-                const double dv = (double)px[i] * xs;
-                nrm[0] += dv * dv;
-                nrm[1] += u[i] * u[i];
-            }
-            block_sum<double, 2>(nrm, lds_d, ph_d);
-            if (sqrt(nrm[0]) <= 4.0 * DBL_EPSILON * sqrt(nrm[1])) {
-                for (int i = threadIdx.x; i < n; i += blockDim.x) u[i] = u[i] + (double)px[i] * xs;
-                __syncthreads();
-                ++it;
-                break;
-            }
-            double lam = 1.0;
-            double rt = 0.0;
-            bool accepted = false, stalled = false;
-            while (true) {
-                for (int i = threadIdx.x; i < n; i += blockDim.x) ut[i] = u[i] + lam * ((double)px[i] * xs);
-                __syncthreads();
-                nl_element_pass(a, ut, el);
-                ++resid_evals;
-                __syncthreads();
-                double v3[1] = {resid_rows(a, ut, cp, el, cur, Rt)};
-                block_sum<double, 1>(v3, lds_d, ph_d);
-                rt = sqrt(v3[0]);
-                if (rt <= (1.0 - 1e-4 * lam) * rn) { accepted = true; break; }
-                lam *= 0.5;
-                if (lam < 0x1p-20) { stalled = true; break; }
-            }
-            if (stalled) {
-                if (rn <= kFloorCap * scale) { ++it; break; }
-                status = isfinite(rt) ? PPC_ERR_NEWTON : PPC_ERR_NONFINITE;
-                fail_step = j;
-                break;
-            }
-            if (accepted) {
-                double* tmp = u;
-                u = ut;
-                ut = tmp;
-                tmp = R_;
-                R_ = Rt;
-                Rt = tmp;
-                // a step that fails to halve a residual below the floor cap: the residual
-                // sits at the rounding floor of its own evaluation
-                const bool floor = rt > 0.5 * rn && rt <= kFloorCap * scale;
-                rn = rt;
-                if (floor) { ++it; break; }
-            }
-        }
-        newton_total += it;
-        newton_max = it > newton_max ? it : newton_max;
-        if (Tc)
-            for (int i = threadIdx.x; i < n; i += blockDim.x) Tc[(long)j * n + i] = u[i];
-    }
-
-    double* Fo = a.F + (long)((c + 1) % a.N) * n;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) Fo[i] = u[i];
-    if (threadIdx.x == 0) {
-        int* cnt = a.count + 8 * c;
-        cnt[C_STATUS] = status;
-        cnt[C_NEWTON] = newton_total;
-        cnt[C_LIN] = lin_total;
-        cnt[C_NEWTON_MAX] = newton_max;
-        cnt[C_LIN_MAX] = lin_max;
-        cnt[C_CAPPED] = capped;
-        cnt[C_FAILSTEP] = fail_step;
-        cnt[C_RESID] = resid_evals;
-    }
-}
-
-// out_i = -(M y)_i (CSR, kRowGroup lanes per row); returns the partial ||M y||^2
-__device__ inline double mass_apply_neg(const FineArgs& a, const double* __restrict__ y,
-                                        double* __restrict__ out) {
-    constexpr int G = kRowGroup;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    const int sub = lane % G, grp = lane / G;
-    constexpr int RPW = 64 / G;
-    double part = 0.0;
-    for (int base = wave * RPW; base < a.n; base += nw * RPW) {
-        const int i = base + grp;
-        double acc = 0.0;
-        if (i < a.n) {
-            const int k1 = a.rowptr[i + 1];
-            for (int k = a.rowptr[i] + sub; k < k1; k += G) acc += a.mval[k] * y[a.colidx[k]];
-        }
-#pragma unroll
-        for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-        if (i < a.n && sub == 0) {
-            out[i] = -acc;
-            part += acc * acc;
-        }
-    }
-    return part;
-}
-
-// One chain of the adjoint backward sweep: from Lambda_{c+1} down to lambda_{cm+1},
-// solving J_j lambda_j = M (lambda_{j+1}/dt + 2/(T dt) (du_j - du_{j+1})) for
-// j = (c+1)m .. cm+1 with J_j assembled at the stored forward state u_j.
-template <typename S, int R, int BLOCK, int LP>
-__device__ __forceinline__ void adjoint_chain(const FineArgs& a, const AdjArgs& b, const int c,
-                                              unsigned char* dyn_lds, double* lds_d, S* lds_s) {
-    int ph_d = 0, ph_s = 0;
-    const int n = a.n, m = a.m, N = a.N;
-    const long NP = a.n_pad;
-    double* vec = a.vec + (long)c * kFineVec * NP;
-    double* lam = vec + V_U * NP;
-    double* y = vec + V_UP * NP;
-    double* rhs = vec + V_R * NP;
-    S* pv = reinterpret_cast<S*>(a.pcg) + (long)c * kPcgVec * NP;
-    S* px = pv + P_X * NP;
-    S* jv = reinterpret_cast<S*>(a.jac) + (long)c * a.vals_pad;
-    double* el = a.elem + (long)c * 8 * a.nl_pad;
-    S* p_l = reinterpret_cast<S*>(dyn_lds);
-    S* d_l = p_l + NP;
-    S* r_l = p_l + NP;
-    float* df_l = reinterpret_cast<float*>(r_l + NP);
-    S* tq_l = reinterpret_cast<S*>(df_l + NP);
-    S* dinv = LP == 2 ? d_l : pv + P_D * NP;
-    const double* T0 = b.traj + (long)c * (m + 1) * n;
-    const double* T1 = b.traj + (long)((c + 1) % N) * (m + 1) * n;
-    const double* Lin = b.lam_in + (long)((c + 1) % N) * n;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) lam[i] = Lin[i];
-    init_jac<S>(a, jv);
-    __syncthreads();
-    const double inv_dt = 1.0 / a.dt;
-    const double gcoef = 2.0 / (b.T * a.dt);
-    int lin_total = 0, lin_max = 0, capped = 0;
-    for (int jl = m; jl >= 1; --jl) {
-        const double* uj = T0 + (long)jl * n;
-        const double* ujm = T0 + (long)(jl - 1) * n;
-        const double* nx0 = jl < m ? uj : T1;
-        const double* nx1 = jl < m ? T0 + (long)(jl + 1) * n : T1 + n;
-        for (int i = threadIdx.x; i < n; i += blockDim.x)
-            y[i] = lam[i] * inv_dt + gcoef * ((uj[i] - ujm[i]) - (nx1[i] - nx0[i]));
-        __syncthreads();
-        double v[1] = {mass_apply_neg(a, y, rhs)};
-        block_sum<double, 1>(v, lds_d, ph_d);
-        const double rn = sqrt(v[0]);
-        nl_element_pass(a, uj, el);
-        __syncthreads();
-        assemble_nl<S>(a, el, jv);
-        __syncthreads();
-        if constexpr (R > 0) {
-            for (int i = threadIdx.x; i < n; i += blockDim.x) df_l[i] = (float)(1.0 / (double)jv[a.dpos[i]]);
-        } else {
-            for (int i = threadIdx.x; i < n; i += blockDim.x) dinv[i] = (S)1 / jv[a.dpos[i]];
-        }
-        __syncthreads();
-        int k = 0;
-        if (rn > 0.0) {
-            if constexpr (R > 0)
-                k = pcg_regs<S, R, BLOCK>(a, jv, p_l, r_l, df_l, tq_l, rhs, 1.0, px, b.tol_lin * rn, lds_s, ph_s);
-            else
-                k = pcg_mem<S, LP>(a, jv, pv, p_l, d_l, rhs, 1.0, b.tol_lin * rn, lds_s, ph_s);
-        } else {
-            for (int i = threadIdx.x; i < n; i += blockDim.x) px[i] = 0;
-        }
-        __syncthreads();
-        lin_total += k;
-        lin_max = k > lin_max ? k : lin_max;
-        if (k == a.max_lin) ++capped;
-        double* Lall = b.lam_all + ((long)c * m + (jl - 1)) * n;
-        for (int i = threadIdx.x; i < n; i += blockDim.x) {
-            const double vv = (double)px[i];
-            lam[i] = vv;
-            Lall[i] = vv;
-        }
-        __syncthreads();
-    }
-    double* out = b.lam_out + (long)c * n;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) out[i] = lam[i];
-    if (threadIdx.x == 0) {
-        int* cnt = a.count + 8 * c;
-        cnt[C_STATUS] = 0;
-        cnt[C_NEWTON] = 0;
-        cnt[C_LIN] = lin_total;
-        cnt[C_NEWTON_MAX] = 0;
-        cnt[C_LIN_MAX] = lin_max;
-        cnt[C_CAPPED] = capped;
-        cnt[C_FAILSTEP] = -1;
-        cnt[C_RESID] = 0;
-    }
-}
-
-template <typename S, int R, int BLOCK, int LP>
-__global__ __launch_bounds__(BLOCK) void k_adjoint_sweep(FineArgs a, AdjArgs b) {
-    extern __shared__ unsigned char dyn_lds[];
-    __shared__ double lds_d[2 * 16 * 4];
-    __shared__ S lds_s[2 * 16 * 4];
-    adjoint_chain<S, R, BLOCK, LP>(a, b, blockIdx.x, dyn_lds, lds_d, lds_s);
-}
-
-template <typename S, int R, int BLOCK, int LP>
-__global__ __launch_bounds__(BLOCK) void k_fine_sweep(FineArgs a) {
-    extern __shared__ unsigned char dyn_lds[];
-    __shared__ double lds_d[2 * 16 * 4];
-    __shared__ S lds_s[2 * 16 * 4];
-    fine_chain<S, R, BLOCK, LP>(a, blockIdx.x, dyn_lds, lds_d, lds_s);
-}
-
-// Batched designs: block b runs chain work[b].y of design work[b].x, whose arguments are
-// args[work[b].x] (a work list over every design of one kernel shape, longest first).
-template <typename S, int R, int BLOCK, int LP>
-__global__ __launch_bounds__(BLOCK) void k_fine_sweep_batch(const FineArgs* __restrict__ args,
-                                                            const int2* __restrict__ work) {
-    extern __shared__ unsigned char dyn_lds[];
-    __shared__ double lds_d[2 * 16 * 4];
-    __shared__ S lds_s[2 * 16 * 4];
-    const int2 wk = work[blockIdx.x];
-    fine_chain<S, R, BLOCK, LP>(args[wk.x], wk.y, dyn_lds, lds_d, lds_s);
-}
 
 namespace {
 
 
-// Register rows (R in {1, 2, 4, 8} rows per thread, 1024 threads) when p, r, the FP32
-// diagonal and the tail sums fit in LDS; otherwise the memory path with as much of p /
-// the inverse diagonal in LDS as fits.
-FineShape pick_shape(int n, size_t n_pad, int n_tail, size_t elem, int block_req) {
+// Register rows (R in {1, 2, 4, 8} rows per thread, the smallest with R rows_block >= n, in
+// workgroups of rows_block threads) when p, r, the FP32 diagonal and the tail sums fit in
+// LDS; otherwise (or with block_req = 1024) the memory path with 1024 threads and as much
+// of p / the inverse diagonal in LDS as fits.
+FineShape pick_shape(int n, size_t n_pad, int n_tail, size_t elem, int block_req, int rows_block) {
     const size_t tail = (size_t)std::max(n_tail, 1) * elem;
     if (block_req != kFineBlock) {
         for (int R : {1, 2, 4, 8}) {
-            if ((long)R * kFineBlock < n) continue;
+            if ((long)R * rows_block < n) continue;
             const size_t lds = 2 * n_pad * elem + n_pad * sizeof(float) + tail;
-            if (lds <= kLdsBudget) return {R, kFineBlock, 0, lds};
+            if (lds <= kLdsBudget) return {R, rows_block, 0, lds};
             break;
         }
     }
@@ -856,7 +39,8 @@ void launch_shape(const FineArgs& a, int N, size_t lds, hipStream_t s) {
 
 template <typename S>
 void launch_typed(const FineArgs& a, int N, const FineShape& sh, hipStream_t s) {
-    if (sh.R == 1) launch_shape<S, 1, kFineBlock, 0>(a, N, sh.lds, s);
+    if (sh.R > 0 && sh.block != kFineBlock) launch_fine_rows_small(a, N, sh, sizeof(S) == 8, s);
+    else if (sh.R == 1) launch_shape<S, 1, kFineBlock, 0>(a, N, sh.lds, s);
     else if (sh.R == 2) launch_shape<S, 2, kFineBlock, 0>(a, N, sh.lds, s);
     else if (sh.R == 4) launch_shape<S, 4, kFineBlock, 0>(a, N, sh.lds, s);
     else if (sh.R == 8) launch_shape<S, 8, kFineBlock, 0>(a, N, sh.lds, s);
@@ -966,12 +150,25 @@ FineArgs make_fine_args(ppc_problem* pr, const ppc_params* p, const double* U, d
     return a;
 }
 
-FineShape fine_shape(const ppc_problem* pr, const ppc_params* p) {
+FineShape rows_shape(const ppc_problem* pr, const ppc_params* p, int rows_block) {
     const size_t elem = p->precision == 0 ? sizeof(double) : sizeof(float);
     // the register-row SpMV reads 16-bit columns (built for n < 65536; R B <= 8192 rows)
     const int block = pr->mesh.ecol16 ? p->block : kFineBlock;
-    return pick_shape(pr->mesh.n_free, pr->ws.n_pad, pr->mesh.n_tail, elem, block);
+    return pick_shape(pr->mesh.n_free, pr->ws.n_pad, pr->mesh.n_tail, elem, block, rows_block);
 }
+
+// Register-row workgroup size: params->fine_block when set, else the tuned size of this
+// precision, else 1024.  A forced size whose rows do not fit is an argument error.
+FineShape fine_shape(const ppc_problem* pr, const ppc_params* p) {
+    const int tuned = pr->tuned_block[p->precision != 0 ? 1 : 0];
+    const int rb = p->fine_block ? p->fine_block : (tuned ? tuned : kFineBlock);
+    const FineShape sh = rows_shape(pr, p, rb);
+    if (p->fine_block && sh.R == 0)
+        fail(PPC_ERR_ARG, "fine_block " + std::to_string(p->fine_block) + ": the mesh's " +
+                              std::to_string(pr->mesh.n_free) + " rows do not fit register rows at that size");
+    return sh;
+}
+
 
 void launch_fine_sweep(ppc_problem* pr, const ppc_params* p, const double* U, double* F,
                        hipStream_t s) {
@@ -1017,7 +214,8 @@ void launch_adj_shape(const FineArgs& a, const AdjArgs& b, size_t lds, hipStream
 void launch_adjoint_sweep(ppc_problem* pr, const ppc_params* p, const AdjArgs& b, hipStream_t s) {
     ensure_jbase(pr, p, s);
     const FineArgs a = make_fine_args(pr, p, nullptr, nullptr);
-    const FineShape sh = pick_shape(pr->mesh.n_free, pr->ws.n_pad, pr->mesh.n_tail, sizeof(double), p->block);
+    const FineShape sh = pick_shape(pr->mesh.n_free, pr->ws.n_pad, pr->mesh.n_tail, sizeof(double), p->block,
+                                    kFineBlock);
     if (sh.R == 1) launch_adj_shape<1, 0>(a, b, sh.lds, s);
     else if (sh.R == 2) launch_adj_shape<2, 0>(a, b, sh.lds, s);
     else if (sh.R == 4) launch_adj_shape<4, 0>(a, b, sh.lds, s);
@@ -1045,7 +243,8 @@ void launch_batch_shape(const FineArgs* args, const int2* work, int nblocks, siz
 template <typename S>
 void launch_batch_typed(const FineArgs* args, const int2* work, int nblocks, const FineShape& sh,
                         hipStream_t s) {
-    if (sh.R == 1) launch_batch_shape<S, 1, 0>(args, work, nblocks, sh.lds, s);
+    if (sh.R > 0 && sh.block != kFineBlock) launch_fine_batch_rows_small(args, work, nblocks, sh, sizeof(S) == 8, s);
+    else if (sh.R == 1) launch_batch_shape<S, 1, 0>(args, work, nblocks, sh.lds, s);
     else if (sh.R == 2) launch_batch_shape<S, 2, 0>(args, work, nblocks, sh.lds, s);
     else if (sh.R == 4) launch_batch_shape<S, 4, 0>(args, work, nblocks, sh.lds, s);
     else if (sh.R == 8) launch_batch_shape<S, 8, 0>(args, work, nblocks, sh.lds, s);
@@ -1054,7 +253,7 @@ void launch_batch_typed(const FineArgs* args, const int2* work, int nblocks, con
     else launch_batch_shape<S, 0, 0>(args, work, nblocks, 0, s);
 }
 
-int shape_key(const FineShape& sh) { return sh.R * 16 + sh.LP; }
+int shape_key(const FineShape& sh) { return sh.block * 256 + sh.R * 16 + sh.LP; }
 
 }  // namespace
 

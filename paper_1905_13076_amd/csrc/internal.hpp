@@ -173,6 +173,8 @@ struct ppc_problem {
     std::vector<int> nl_elem;        // host list of Brauer elements
     double* lawtab = nullptr;        // device [n_mat][5]: law, nu, k1, k2, k3
     double* wavtab = nullptr;        // device [n_h][3]: order, amp, phase
+    // register-row workgroup size chosen by ppc_autotune per precision (0: not tuned)
+    int tuned_block[2] = {0, 0};
     // batched problem: one sub-problem per design (the fields above are unused then)
     std::vector<ppc_problem*> parts;
     bool batch = false;
@@ -313,6 +315,19 @@ FineArgs make_fine_args(ppc_problem* pr, const ppc_params* p, const double* U, d
 FineShape fine_shape(const ppc_problem* pr, const ppc_params* p);
 void launch_fine_sweep_traj(ppc_problem* pr, const ppc_params* p, const double* U, double* F,
                             double* traj, hipStream_t s);
+// register-row workgroup sizes the library builds, and the shape one of them gives a mesh
+// (R = 0 when its rows do not fit registers and LDS at that size)
+constexpr int kRowBlocks[3] = {256, 512, 1024};
+FineShape rows_shape(const ppc_problem* pr, const ppc_params* p, int block);
+// Times one fine sweep per register-row workgroup size that fits the mesh (from U = 0 in the
+// problem's own workspace, best of two after a warm-up); ms[i] for kRowBlocks[i], NaN when
+// it does not fit.  Returns the fastest size, 0 when the mesh takes the memory path.
+int autotune_fine(ppc_problem* pr, const ppc_params* p, double ms[3], hipEvent_t e0, hipEvent_t e1,
+                  hipStream_t s);
+// 256- and 512-thread register-row kernels (fine_blocks.hip)
+void launch_fine_rows_small(const FineArgs& a, int N, const FineShape& sh, bool fp64, hipStream_t s);
+void launch_fine_batch_rows_small(const FineArgs* args, const int2* work, int nblocks, const FineShape& sh,
+                                  bool fp64, hipStream_t s);
 void launch_adjoint_sweep(ppc_problem* pr, const ppc_params* p, const AdjArgs& b, hipStream_t s);
 
 // adjoint helpers (adjoint.hip)

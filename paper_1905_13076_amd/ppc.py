@@ -236,6 +236,16 @@ class Problem:
             raise PPCError(rc, "ppc_fine_counts: no sweep with this N on this problem")
         return out
 
+    def autotune(self, prm):
+        """ppc_autotune: returns (chosen register-row workgroup size or 0, sweep ms at 256,
+        512, 1024 threads, NaN where the rows do not fit)."""
+        b = np.zeros(1, dtype=np.int32)
+        ms = np.zeros(3, dtype=np.float64)
+        rc = lib().ppc_autotune(self.handle.h, self.p, byref(prm), _pi(b), _pd(ms))
+        if rc < 0:
+            raise _err(self.handle.h, rc)
+        return int(b[0]), ms
+
     def coarse_correction(self, prm, U, J):
         """dU solving the cyclic coarse system for jumps J.  CUDA [N, n_nodes] each."""
         import torch
@@ -286,6 +296,15 @@ class BatchProblem:
             self.close()
         except Exception:
             pass
+
+    def autotune(self, prm):
+        """ppc_autotune by size class: (chosen size per design, ms [D, 3] of its class)."""
+        b = np.zeros(self.n_designs, dtype=np.int32)
+        ms = np.zeros((self.n_designs, 3), dtype=np.float64)
+        rc = lib().ppc_autotune(self.handle.h, self.p, byref(prm), _pi(b), _pd(ms))
+        if rc < 0:
+            raise _err(self.handle.h, rc)
+        return b, ms
 
     def solve(self, prm, U_init=None):
         """Returns (list of per-design U [N, n_nodes_d] CUDA views, eps [D, k+1] numpy,

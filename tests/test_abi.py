@@ -138,7 +138,8 @@ def test_invalid_problems_are_rejected_on_host(case, code, needle):
     (dict(coarse_precision=2), "coarse_precision"), (dict(coarse_precision=-2), "coarse_precision"),
     (dict(graph=2), "graph"), (dict(b_cap=-1.0), "b_cap"), (dict(b_cap=float("inf")), "b_cap"),
     (dict(init_mode=4), "init_mode"), (dict(method=2), "method"), (dict(method=-1), "method"),
-    (dict(method=1, b_cap=3.0), "b_cap"),
+    (dict(method=1, b_cap=3.0), "b_cap"), (dict(fine_block=128), "fine_block"),
+    (dict(fine_block=512, block=1024), "fine_block"),
 ])
 def test_invalid_params_are_rejected_on_host(kw, needle):
     import paper_1905_13076_amd as P
@@ -154,6 +155,7 @@ def test_null_safety_and_no_device_error():
     assert lib.ppc_params_default(None) == -1
     assert lib.ppc_problem_info(None, None, None, None, None) == -1
     assert lib.ppc_fine_counts(None, 4, None) == -1
+    assert lib.ppc_autotune(None, None, None, None, None) == -1
     assert lib.ppc_last_error(None) is not None
     h = ctypes.c_void_p()
     assert lib.ppc_create(-1, ctypes.byref(h)) == -1
