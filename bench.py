@@ -67,6 +67,9 @@ def parse():
     ap.add_argument("--method", default="ppc", choices=["ppc", "ppic"],
                     help="ppc: PP-PC, eq. (4) with the periodic coarse problem; ppic: PP-IC, "
                          "eq. (5), U_0^{k+1} = U_N^k with sequential coarse propagation")
+    ap.add_argument("--n-harm", type=int, default=0,
+                    help="harmonics each PP-PC correction solves (0: all N/2+1); the others "
+                         "take the jumps' harmonics")
     ap.add_argument("--init", default="auto", choices=["auto", "rest"],
                     help="U^0: auto (zero for nonlinear, coarse periodic for linear) or rest "
                          "(one fine sweep from zero, U^0_n = F_n(0))")
@@ -253,7 +256,7 @@ def main():
     if a.probe == "fine":
         return probe_fine(a, prob, ref)
     cpu = None
-    if a.cpu and ref is not None and a.method == "ppc" and a.init == "auto":
+    if a.cpu and ref is not None and a.method == "ppc" and a.init == "auto" and a.n_harm == 0:
         # before any GPU initialisation: the oracle's worker pool forks this process
         cpu = cpu_baseline(prob, ref, a.cpu_procs)
     import numpy as np
@@ -272,6 +275,9 @@ def main():
         extra["coarse_precision"] = 0
     extra["method"] = 1 if a.method == "ppic" else 0
     extra["init_mode"] = 3 if a.init == "rest" else 0
+    extra["n_harm"] = a.n_harm
+    if a.n_harm:
+        extra["max_iters"] = 300
     if a.method == "ppic":
         extra["max_iters"] = 300
     prm = P.problem_params(prob, tol_ppc=a.tol, precision=prec, tol_cocg=a.tol_cocg, **extra)
@@ -329,6 +335,7 @@ def main():
                         f"{prob.N // 2 + 1} harmonics, amplitude {prob.amps[0]:.1f} A",
             "precision": a.precision,
             "method": a.method,
+            "harmonics_solved": a.n_harm or prob.N // 2 + 1,
             "init": a.init,
             "tol_ppc": a.tol,
             "tol_cocg": a.tol_cocg,

@@ -138,7 +138,11 @@ typedef struct {
                                chose for this problem and precision, else 1024; 256, 512 or
                                1024 = that size (PPC_ERR_ARG when the mesh's rows do not fit:
                                R rows per thread, R <= 8, R * fine_block >= free nodes) */
-    int32_t reserved[1];
+    int32_t n_harm;         /* harmonics each PP-PC correction solves: 0 = all N/2 + 1 (eq.
+                               (12)); 1..N/2+1 = p = 0..n_harm-1 only, every other harmonic of
+                               the correction being that of the jumps (zero at the fixed point,
+                               which is therefore unchanged).  The initial coarse solve and the
+                               adjoint use all harmonics */
     double b_cap;           /* coarse-correction safeguard (T): 0 = off; > 0 = apply
                                U += theta dU with the largest theta <= 1 that keeps |B| <= b_cap
                                in every Brauer element and sample, when the full correction
@@ -176,7 +180,7 @@ int ppc_version(void);
 /* Defaults: T = 0.02, N = 10, m = 20, shift 0, lin 0, init 0, FP64, tol_ppc 1e-12,
  * max_iters 60, tol_newton 1e-13, max_newton 50, tol_lin 1e-8, max_lin 20000,
  * tol_cocg 1e-10, max_cocg 20000, block 0, predictor on, lin_point 1 (fine results),
- * coarse_precision -1, graph 1, method 0, fine_block 0, b_cap 0.
+ * coarse_precision -1, graph 1, method 0, fine_block 0, n_harm 0, b_cap 0.
  * Returns PPC_ERR_ARG on a null pointer. */
 int ppc_params_default(ppc_params* p);
 
@@ -309,8 +313,9 @@ int ppc_fine_counts(const ppc_problem* pr, int32_t n_chains, int32_t* counts);
 /* One coarse correction (Section 3, eqs. (11)-(14), in correction form): from the
  * samples U and jumps J (DEVICE [N * n_nodes]; J[n] = F_n - U_n mod N) compute
  * dU (DEVICE [N * n_nodes]) solving Q dU_n - C dU_{n-1} = Q J_n cyclically, with
- * C = M/dT, Q = C + Kbar(U) (eq. (10)).  cocg_out: host [N/2 + 1] or null (COCG
- * iterations per harmonic). */
+ * C = M/dT, Q = C + Kbar(U) (eq. (10)).  With params->n_harm the harmonics from n_harm
+ * on are those of J instead.  cocg_out: host [N/2 + 1] or null (COCG iterations per
+ * harmonic; 0 for the harmonics not solved). */
 int ppc_coarse_correction_device(ppc_handle* h, ppc_problem* pr, const ppc_params* p,
                                  const double* U_dev, const double* J_dev, double* dU_dev,
                                  int32_t* cocg_out, void* stream);

@@ -144,17 +144,28 @@ def coarse_stiffness(fe, U, lin="tensor"):
     raise ValueError(lin)
 
 
-def harmonic_solve(fe, Kbar, Rrows, T, shift="ie"):
+def harmonic_solve(fe, Kbar, Rrows, T, shift="ie", n_harm=None, Jrows=None):
     """Solve the block-cyclic coarse system G X = R (eq. (9), with G built from
     C = M/dT and Q = C + Kbar) through the DFT along time (eqs. (11)-(14)): one
     shifted sparse system (Kbar + sigma_p M) per harmonic p = 0..N/2; the negative
-    harmonics follow by conjugate symmetry.  Rows of Rrows are n = 0..N-1."""
+    harmonics follow by conjugate symmetry.  Rows of Rrows are n = 0..N-1.
+
+    Truncated harmonic set (n_harm < N/2 + 1; eq. (11) summed over a subset of the
+    spectrum of eq. (12)): only p < n_harm are solved; every other harmonic of the
+    correction is the harmonic of the jumps Jrows, X_p = J_p, which vanishes at the
+    fixed point and so leaves it unchanged (reading)."""
     N = Rrows.shape[0]
     Rh = np.fft.rfft(Rrows, axis=0)
+    H = Rh.shape[0]
+    nh = H if n_harm is None else n_harm
     Xh = np.zeros_like(Rh)
     for p, s in enumerate(shifts(N, T, shift)):
+        if p >= nh:
+            break
         A = (Kbar + s * fe.M).astype(np.complex128).tocsc()
         Xh[p] = spla.splu(A, permc_spec="MMD_AT_PLUS_A").solve(Rh[p])
+    if nh < H:
+        Xh[nh:] = np.fft.rfft(Jrows, axis=0)[nh:]
     return np.fft.irfft(Xh, n=N, axis=0)
 
 
@@ -244,7 +255,7 @@ def make_pool(prob, processes):
     return mp.get_context("fork").Pool(processes, initializer=_init_worker, initargs=(prob,))
 
 
-def coarse_correction(fe, U, J, shift="ie", lin="tensor", U_lin=None):
+def coarse_correction(fe, U, J, shift="ie", lin="tensor", U_lin=None, n_harm=None):
     """Delta U from the jumps J (rows n = 0..N-1, J[n] = F_n - U_n mod N).
 
     In the linear case eq. (4) with implicit-Euler G (eq. (8)) is equivalent to the
@@ -257,7 +268,7 @@ def coarse_correction(fe, U, J, shift="ie", lin="tensor", U_lin=None):
     Kbar = coarse_stiffness(fe, U if U_lin is None else U_lin, lin)
     Q = fe.M / (T / N) + Kbar
     R = np.asarray((Q @ J.T).T)
-    return harmonic_solve(fe, Kbar, R, T, shift)
+    return harmonic_solve(fe, Kbar, R, T, shift, n_harm=n_harm, Jrows=J)
 
 
 def brauer_bmax(fe, U):
@@ -281,8 +292,12 @@ def safeguard_step(fe, U, dU, b_cap):
 
 
 def ppc(fe, tol=1e-12, max_iter=60, U_init=None, shift="ie", lin="tensor",
-        newton_tol=NEWTON_TOL, pool=None, callback=None, init="auto", lin_point="F", b_cap=None):
+        newton_tol=NEWTON_TOL, pool=None, callback=None, init="auto", lin_point="F", b_cap=None,
+        n_harm=None):
     """Plain PP-PC (eq. (4)).
+
+    n_harm < N/2 + 1 solves only the first n_harm harmonics of each correction (the rest
+    take the jumps' harmonics; see harmonic_solve).  The initial iterate uses them all.
 
     lin_point selects the samples the frozen coarse stiffness is linearised at: "U" the
     current iterate U^k, "F" the fine results F^k of the same sweep (they coincide at the
@@ -311,7 +326,7 @@ def ppc(fe, tol=1e-12, max_iter=60, U_init=None, shift="ie", lin="tensor",
             return U, np.array(hist), k
         if k == max_iter:
             break
-        dU = coarse_correction(fe, U, J, shift, lin, U_lin=Fs if lin_point == "F" else None)
+        dU = coarse_correction(fe, U, J, shift, lin, U_lin=Fs if lin_point == "F" else None, n_harm=n_harm)
         U = U + (safeguard_step(fe, U, dU, b_cap) * dU if b_cap else dU)
     raise RuntimeError(f"PP-PC did not converge: eps history {hist[-5:]}")
 

@@ -51,7 +51,7 @@ class Params(ctypes.Structure):
                 ("max_newton", c_int32), ("tol_lin", c_double), ("max_lin", c_int32),
                 ("tol_cocg", c_double), ("max_cocg", c_int32), ("block", c_int32),
                 ("no_predictor", c_int32), ("lin_point", c_int32), ("coarse_precision", c_int32),
-                ("graph", c_int32), ("method", c_int32), ("fine_block", c_int32), ("reserved", c_int32 * 1),
+                ("graph", c_int32), ("method", c_int32), ("fine_block", c_int32), ("n_harm", c_int32),
                 ("b_cap", c_double)]
 
 

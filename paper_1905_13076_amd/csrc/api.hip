@@ -340,7 +340,7 @@ int solve_device(ppc_handle* h, ppc_problem* pr, const ppc_params* p, const doub
     // kernels' attributes and the base Jacobian, which capture must not do).
     const bool use_graph = p->graph != 0;
     const bool ic = p->method == 1;
-    const int n_solves = ic ? N : H;   // coarse solves (counter rows) per correction
+    const int n_solves = ic ? N : solved_harmonics(p, false);   // coarse solves (counter rows) per correction
     // PP-IC: the first propagation starts from U_N = U^0_0
     if (ic) PPC_HIP(hipMemcpyAsync(w.ic_un, w.U, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
     GraphExec g_fine, g_coarse;
@@ -482,7 +482,8 @@ int solve_batch_device(ppc_handle* h, ppc_problem* bp, const ppc_params* p, cons
             launch_coarse_pre(parts[d], p, excitation ? nullptr : (p->lin_point == 1 ? w.F : w.U),
                               excitation ? nullptr : w.J, excitation, s);
         }
-        launch_cocg_batch(parts, list, p, static_cast<CocgArgs*>(cargs.p), static_cast<int2*>(cwork.p), cw, s);
+        const int Hs = solved_harmonics(p, excitation);
+        launch_cocg_batch(parts, list, p, Hs, static_cast<CocgArgs*>(cargs.p), static_cast<int2*>(cwork.p), cw, s);
         for (int d : list) {
             Workspace& w = parts[d]->ws;
             if (!excitation && p->b_cap > 0.0) {
@@ -496,7 +497,7 @@ int solve_batch_device(ppc_handle* h, ppc_problem* bp, const ppc_params* p, cons
             PPC_HIP(hipMemcpyAsync(ccount.data(), parts[d]->ws.ccount, ccount.size() * sizeof(int),
                                    hipMemcpyDeviceToHost, s));
             PPC_HIP(hipStreamSynchronize(s));
-            for (int q = 0; q < H; ++q) {
+            for (int q = 0; q < Hs; ++q) {
                 if (ccount[4 * q] != 0)
                     fail(ccount[4 * q], "design " + std::to_string(d) + ": " +
                                             (ccount[4 * q] == PPC_ERR_BREAKDOWN ? "COCG breakdown" : "non-finite COCG residual"));
@@ -634,6 +635,8 @@ int adjoint_device(ppc_handle* h, ppc_problem* pr, const ppc_params* p, const do
     const DeviceMesh& d = pr->mesh;
     const int N = p->N, m = p->m, n = d.n_free, H = N / 2 + 1;
     const int n_mat = pr->laws.n_mat;
+    ppc_params p_full = *p;   // the adjoint's corrections solve every harmonic
+    p_full.n_harm = 0;
     DevBuf traj, lam_all, Lam, FB, JR, dLR, part, out1, dsig, dke, dkm, Unod;
     PPC_HIP(hipMalloc(&traj.p, sizeof(double) * (size_t)N * (m + 1) * n));
     PPC_HIP(hipMalloc(&lam_all.p, sizeof(double) * (size_t)N * m * n));
@@ -699,7 +702,7 @@ int adjoint_device(ppc_handle* h, ppc_problem* pr, const ppc_params* p, const do
         // in reversed subinterval order is the forward one), K frozen at the samples U
         PPC_HIP(hipEventRecord(ev[2], s));
         launch_reverse_rows(N, n, w.J, static_cast<double*>(JR.p), s);
-        launch_coarse(pr, p, w.U, static_cast<double*>(JR.p), static_cast<double*>(dLR.p), false, false, s);
+        launch_coarse(pr, &p_full, w.U, static_cast<double*>(JR.p), static_cast<double*>(dLR.p), false, false, s);
         launch_add_reversed(N, n, static_cast<double*>(dLR.p), dL, s);
         PPC_HIP(hipEventRecord(ev[3], s));
         read_cocg(pr, H, s, nullptr, &S.cocg_total, &S.cocg_max);
@@ -1113,7 +1116,10 @@ int ppc_coarse_correction_device(ppc_handle* h, ppc_problem* pr, const ppc_param
         launch_to_free(pr, p->N, U_dev, pr->ws.U, s);
         launch_to_free(pr, p->N, J_dev, pr->ws.J, s);
         launch_coarse(pr, p, pr->ws.U, pr->ws.J, pr->ws.F, false, false, s);
-        read_cocg(pr, p->N / 2 + 1, s, cocg_out, nullptr, nullptr);
+        const int Hs = solved_harmonics(p, false);
+        read_cocg(pr, Hs, s, cocg_out, nullptr, nullptr);
+        if (cocg_out)
+            for (int q = Hs; q < p->N / 2 + 1; ++q) cocg_out[q] = 0;
         launch_to_nodal(pr, p->N, pr->ws.F, dU_dev, s);
         PPC_HIP(hipStreamSynchronize(s));
         return PPC_OK;

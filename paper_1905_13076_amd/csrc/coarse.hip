@@ -231,11 +231,11 @@ __global__ void k_twiddle(int N, double2* __restrict__ tw) {
     tw[k] = make_double2(c, -s);   // exp(-2 pi i k / N)
 }
 
-// Rhat[p][i] = sum_s R[s][i] exp(-2 pi i p s / N), p = 0..N/2
-__global__ void k_dft(int n, int N, const double* __restrict__ R, const double2* __restrict__ tw,
+// Rhat[p][i] = sum_s R[s][i] exp(-2 pi i p s / N) for harmonics p = p0 + blockIdx.y
+__global__ void k_dft(int n, int N, int p0, const double* __restrict__ R, const double2* __restrict__ tw,
                       double2* __restrict__ Rh) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int p = blockIdx.y;
+    const int p = p0 + blockIdx.y;
     if (i >= n) return;
     double re = 0.0, im = 0.0;
     for (int s = 0; s < N; ++s) {
@@ -1027,7 +1027,13 @@ void launch_coarse_pre(ppc_problem* pr, const ppc_params* p, const double* U, co
         hipLaunchKernelGGL(k_coarse_rhs, rg, dim3(256), 0, s, n, N, d.rowptr, d.colidx, d.mval, w.kbar,
                            1.0 / dT, J, w.R);
     hipLaunchKernelGGL(k_twiddle, dim3((N + 255) / 256), dim3(256), 0, s, N, w.twiddle);
-    hipLaunchKernelGGL(k_dft, dim3((n + 255) / 256, H), dim3(256), 0, s, n, N, w.R, w.twiddle, w.rhat);
+    const int Hs = solved_harmonics(p, excitation_rhs);
+    hipLaunchKernelGGL(k_dft, dim3((n + 255) / 256, Hs), dim3(256), 0, s, n, N, 0, w.R, w.twiddle, w.rhat);
+    // truncated harmonic set: the unsolved harmonics of the correction are those of the jumps,
+    // written straight into the solution block
+    if (Hs < H)
+        hipLaunchKernelGGL(k_dft, dim3((n + 255) / 256, H - Hs), dim3(256), 0, s, n, N, Hs, J, w.twiddle,
+                           w.rhat + (long)H * n);
     hipLaunchKernelGGL(k_shifts, dim3((H + 63) / 64), dim3(64), 0, s, N, p->T, p->shift_mode, w.sig);
     PPC_HIP(hipGetLastError());
 }
@@ -1038,7 +1044,7 @@ CocgArgs make_cocg_args(ppc_problem* pr, const ppc_params* p) {
     const int H = p->N / 2 + 1;
     CocgArgs a{};
     a.n = d.n_free;
-    a.H = H;
+    a.H = solved_harmonics(p, false);    // the solution block still holds all H harmonics
     a.rowptr = d.rowptr;
     a.colidx = d.colidx;
     a.kbar = w.kbar;
@@ -1139,7 +1145,9 @@ void launch_cocg_solves(const ppc_problem* pr, const CocgArgs& a, hipStream_t s)
 void launch_coarse(ppc_problem* pr, const ppc_params* p, const double* U, const double* J,
                    double* dU, bool accumulate, bool excitation_rhs, hipStream_t s) {
     launch_coarse_pre(pr, p, U, J, excitation_rhs, s);
-    launch_cocg_solves(pr, make_cocg_args(pr, p), s);
+    CocgArgs a = make_cocg_args(pr, p);
+    a.H = solved_harmonics(p, excitation_rhs);
+    launch_cocg_solves(pr, a, s);
     launch_coarse_post(pr, p, dU, accumulate, s);
 }
 
@@ -1172,9 +1180,8 @@ void launch_ic_propagation(ppc_problem* pr, const ppc_params* p, hipStream_t s) 
 // design launch picks it, so a design's arithmetic does not depend on its batch) and
 // each group is one launch.  cw keeps the host work list alive for the copy.
 void launch_cocg_batch(const std::vector<ppc_problem*>& parts, const std::vector<int>& list,
-                       const ppc_params* p, const CocgArgs* d_args, int2* d_work, std::vector<int2>& cw,
+                       const ppc_params* p, int H, const CocgArgs* d_args, int2* d_work, std::vector<int2>& cw,
                        hipStream_t s) {
-    const int H = p->N / 2 + 1;
     struct Span {
         int R;
         size_t lds;

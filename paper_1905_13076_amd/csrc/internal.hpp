@@ -302,6 +302,13 @@ int validate_problem(const ppc_mesh* mesh, const ppc_material* mat, const ppc_ex
                      std::string& msg);
 int validate_params(const ppc_params* p, std::string& msg);
 
+// Harmonics a coarse correction solves: all N/2 + 1, or the first params->n_harm (the
+// others take the jumps' harmonics).  Excitation solves (the initial iterate) use all.
+inline int solved_harmonics(const ppc_params* p, bool excitation) {
+    const int H = p->N / 2 + 1;
+    return (excitation || p->n_harm <= 0 || p->n_harm > H) ? H : p->n_harm;
+}
+
 // workspace sizing (api.hip)
 void ensure_workspace(ppc_problem* pr, const ppc_params* p);
 
@@ -347,7 +354,7 @@ void launch_coarse_pre(ppc_problem* pr, const ppc_params* p, const double* U, co
                        bool excitation_rhs, hipStream_t s);
 CocgArgs make_cocg_args(ppc_problem* pr, const ppc_params* p);
 void launch_cocg_batch(const std::vector<ppc_problem*>& parts, const std::vector<int>& list,
-                       const ppc_params* p, const CocgArgs* d_args, int2* d_work, std::vector<int2>& cw,
+                       const ppc_params* p, int H, const CocgArgs* d_args, int2* d_work, std::vector<int2>& cw,
                        hipStream_t s);
 // PP-IC coarse propagation (eq. (5) with the update of eq. (4)): frozen coarse stiffness at
 // the current iterate U, then U_0 = U_N of the last propagation and, for n = 1..N in order,

@@ -133,6 +133,8 @@ int validate_params(const ppc_params* p, std::string& msg) {
     if (p->graph < 0 || p->graph > 1) { msg = "graph must be 0 or 1"; return PPC_ERR_ARG; }
     if (p->method < 0 || p->method > 1) { msg = "method must be 0 (PP-PC) or 1 (PP-IC)"; return PPC_ERR_ARG; }
     if (p->method == 1 && p->b_cap > 0.0) { msg = "b_cap applies to PP-PC only"; return PPC_ERR_ARG; }
+    if (p->n_harm < 0 || p->n_harm > p->N / 2 + 1) { msg = "n_harm must be 0 (all) or 1..N/2+1"; return PPC_ERR_ARG; }
+    if (p->method == 1 && p->n_harm != 0) { msg = "n_harm applies to PP-PC only"; return PPC_ERR_ARG; }
     if (p->fine_block != 0 && p->fine_block != 256 && p->fine_block != 512 && p->fine_block != 1024) {
         msg = "fine_block must be 0, 256, 512 or 1024";
         return PPC_ERR_ARG;

@@ -230,6 +230,43 @@ def test_ppic_with_coincident_propagators_steps_one_period_per_iteration():
     assert seen[1][1] > 1e-3 and rel(seen[1][0], seen[2][0]) > 1e-3
 
 
+@pytest.mark.parametrize("n_harm", [1, 2, 4])
+def test_truncated_harmonic_set_keeps_the_fixed_point(n_harm):
+    """Solving only the first n_harm harmonics of each correction (the others take the
+    jumps' harmonics, which vanish at the fixed point) converges to the same periodic
+    solution: linear tiny coax against the exact DFT solve of the cyclic fine system
+    (route L), saturating tiny coax against sequential periods (route S), whose odd
+    harmonics 3 and 5 carry the saturation and so must be reached by the relaxation."""
+    prob = coax.tiny(nr=5, ntheta=10, N=8, m=4)
+    fe = FE(prob)
+    UL, _ = periodic.route_l(fe)
+    U, hist, k = periodic.ppc(fe, tol=1e-12, n_harm=n_harm, max_iter=200)
+    assert rel(U, UL) <= 1e-10
+    fn = FE(coax.tiny(nr=5, ntheta=10, N=8, m=4, nonlinear=True, amp=600.0))
+    US, _ = periodic.route_s(fn, tol=1e-13)
+    Un, _, _ = periodic.ppc(fn, tol=1e-12, n_harm=n_harm, max_iter=300)
+    H = np.abs(np.fft.rfft(US, axis=0))
+    assert H[3].max() > 1e-3 * H[1].max()            # the dropped harmonics are not empty
+    assert rel(Un, US) <= 1e-9
+    # all N/2 + 1 harmonics is the untruncated iteration, term for term
+    Ua, ha, ka = periodic.ppc(fe, tol=1e-12, n_harm=prob.N // 2 + 1)
+    Ub, hb, kb = periodic.ppc(fe, tol=1e-12)
+    assert ka == kb and np.array_equal(Ua, Ub)
+
+
+def test_truncated_harmonics_with_a_slow_transient_need_the_low_harmonics():
+    """Linearised sheath (time constant near the period): dropping every harmonic but the
+    mean leaves the fundamental to the jump relaxation, which contracts slowly, while
+    keeping the fundamental converges as fast as the full set."""
+    prob = coax.c2lin(nr=6, ntheta=12, N=8, m=6)
+    fe = FE(prob)
+    _, hf, kf = periodic.ppc(fe, tol=1e-9, max_iter=300)
+    _, h2, k2 = periodic.ppc(fe, tol=1e-9, n_harm=2, max_iter=300)
+    assert k2 <= kf + 1
+    with pytest.raises(RuntimeError, match="did not converge"):
+        periodic.ppc(fe, tol=1e-9, n_harm=1, max_iter=5 * kf)
+
+
 def test_epsilon_definition():
     U = np.ones((2, 3))
     assert periodic.periodicity_residual(U, 0.5 * U) == pytest.approx(0.5)
