@@ -64,9 +64,11 @@ def parse():
                          "first 64 (21 designs, full 40 x 50 grid), one batched solve per step; "
                          "c2lin: C2 with the steel linearised at its unsaturated reluctivity")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed", "mixed-fine"])
-    ap.add_argument("--method", default="ppc", choices=["ppc", "ppic"],
+    ap.add_argument("--method", default="ppc", choices=["ppc", "ppic", "seq"],
                     help="ppc: PP-PC, eq. (4) with the periodic coarse problem; ppic: PP-IC, "
-                         "eq. (5), U_0^{k+1} = U_N^k with sequential coarse propagation")
+                         "eq. (5), U_0^{k+1} = U_N^k with sequential coarse propagation; seq: "
+                         "classical time stepping from zero, one chain of the fine kernel per "
+                         "period, until two periods' samples agree to --tol")
     ap.add_argument("--n-harm", type=int, default=0,
                     help="harmonics each PP-PC correction solves (0: all N/2+1); the others "
                          "take the jumps' harmonics")
@@ -243,6 +245,65 @@ def bench_batch(a):
     return 0
 
 
+def bench_time_stepping(a):
+    """Classical time stepping on the same GPU: one steady state = periods stepped from zero
+    until two periods' samples agree to --tol; progress (one line per call of a few
+    periods) on stderr."""
+    import numpy as np
+    import torch
+    import paper_1905_13076_amd as P
+    torch.cuda.set_device(0)
+    prob = workload(a.workload)
+    ref = load_reference(a.workload)
+    h = P.Handle(0)
+    pr = P.Problem(h, prob)
+    prec = 0 if a.precision == "fp64" else 1
+    chunk = 4
+    prm = P.problem_params(prob, tol_ppc=a.tol, precision=prec, max_iters=chunk,
+                           **({"tol_lin": 1e-4} if prec == 1 else {}))
+    walls, periods_all, fine_ms = [], [], 0.0
+    for step in range(a.warmup + a.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        total, u0, Up, newton, steps = 0, None, None, 0, 0
+        while True:
+            U, per, st, rc = pr.time_stepping(prm, u_start=u0, U_prev=Up)
+            total += per
+            newton += st["newton_total"]
+            steps += st["steps_total"]
+            if step >= a.warmup:
+                fine_ms += st["fine_ms"]
+            print(f"[seq] step {step} periods {total} change {st['eps']:.3e}", file=sys.stderr, flush=True)
+            if rc == 0 or total >= 2000:
+                break
+            Up, u0 = U, U[0].contiguous()
+        torch.cuda.synchronize()
+        if step >= a.warmup:
+            walls.append(time.perf_counter() - t0)
+            periods_all.append(total)
+    if rc != 0:
+        print(json.dumps({"error": f"time stepping did not reach a periodic state in {total} periods"}))
+        return 1
+    err = None
+    if ref is not None:
+        Ug = U.cpu().numpy()[:, ref["free"]]
+        err = float(np.linalg.norm(Ug - ref["U"]) / np.linalg.norm(ref["U"]))
+    wall = sum(walls)
+    print(json.dumps({
+        "metric": "periodic steady states/s at 1e-6 rel. err vs FP64 oracle; achieved HBM GB/s",
+        "value": a.steps / wall, "unit": "steady states/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": 1e3 * wall / a.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64" if prec == 0 else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"{prob.name}: nr={prob.meta['nr']} x ntheta={prob.meta['ntheta']}, "
+                               f"T = {prob.T}, {prob.N * prob.m} steps per period",
+                   "method": "classical time stepping (one chain per period)", "precision": a.precision,
+                   "tol": a.tol, "periods": periods_all[-1], "err_vs_oracle": err,
+                   "newton_per_step": newton / max(1, steps), "fine_ms_per_state": fine_ms / a.steps},
+        "roofline": None, "cpu_baseline": None}), flush=True)
+    return 0
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -251,6 +312,8 @@ def main():
         return 2
     if a.workload == "c4reg":
         return bench_batch(a)
+    if a.method == "seq":
+        return bench_time_stepping(a)
     prob = workload(a.workload)
     ref = load_reference(a.workload)
     if a.probe == "fine":

@@ -255,6 +255,26 @@ int ppc_solve_device(ppc_handle* h, ppc_problem* pr, const ppc_params* p,
                      const double* U_init_dev, double* U_out_dev, double* resid_out,
                      int32_t* iters_out, ppc_stats* stats, void* stream);
 
+/* Classical time stepping, the sequential method that parallel-in-time iterations are
+ * measured against (Section 1): the implicit-Euler fine propagator of eqs. (2)-(3) run as
+ * one chain over whole periods (N m steps of dt = T/(N m) each, one launch per period, one
+ * workgroup), from u(0) = u_start, until the samples u(T_n) of two consecutive periods
+ * agree: max_n ||U_n^(p) - U_n^(p-1)|| <= tol_ppc max_n ||U_n^(p)||.  At most max_iters
+ * periods.  The problem's workspace is resized for one chain (a later PP-PC solve resizes
+ * it back).
+ *   u_start_dev  DEVICE [n_nodes] or null (zero)
+ *   U_prev_dev   DEVICE [N * n_nodes] or null: the samples of the period that ended at
+ *                u_start, so that a long run can be split into calls without losing a
+ *                comparison (null: the first period is only a reference)
+ *   U_out_dev    DEVICE [N * n_nodes]: the last period's samples, row n = u(T_n) with row 0
+ *                the period's end u(T) (the layout of ppc_solve)
+ *   periods_out  host or null: periods stepped in this call
+ *   stats        host or null: fine counters; eps = the last relative sample change
+ * Returns PPC_OK when periodic, PPC_NOT_CONVERGED after max_iters periods. */
+int ppc_time_stepping_device(ppc_handle* h, ppc_problem* pr, const ppc_params* p, const double* u_start_dev,
+                             const double* U_prev_dev, double* U_out_dev, int32_t* periods_out, ppc_stats* stats,
+                             void* stream);
+
 /* Autotuner of the fine sweep's register-row workgroup size (256, 512 or 1024 threads; a
  * smaller workgroup takes more rows per thread).  For each size whose rows fit the mesh it
  * times one fine sweep from U = 0 in the problem's workspace (overwriting the workspace

@@ -93,6 +93,8 @@ SIGNATURES = {
                                       c_void_p]),
     "ppc_fine_counts": (c_int, [c_void_p, c_int32, PI]),
     "ppc_autotune": (c_int, [c_void_p, c_void_p, c_void_p, PI, PD]),
+    "ppc_time_stepping_device": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, PI,
+                                         c_void_p, c_void_p]),
     "ppc_coarse_correction_device": (c_int, [c_void_p, c_void_p, POINTER(Params), c_void_p, c_void_p,
                                              c_void_p, PI, c_void_p]),
 }

@@ -627,6 +627,92 @@ int solve_batch_device(ppc_handle* h, ppc_problem* bp, const ppc_params* p, cons
 // ---------------------------------------------------------------------------------------
 // adjoint of the periodic steady state
 // ---------------------------------------------------------------------------------------
+// Classical time stepping on the device: one chain of the fine kernel per period (N m
+// steps from u_start), the period's N samples gathered from its trajectory and compared
+// with the previous period's.
+int time_stepping_device(ppc_handle* h, ppc_problem* pr, const ppc_params* p, const double* u_start_dev,
+                         const double* U_prev_dev, double* U_out_dev, int32_t* periods_out, ppc_stats* st,
+                         hipStream_t s) {
+    PPC_HIP(hipSetDevice(h->device));
+    const DeviceMesh& d = pr->mesh;
+    const int N = p->N, n = d.n_free;
+    ppc_params q = *p;        // one chain over the whole period, same step size
+    q.N = 1;
+    q.m = p->N * p->m;
+    ensure_workspace(pr, &q);
+    Workspace& w = pr->ws;
+    ppc_stats S{};
+    S.n_free = d.n_free;
+    S.nnz = d.nnz;
+    S.n_tri = d.n_tri;
+    DevBuf traj, cur, prev, nrm;
+    PPC_HIP(hipMalloc(&traj.p, sizeof(double) * ((size_t)q.m + 1) * n));
+    PPC_HIP(hipMalloc(&cur.p, sizeof(double) * (size_t)N * n));
+    PPC_HIP(hipMalloc(&prev.p, sizeof(double) * (size_t)N * n));
+    PPC_HIP(hipMalloc(&nrm.p, sizeof(double) * 2 * (size_t)N));
+    double* Tr = static_cast<double*>(traj.p);
+    double* C = static_cast<double*>(cur.p);
+    double* P = static_cast<double*>(prev.p);
+    hipEvent_t* ev = h->ev;
+    PPC_HIP(hipEventRecord(ev[4], s));
+    if (u_start_dev) launch_to_free(pr, 1, u_start_dev, w.U, s);
+    else fill(w.U, n, 0.0, s);
+    bool have_prev = false;
+    if (U_prev_dev) {
+        launch_to_free(pr, N, U_prev_dev, P, s);
+        have_prev = true;
+    }
+    std::vector<double> hn(2 * (size_t)N);
+    int status = PPC_NOT_CONVERGED, period = 0;
+    for (period = 1; period <= p->max_iters; ++period) {
+        PPC_HIP(hipEventRecord(ev[0], s));
+        launch_fine_sweep_traj(pr, &q, w.U, w.F, Tr, s);
+        PPC_HIP(hipEventRecord(ev[1], s));
+        const SweepCounts c = read_chain_counts(pr, 1, s, nullptr, nullptr);   // synchronises
+        S.fine_launches++;
+        S.fine_ms += elapsed(ev[0], ev[1]);
+        S.newton_total += c.newton;
+        S.lin_total += c.lin;
+        S.newton_max = std::max(S.newton_max, c.newton_max);
+        S.lin_max = std::max(S.lin_max, c.lin_max);
+        S.lin_capped += c.capped;
+        S.resid_total += c.resid;
+        S.steps_total += q.m;
+        check_sweep(c);
+        launch_gather_samples(n, N, p->m, Tr, C, s);
+        PPC_HIP(hipMemcpyAsync(w.U, w.F, sizeof(double) * n, hipMemcpyDeviceToDevice, s));   // next start
+        bool done = false;
+        if (have_prev) {
+            launch_sample_change(n, N, C, P, static_cast<double*>(nrm.p), s);
+            PPC_HIP(hipMemcpyAsync(hn.data(), nrm.p, sizeof(double) * hn.size(), hipMemcpyDeviceToHost, s));
+            PPC_HIP(hipStreamSynchronize(s));
+            double change = 0.0, size = 0.0;
+            for (int k = 0; k < N; ++k) {
+                change = std::max(change, std::sqrt(hn[2 * k]));
+                size = std::max(size, std::sqrt(hn[2 * k + 1]));
+            }
+            if (!std::isfinite(change)) fail(PPC_ERR_NONFINITE, "non-finite state in time stepping");
+            S.eps = size > 0.0 ? change / size : (change == 0.0 ? 0.0 : INFINITY);
+            done = change <= p->tol_ppc * size;
+        }
+        std::swap(C, P);          // P: this period's samples
+        have_prev = true;
+        if (done) {
+            status = PPC_OK;
+            break;
+        }
+    }
+    S.iterations = std::min(period, p->max_iters);
+    if (U_out_dev) launch_to_nodal(pr, N, P, U_out_dev, s);
+    PPC_HIP(hipEventRecord(ev[5], s));
+    PPC_HIP(hipStreamSynchronize(s));
+    S.total_ms = elapsed(ev[4], ev[5]);
+    S.status = status;
+    if (periods_out) *periods_out = S.iterations;
+    if (st) *st = S;
+    return status;
+}
+
 int adjoint_device(ppc_handle* h, ppc_problem* pr, const ppc_params* p, const double* U_host, double* loss,
                    double* dsigma, double* dbrauer, int32_t* iters_out, ppc_stats* st, hipStream_t s) {
     PPC_HIP(hipSetDevice(h->device));
@@ -1030,6 +1116,20 @@ int ppc_fine_sweep_device(ppc_handle* h, ppc_problem* pr, const ppc_params* p, c
         launch_to_nodal(pr, p->N, pr->ws.F, F_out_dev, s);
         PPC_HIP(hipStreamSynchronize(s));
         return PPC_OK;
+    });
+}
+
+int ppc_time_stepping_device(ppc_handle* h, ppc_problem* pr, const ppc_params* p, const double* u_start_dev,
+                             const double* U_prev_dev, double* U_out_dev, int32_t* periods_out, ppc_stats* stats,
+                             void* stream) {
+    return guarded(h, [&]() -> int {
+        check_handle_problem(h, pr);
+        check_params(p);
+        if (!U_out_dev) fail(PPC_ERR_ARG, "null U_out");
+        if (pr->batch) fail(PPC_ERR_ARG, "single-design entry point called with a batch problem");
+        if ((long)p->N * p->m > 1000000) fail(PPC_ERR_ARG, "N m above 1e6 steps per period");
+        return time_stepping_device(h, pr, p, u_start_dev, U_prev_dev, U_out_dev, periods_out, stats,
+                                    pick_stream(h, stream));
     });
 }
 

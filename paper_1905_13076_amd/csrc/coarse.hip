@@ -172,6 +172,54 @@ __global__ void k_coarse_rhs(int n, int N, const int* __restrict__ rowptr, const
     R[(long)s * n + i] = acc;
 }
 
+// Time stepping: samples U[j mod N] = traj[j m] (the state at T_j), j = 1..N, of one
+// chain's trajectory over a whole period ([N m + 1][n], row 0 the start).
+__global__ void k_gather_samples(int n, int N, int m, const double* __restrict__ traj, double* __restrict__ U) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y + 1;
+    if (i >= n) return;
+    U[(long)(j % N) * n + i] = traj[(long)j * m * n + i];
+}
+
+// Per sample s (one workgroup each): out[2s] = ||A_s - B_s||^2, out[2s+1] = ||A_s||^2.
+__global__ void k_sample_change(int n, const double* __restrict__ A, const double* __restrict__ B,
+                                double* __restrict__ out) {
+    __shared__ double red[2][256];
+    const int s = blockIdx.x;
+    const double* a = A + (long)s * n;
+    const double* b = B + (long)s * n;
+    double dd = 0.0, aa = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const double d = a[i] - b[i];
+        dd += d * d;
+        aa += a[i] * a[i];
+    }
+    red[0][threadIdx.x] = dd;
+    red[1][threadIdx.x] = aa;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + w];
+            red[1][threadIdx.x] += red[1][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[2 * s] = red[0][0];
+        out[2 * s + 1] = red[1][0];
+    }
+}
+
+void launch_gather_samples(int n, int N, int m, const double* traj, double* U, hipStream_t s) {
+    hipLaunchKernelGGL(k_gather_samples, dim3((n + 255) / 256, N), dim3(256), 0, s, n, N, m, traj, U);
+    PPC_HIP(hipGetLastError());
+}
+
+void launch_sample_change(int n, int N, const double* A, const double* B, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_sample_change, dim3(N), dim3(256), 0, s, n, A, B, out);
+    PPC_HIP(hipGetLastError());
+}
+
 // PP-IC start of a propagation (eq. (5)): e = U_N - U^k_0, then U_0 = U_N; thread 0 also
 // sets the single shift 1/dT of the propagation's solves.
 __global__ void k_ic_start(int n, double inv_dT, const double* __restrict__ un, double* __restrict__ u0,

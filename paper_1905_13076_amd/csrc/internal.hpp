@@ -361,6 +361,10 @@ void launch_cocg_batch(const std::vector<ppc_problem*>& parts, const std::vector
 // U^{k+1}_n = F_n + Q^{-1} C (U^{k+1}_{n-1} - U^k_{n-1}), Q = C + Kbar, C = M/dT; the value
 // at n = N is kept for the next iteration's U_0.  Counters of step n in ccount row n-1.
 void launch_ic_propagation(ppc_problem* pr, const ppc_params* p, hipStream_t s);
+// time stepping: the N samples of one chain's period trajectory, and per-sample squared
+// norms of A - B and of A (out [N][2])
+void launch_gather_samples(int n, int N, int m, const double* traj, double* U, hipStream_t s);
+void launch_sample_change(int n, int N, const double* A, const double* B, double* out, hipStream_t s);
 void launch_coarse_post(ppc_problem* pr, const ppc_params* p, double* dU, bool accumulate,
                         hipStream_t s);
 void launch_to_nodal(const ppc_problem* pr, int N, const double* Ufree, double* Unodal,

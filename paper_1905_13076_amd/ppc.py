@@ -236,6 +236,24 @@ class Problem:
             raise PPCError(rc, "ppc_fine_counts: no sweep with this N on this problem")
         return out
 
+    def time_stepping(self, prm, u_start=None, U_prev=None):
+        """ppc_time_stepping_device: classical time stepping period after period until two
+        consecutive periods' samples agree to prm.tol_ppc (at most prm.max_iters periods).
+        u_start CUDA [n_nodes] or None, U_prev CUDA [N, n_nodes] or None.  Returns (U CUDA
+        [N, n_nodes] of the last period, periods stepped, stats dict, status)."""
+        import torch
+        shape = (prm.N, self.n_nodes)
+        out = torch.empty(shape, dtype=torch.float64, device=f"cuda:{self.handle.device}")
+        us = _dev_ptr(u_start, (self.n_nodes,)) if u_start is not None else None
+        up = _dev_ptr(U_prev, shape) if U_prev is not None else None
+        per = np.zeros(1, dtype=np.int32)
+        st = nat.Stats()
+        rc = lib().ppc_time_stepping_device(self.handle.h, self.p, byref(prm), us, up, _dev_ptr(out, shape),
+                                            _pi(per), byref(st), _stream())
+        if rc < 0:
+            raise _err(self.handle.h, rc)
+        return out, int(per[0]), st.as_dict(), rc
+
     def autotune(self, prm):
         """ppc_autotune: returns (chosen register-row workgroup size or 0, sweep ms at 256,
         512, 1024 threads, NaN where the rows do not fit)."""

@@ -9,7 +9,8 @@ Each output ``<name>_oracle.npz`` holds the fixed point U (rows n = 0..N-1, colu
 free nodes in ascending node order), the eps history, the iteration count and the
 generator arguments that define the workload.  Cases ending in ``_ppic`` run PP-IC
 (eq. (5)) instead of PP-PC (c5small from the fine sweep from rest); ``_h3`` runs PP-PC
-solving only the harmonics p = 0, 1, 2 of each correction.
+solving only the harmonics p = 0, 1, 2 of each correction; ``_routes`` steps period after
+period from zero (route S), its iteration count being the periods stepped.
 """
 from __future__ import annotations
 
@@ -36,6 +37,7 @@ CASES = {
     "c5small_h3": (coax.c5_small, {}, 1e-12),
     "c2lin_small": (coax.c2lin, dict(nr=20, ntheta=40, N=10, m=20), 1e-12),
     "c2lin_small_ppic": (coax.c2lin, dict(nr=20, ntheta=40, N=10, m=20), 1e-12),
+    "c2lin_small_routes": (coax.c2lin, dict(nr=20, ntheta=40, N=10, m=20), 1e-10),
 }
 
 
@@ -52,7 +54,10 @@ def make(name, procs):
         print(f"  [{name}] k={k} eps={eps:.3e} t={time.time() - t:.1f}s", flush=True)
 
     try:
-        if name == "c5small_ppic":     # from rest: a coarse start from zero overshoots
+        if name.endswith("_routes"):    # sequential periods from zero (classical time stepping)
+            U, k = periodic.route_s(fe, tol=tol)
+            hist = np.zeros(0)
+        elif name == "c5small_ppic":     # from rest: a coarse start from zero overshoots
             U0 = periodic.initial_iterate(fe, mode="fine", pool=pool)
             U, hist, k = periodic.ppic(fe, tol=tol, U_init=U0, pool=pool, callback=cb)
         elif name.endswith("_ppic"):
@@ -68,7 +73,8 @@ def make(name, procs):
     out = os.path.join(HERE, f"{name}_oracle.npz")
     np.savez_compressed(out, U=U, hist=hist, iterations=k, tol=tol,
                         free=fe.free.astype(np.int32), generator=name)
-    print(f"wrote {out}: iterations={k} eps={hist[-1]:.3e} in {time.time() - t:.1f}s")
+    last = f"{hist[-1]:.3e}" if len(hist) else "-"
+    print(f"wrote {out}: iterations={k} eps={last} in {time.time() - t:.1f}s")
 
 
 def main():

@@ -157,6 +157,7 @@ def test_null_safety_and_no_device_error():
     assert lib.ppc_problem_info(None, None, None, None, None) == -1
     assert lib.ppc_fine_counts(None, 4, None) == -1
     assert lib.ppc_autotune(None, None, None, None, None) == -1
+    assert lib.ppc_time_stepping_device(None, None, None, None, None, None, None, None, None) == -1
     assert lib.ppc_last_error(None) is not None
     h = ctypes.c_void_p()
     assert lib.ppc_create(-1, ctypes.byref(h)) == -1
