@@ -23,7 +23,6 @@ from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -36,9 +35,9 @@ COUNTERS = os.path.join(ROOT, "profiles", "fine_sweep_c2_fp64_counters.md")
 FINE_SRC = os.path.join(ROOT, "paper_1905_13076_amd", "csrc", "fine_chain.hpp")
 
 
-def measured_traffic():
+def measured_traffic(tol_newton):
     """HBM bytes per fine-sweep launch from the committed counter summary, if it was
-    taken on the current fine-sweep source (else None)."""
+    taken on the current fine-sweep source at this Newton tolerance (else None)."""
     import hashlib
     import re
     if not os.path.exists(COUNTERS):
@@ -50,6 +49,9 @@ def measured_traffic():
     if not (m and t and g):
         return None
     if hashlib.sha1(open(FINE_SRC, "rb").read()).hexdigest() != m.group(1):
+        return None
+    tn = re.search(r"tol_newton: ([0-9.eE+-]+)", text)
+    if not tn or float(tn.group(1)) != tol_newton:
         return None
     return {"bytes": int(t.group(1)), "algorithmic_bytes_same_launch": int(g.group(1))}
 
@@ -75,7 +77,13 @@ def parse():
     ap.add_argument("--init", default="auto", choices=["auto", "rest"],
                     help="U^0: auto (zero for nonlinear, coarse periodic for linear) or rest "
                          "(one fine sweep from zero, U^0_n = F_n(0))")
-    ap.add_argument("--tol", type=float, default=1e-8, help="PP-PC stopping tolerance on eps")
+    ap.add_argument("--tol", type=float, default=1e-7,
+                    help="PP-PC stopping tolerance on eps (the metric asks for 1e-6 relative error "
+                         "against the FP64 oracle; 1e-7 reaches 6.8e-8 on C2)")
+    ap.add_argument("--tol-newton", type=float, default=1e-10,
+                    help="Newton stopping tolerance of the fine steps, relative to ||f(t)|| + "
+                         "||M u_prev||/dt (the oracle uses 1e-13; on C2 the PP-PC error against it "
+                         "does not change between 1e-13 and 1e-9)")
     ap.add_argument("--tol-cocg", type=float, default=1e-6,
                     help="relative tolerance of the harmonic solves (a correction only needs to be "
                          "accurate relative to the current jumps)")
@@ -102,50 +110,54 @@ def load_reference(name):
     if not os.path.exists(path):
         return None
     with np.load(path, allow_pickle=False) as z:
-        return {"U": z["U"], "iterations": int(z["iterations"]), "free": z["free"]}
+        return {"U": z["U"], "iterations": int(z["iterations"]), "free": z["free"], "hist": z["hist"]}
 
 
-def cpu_baseline(prob, ref, procs):
-    """The oracle (scipy direct solves, FP64) on the host cores, on a bounded sample:
-    one round of `cores` fine chains run in parallel (one per worker process, started
-    from the oracle fixed point) and one coarse correction; extrapolated to the
-    oracle's own count of sweeps and corrections for one steady state."""
+def cpu_baseline(prob, ref, procs, tol):
+    """The oracle as it stands (scipy direct solves, FP64, Newton to 1e-13) on the host
+    cores, on a bounded sample: two fine sweeps of all N chains from the oracle fixed point
+    (one chain per worker process) and two coarse corrections, ~15 s of work at C2;
+    extrapolated to the sweeps and corrections the oracle's own PP-PC takes to reach eps <=
+    tol (its stored eps history), for one steady state."""
     import numpy as np
     from oracle import periodic
     from oracle.fe import FE
     os.environ.setdefault("OMP_NUM_THREADS", "1")
     cores = max(1, min(procs, len(os.sched_getaffinity(0)), prob.N))
     fe = FE(prob)
-    U = ref["U"] if ref is not None else np.zeros((prob.N, fe.n))
-    iters = ref["iterations"] if ref is not None else None
+    U = ref["U"]
+    hist = ref["hist"]
+    iters = next(k for k in range(len(hist)) if hist[k] <= tol) if np.any(hist <= tol) else int(ref["iterations"])
     dt = periodic.fine_dt(prob)
-    args = [((n - 1) * (prob.T / prob.N), U[n - 1], prob.m, dt, 1e-13) for n in range(1, cores + 1)]
+    args = [((n - 1) * (prob.T / prob.N), U[n - 1], prob.m, dt, 1e-13) for n in range(1, prob.N + 1)]
     pool = periodic.make_pool(prob, cores)
+    reps = 2
     try:
-        pool.starmap(periodic._chain_worker, args[:1])          # warm the workers' imports
+        pool.starmap(periodic._chain_worker, args[:cores])      # warm the workers' imports
         t0 = time.perf_counter()
-        outs = pool.starmap(periodic._chain_worker, args)
-        t_round = time.perf_counter() - t0
+        for _ in range(reps):
+            outs = pool.starmap(periodic._chain_worker, args)
+        t_sweep = (time.perf_counter() - t0) / reps
     finally:
         pool.close()
         pool.join()
     J = np.zeros_like(U)
-    for n in range(1, cores + 1):
+    for n in range(1, prob.N + 1):
         J[n % prob.N] = outs[n - 1] - U[n % prob.N]
     t0 = time.perf_counter()
-    periodic.coarse_correction(fe, U, J)
-    t_coarse = time.perf_counter() - t0
-    rounds = math.ceil(prob.N / cores)
-    sweeps = (iters + 1) if iters is not None else None
-    t_state = sweeps * rounds * t_round + iters * t_coarse if iters is not None else None
+    for _ in range(reps):
+        periodic.coarse_correction(fe, U, J)
+    t_coarse = (time.perf_counter() - t0) / reps
+    t_state = (iters + 1) * t_sweep + iters * t_coarse
     return {
-        "value": (1.0 / t_state) if t_state else None,
+        "value": 1.0 / t_state,
         "unit": "steady states/s",
         "cores": cores,
         "kind": "oracle",
-        "sample": (f"{cores} of {prob.N} fine chains ({prob.m} steps each, one per process) "
-                   f"in {t_round:.2f} s + 1 coarse correction in {t_coarse:.2f} s; extrapolated to "
-                   f"{sweeps} sweeps x {rounds} rounds + {iters} corrections = {t_state:.1f} s per steady state"),
+        "sample": (f"{reps} fine sweeps of all {prob.N} chains ({prob.m} steps each, {cores} processes) at "
+                   f"{t_sweep:.2f} s each + {reps} coarse corrections at {t_coarse:.2f} s each; extrapolated "
+                   f"to the oracle's {iters + 1} sweeps + {iters} corrections to eps <= {tol:g} = "
+                   f"{t_state:.1f} s per steady state"),
     }
 
 
@@ -164,7 +176,8 @@ def probe_fine(a, prob, ref):
     h = P.Handle(0)
     pr = P.Problem(h, prob)
     prec = 0 if a.precision == "fp64" else 1
-    prm = P.problem_params(prob, precision=prec, **({"tol_lin": 1e-4} if prec == 1 else {}))
+    prm = P.problem_params(prob, precision=prec, tol_newton=a.tol_newton,
+                           **({"tol_lin": 1e-4} if prec == 1 else {}))
     U = np.zeros((prob.N, pr.n_nodes))
     U[:, ref["free"]] = ref["U"]
     Ud = torch.tensor(U, device="cuda")
@@ -178,7 +191,8 @@ def probe_fine(a, prob, ref):
     tot = {"lin_total": int(cnt[:, 2].sum()), "newton_total": int(cnt[:, 1].sum()),
            "resid_total": int(cnt[:, 7].sum()), "steps_total": prob.N * prob.m, "fine_launches": 1,
            "n_free": pr.n_free, "nnz": pr.nnz, "n_tri": pr.n_tri}
-    print(json.dumps({"probe": "fine", "copy_bytes_each_way": src.numel() * 8, "sweep_ms": dt * 1e3,
+    print(json.dumps({"probe": "fine", "tol_newton": a.tol_newton, "copy_bytes_each_way": src.numel() * 8,
+                      "sweep_ms": dt * 1e3,
                       "newton_total": tot["newton_total"], "lin_total": tot["lin_total"],
                       "resid_total": tot["resid_total"],
                       "algorithmic_bytes": fine_sweep_bytes(tot, prob.N, prec)}), flush=True)
@@ -206,6 +220,7 @@ def bench_batch(a):
     if a.precision == "mixed-fine":
         extra["coarse_precision"] = 0
     prm = P.problem_params(designs[0], tol_ppc=a.tol, precision=prec, tol_cocg=a.tol_cocg, max_newton=200,
+                           tol_newton=a.tol_newton,
                            init_mode=3, b_cap=3.0, **extra)
     tuned = None
     if a.autotune:
@@ -237,6 +252,7 @@ def bench_batch(a):
         "config": {"workload": f"batched designs: {len(designs)} designs, nr {min(nrs)}-{max(nrs)} "
                                f"(ntheta = 2 nr), N=40 x m=50, 21 harmonics each; from rest, b_cap 3 T",
                    "precision": a.precision, "tol_ppc": a.tol, "tol_cocg": a.tol_cocg,
+                   "tol_newton": a.tol_newton,
                    "iterations_max": int(max(iters)), "damped_corrections": st["damped"],
                    "fine_ms_per_step": st["fine_ms"], "coarse_ms_per_step": st["coarse_ms"],
                    "newton_per_step": st["newton_total"] / max(1, st["steps_total"]),
@@ -259,7 +275,7 @@ def bench_time_stepping(a):
     pr = P.Problem(h, prob)
     prec = 0 if a.precision == "fp64" else 1
     chunk = 4
-    prm = P.problem_params(prob, tol_ppc=a.tol, precision=prec, max_iters=chunk,
+    prm = P.problem_params(prob, tol_ppc=a.tol, precision=prec, max_iters=chunk, tol_newton=a.tol_newton,
                            **({"tol_lin": 1e-4} if prec == 1 else {}))
     walls, periods_all, fine_ms = [], [], 0.0
     for step in range(a.warmup + a.steps):
@@ -321,7 +337,7 @@ def main():
     cpu = None
     if a.cpu and ref is not None and a.method == "ppc" and a.init == "auto" and a.n_harm == 0:
         # before any GPU initialisation: the oracle's worker pool forks this process
-        cpu = cpu_baseline(prob, ref, a.cpu_procs)
+        cpu = cpu_baseline(prob, ref, a.cpu_procs, a.tol)
     import numpy as np
     import torch
     import paper_1905_13076_amd as P
@@ -343,7 +359,8 @@ def main():
         extra["max_iters"] = 300
     if a.method == "ppic":
         extra["max_iters"] = 300
-    prm = P.problem_params(prob, tol_ppc=a.tol, precision=prec, tol_cocg=a.tol_cocg, **extra)
+    prm = P.problem_params(prob, tol_ppc=a.tol, precision=prec, tol_cocg=a.tol_cocg, tol_newton=a.tol_newton,
+                           **extra)
     tuned = None
     if a.autotune:
         t0 = time.perf_counter()
@@ -378,7 +395,7 @@ def main():
     launch_s = fine_ms / launches / 1e3
     achieved = bytes_launch / launch_s / 1e9
     value = a.steps / wall
-    traffic = measured_traffic() if prec == 0 else None
+    traffic = measured_traffic(a.tol_newton) if prec == 0 else None
     line = {
         "metric": "periodic steady states/s at 1e-6 rel. err vs FP64 oracle; achieved HBM GB/s",
         "value": value,
@@ -402,6 +419,7 @@ def main():
             "init": a.init,
             "tol_ppc": a.tol,
             "tol_cocg": a.tol_cocg,
+            "tol_newton": a.tol_newton,
             "iterations": k,
             "err_vs_oracle": err,
             "max_b_steel_T": st["max_b_steel"],
