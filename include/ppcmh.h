@@ -117,8 +117,9 @@ typedef struct {
                                meshes, else LDS-resident p / diagonal); 1024 = force the
                                workgroup-memory PCG path */
     int32_t no_predictor;   /* 1: start every Newton solve from u_{j-1}; 0: also try the
-                               extrapolation of the previous steps (quadratic from the third
-                               step, linear at the second) and keep the smaller residual */
+                               extrapolation of the previous steps (cubic from the fourth
+                               step, quadratic at the third, linear at the second) and keep
+                               the smaller residual */
     int32_t lin_point;      /* samples the coarse stiffness is linearised at: 0 = the current
                                iterate U^k, 1 = the fine results F^k of the same sweep (equal
                                at the fixed point) */

@@ -60,7 +60,7 @@ enum { E_F0 = 0, E_W0 = 3, E_NU = 6, E_SF = 7 };
 // Newton accepts a residual that stops halving (or a stalled line search) once it is
 // below kFloorCap * scale: it then sits at the rounding floor of its evaluation.
 constexpr double kFloorCap = 1e-9;
-enum { V_U = 0, V_UP = 1, V_R = 2, V_RT = 3, V_UPP = 4, V_UT = 5, V_CP = 6, V_UP3 = 7 };
+enum { V_U = 0, V_UP = 1, V_R = 2, V_RT = 3, V_UPP = 4, V_UT = 5, V_CP = 6, V_UP3 = 7, V_UP4 = 8 };
 enum { P_R = 0, P_P = 1, P_Q = 2, P_X = 3, P_D = 4 };
 enum { C_STATUS = 0, C_NEWTON = 1, C_LIN = 2, C_NEWTON_MAX = 3, C_LIN_MAX = 4, C_CAPPED = 5,
        C_FAILSTEP = 6, C_RESID = 7 };
@@ -507,6 +507,7 @@ __device__ __forceinline__ void fine_chain(const FineArgs& a, const int c, unsig
     double* Rt = vec + V_RT * NP;
     double* upp = vec + V_UPP * NP;
     double* up3 = vec + V_UP3 * NP;           // u_{j-3}
+    double* up4 = vec + V_UP4 * NP;           // u_{j-4}
     double* ut = vec + V_UT * NP;             // trial state of the line search
     double* cp = vec + V_CP * NP;             // M u_prev / dt
     S* pv = reinterpret_cast<S*>(a.pcg) + (long)c * kPcgVec * NP;
@@ -536,8 +537,9 @@ __device__ __forceinline__ void fine_chain(const FineArgs& a, const int c, unsig
 
     for (int j = 1; j <= a.m && status == 0; ++j) {
         const double t = t0 + j * a.dt;
-        // u_{j-1} -> u_prev (u_{j-2}, u_{j-3} kept for the predictor)
+        // u_{j-1} -> u_prev (u_{j-2}, u_{j-3}, u_{j-4} kept for the predictor)
         for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            up4[i] = up3[i];
             up3[i] = upp[i];
             upp[i] = up[i];
             up[i] = u[i];
@@ -556,12 +558,16 @@ __device__ __forceinline__ void fine_chain(const FineArgs& a, const int c, unsig
         block_sum<double, 1>(v2, lds_d, ph_d);
         double rn = sqrt(v2[0]);
         if (!isfinite(rn)) { status = PPC_ERR_NONFINITE; fail_step = j; break; }
-        // Newton starts from the extrapolation of the previous steps (quadratic
-        // 3 u_{j-1} - 3 u_{j-2} + u_{j-3} from the third step on, linear 2 u_{j-1} - u_{j-2}
-        // at the second) when that has the smaller residual; it changes only the iteration
-        // count, not the step's solution
+        // Newton starts from the extrapolation of the previous steps (cubic
+        // 4 u_{j-1} - 6 u_{j-2} + 4 u_{j-3} - u_{j-4} from the fourth step on, quadratic
+        // 3 u_{j-1} - 3 u_{j-2} + u_{j-3} at the third, linear 2 u_{j-1} - u_{j-2} at the
+        // second) when that has the smaller residual; it changes only the iteration count,
+        // not the step's solution
         if (j >= 2 && a.predictor && rn > target) {
-            if (j >= 3)
+            if (j >= 4)
+                for (int i = threadIdx.x; i < n; i += blockDim.x)
+                    ut[i] = 4.0 * (up[i] + up3[i]) - 6.0 * upp[i] - up4[i];
+            else if (j >= 3)
                 for (int i = threadIdx.x; i < n; i += blockDim.x) ut[i] = 3.0 * (up[i] - upp[i]) + up3[i];
             else
                 for (int i = threadIdx.x; i < n; i += blockDim.x) ut[i] = 2.0 * up[i] - upp[i];

@@ -292,7 +292,7 @@ struct CocgArgs {
     const int* tail_col;
 };
 
-constexpr int kFineVec = 8;   // u, u_prev, R, R_trial, u_{j-2}, trial state, M u_prev / dt, u_{j-3}
+constexpr int kFineVec = 9;   // u, u_prev, R, R_trial, u_{j-2}, trial state, M u_prev / dt, u_{j-3}, u_{j-4}
 constexpr int kPcgVec = 5;    // r, p, q, x, dinv
 
 // set-up (setup.hip)
