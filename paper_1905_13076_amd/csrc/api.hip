@@ -438,6 +438,20 @@ struct DevBuf {
     ~DevBuf() { if (p) (void)hipFree(p); }
 };
 
+// Pinned host array: the target of device-to-host copies that a captured graph replays.
+template <typename T>
+struct PinnedBuf {
+    T* p = nullptr;
+    explicit PinnedBuf(size_t n) {
+        void* q = nullptr;
+        PPC_HIP(hipHostMalloc(&q, std::max<size_t>(n, 1) * sizeof(T), hipHostMallocDefault));
+        p = static_cast<T*>(q);
+    }
+    ~PinnedBuf() { if (p) (void)hipHostFree(p); }
+    PinnedBuf(const PinnedBuf&) = delete;
+    PinnedBuf& operator=(const PinnedBuf&) = delete;
+};
+
 int solve_batch_device(ppc_handle* h, ppc_problem* bp, const ppc_params* p, const double* U_init_dev,
                        double* U_out_dev, double* resid_out, int32_t* iters_out, ppc_stats* st,
                        hipStream_t s) {
@@ -467,7 +481,6 @@ int solve_batch_device(ppc_handle* h, ppc_problem* bp, const ppc_params* p, cons
         PPC_HIP(hipMemcpyAsync(cargs.p, ca.data(), sizeof(CocgArgs) * D, hipMemcpyHostToDevice, s));
         PPC_HIP(hipStreamSynchronize(s));
     }
-    std::vector<double> hs(3 * (size_t)D);
     std::vector<int> counts(8 * (size_t)N);
     std::vector<int> ccount(4 * (size_t)H);
     std::vector<int2> cw;
@@ -513,9 +526,9 @@ int solve_batch_device(ppc_handle* h, ppc_problem* bp, const ppc_params* p, cons
         S.coarse_solves++;
     };
 
-    // chain counters of design d's last sweep into the stats; fails on a chain's status
-    auto take_counts = [&](int d) {
-        PPC_HIP(hipMemcpy(counts.data(), parts[d]->ws.fcount, counts.size() * sizeof(int), hipMemcpyDeviceToHost));
+    // chain counters of design d's last sweep (in counts) into the stats; fails on a
+    // chain's status
+    auto add_counts = [&](int d) {
         for (int c = 0; c < N; ++c) {
             const int* q = counts.data() + 8 * c;
             if (q[0] != 0)
@@ -529,6 +542,10 @@ int solve_batch_device(ppc_handle* h, ppc_problem* bp, const ppc_params* p, cons
             S.resid_total += q[7];
         }
         S.steps_total += (int64_t)N * p->m;
+    };
+    auto take_counts = [&](int d) {
+        PPC_HIP(hipMemcpy(counts.data(), parts[d]->ws.fcount, counts.size() * sizeof(int), hipMemcpyDeviceToHost));
+        add_counts(d);
     };
 
     // initial iterate per design
@@ -567,28 +584,77 @@ int solve_batch_device(ppc_handle* h, ppc_problem* bp, const ppc_params* p, cons
                                    hipMemcpyDeviceToDevice, s));
         }
     }
-    std::vector<char> active(D, 1);
+    // Device work of one iteration, as in the single-design solve: the fine sweep of the
+    // active designs with their jump norms and chain counters copied to pinned memory, then
+    // the corrections of the designs that go on with their counters.  With params->graph
+    // each part is captured for the set of designs it serves (the first time that set
+    // occurs after the first iteration) and replayed while the set is unchanged; the
+    // work lists are uploaded eagerly when the set changes.
+    const bool use_graph = p->graph != 0;
+    const int Hs = solved_harmonics(p, false);
+    PinnedBuf<double> hs_p(3 * (size_t)D), th_p((size_t)D);
+    PinnedBuf<int> cnt_p(8 * (size_t)N * D), cc_p(4 * (size_t)H * D);
+    std::vector<char> active(D, 1), fine_set, coarse_set;
+    std::vector<int> corr;
+    CocgBatchPlan cplan;
+    GraphExec g_fine, g_coarse;
+    auto fine_ops = [&]() {
+        fine_batch_run(fb, s);
+        for (int d = 0; d < D; ++d)
+            if (active[d]) {
+                Workspace& w = parts[d]->ws;
+                launch_jumps(parts[d], N, w.U, w.F, w.J, static_cast<double*>(scal.p) + 3 * d, s);
+                PPC_HIP(hipMemcpyAsync(cnt_p.p + 8 * (size_t)N * d, w.fcount, 8 * (size_t)N * sizeof(int),
+                                       hipMemcpyDeviceToHost, s));
+            }
+        PPC_HIP(hipMemcpyAsync(hs_p.p, scal.p, sizeof(double) * 3 * D, hipMemcpyDeviceToHost, s));
+    };
+    auto coarse_ops = [&]() {
+        for (int d : corr) {
+            Workspace& w = parts[d]->ws;
+            launch_coarse_pre(parts[d], p, p->lin_point == 1 ? w.F : w.U, w.J, false, s);
+        }
+        cocg_batch_run(cplan, static_cast<CocgArgs*>(cargs.p), static_cast<int2*>(cwork.p), s);
+        for (int d : corr) {
+            Workspace& w = parts[d]->ws;
+            if (p->b_cap > 0.0) {
+                launch_coarse_post(parts[d], p, w.R, false, s);
+                launch_safeguarded_update(parts[d], N, p->b_cap, w.R, w.U, w.scal + 8, s);
+                PPC_HIP(hipMemcpyAsync(th_p.p + d, w.scal + 8, sizeof(double), hipMemcpyDeviceToHost, s));
+            } else {
+                launch_coarse_post(parts[d], p, w.U, true, s);
+            }
+            PPC_HIP(hipMemcpyAsync(cc_p.p + 4 * (size_t)H * d, w.ccount, 4 * (size_t)Hs * sizeof(int),
+                                   hipMemcpyDeviceToHost, s));
+        }
+    };
     std::vector<int> iters(D, p->max_iters);
     int status = PPC_OK;
     int k = 0;
     for (k = 0; k <= p->max_iters; ++k) {
         PPC_HIP(hipEventRecord(ev[0], s));
-        fine_batch_launch(fb, active, s);
+        if (active != fine_set) {
+            fine_batch_plan(fb, active, s);
+            if (g_fine.exec) (void)hipGraphExecDestroy(g_fine.exec);
+            g_fine.exec = nullptr;
+            fine_set = active;
+        }
+        if (use_graph && k > 0) {
+            if (!g_fine.exec) capture_graph(g_fine, s, fine_ops);
+            PPC_HIP(hipGraphLaunch(g_fine.exec, s));
+        } else {
+            fine_ops();
+        }
         PPC_HIP(hipEventRecord(ev[1], s));
         S.fine_launches++;
-        for (int d = 0; d < D; ++d)
-            if (active[d]) {
-                Workspace& w = parts[d]->ws;
-                launch_jumps(parts[d], N, w.U, w.F, w.J, static_cast<double*>(scal.p) + 3 * d, s);
-            }
-        PPC_HIP(hipMemcpyAsync(hs.data(), scal.p, sizeof(double) * 3 * D, hipMemcpyDeviceToHost, s));
         PPC_HIP(hipStreamSynchronize(s));
         S.fine_ms += elapsed(ev[0], ev[1]);
-        std::vector<int> corr;
+        std::vector<int> next;
         for (int d = 0; d < D; ++d) {
             if (!active[d]) continue;
-            take_counts(d);
-            const double jj = hs[3 * d], uu = hs[3 * d + 1];
+            std::copy(cnt_p.p + 8 * (size_t)N * d, cnt_p.p + 8 * (size_t)N * (d + 1), counts.begin());
+            add_counts(d);
+            const double jj = hs_p.p[3 * d], uu = hs_p.p[3 * d + 1];
             if (!std::isfinite(jj)) fail(PPC_ERR_NONFINITE, "design " + std::to_string(d) + ": non-finite jump norm");
             const double eps = uu > 0.0 ? std::sqrt(jj) / std::sqrt(uu) : (jj == 0.0 ? 0.0 : INFINITY);
             if (resid_out) resid_out[(size_t)d * R1 + k] = eps;
@@ -597,15 +663,41 @@ int solve_batch_device(ppc_handle* h, ppc_problem* bp, const ppc_params* p, cons
                 active[d] = 0;
                 iters[d] = k;
             } else if (k < p->max_iters) {
-                corr.push_back(d);
+                next.push_back(d);
             }
         }
-        if (corr.empty()) break;
+        if (next.empty()) break;
         PPC_HIP(hipEventRecord(ev[2], s));
-        coarse(corr, false);
+        std::vector<char> cset(D, 0);
+        for (int d : next) cset[d] = 1;
+        if (cset != coarse_set) {
+            corr = next;
+            cocg_batch_plan(parts, corr, p, Hs, static_cast<int2*>(cwork.p), cplan, s);
+            if (g_coarse.exec) (void)hipGraphExecDestroy(g_coarse.exec);
+            g_coarse.exec = nullptr;
+            coarse_set = cset;
+        }
+        if (use_graph && k > 0) {
+            if (!g_coarse.exec) capture_graph(g_coarse, s, coarse_ops);
+            PPC_HIP(hipGraphLaunch(g_coarse.exec, s));
+        } else {
+            coarse_ops();
+        }
         PPC_HIP(hipEventRecord(ev[3], s));
         PPC_HIP(hipStreamSynchronize(s));
         S.coarse_ms += elapsed(ev[2], ev[3]);
+        S.coarse_solves++;
+        for (int d : corr) {
+            const int* c = cc_p.p + 4 * (size_t)H * d;
+            for (int q = 0; q < Hs; ++q) {
+                if (c[4 * q] != 0)
+                    fail(c[4 * q], "design " + std::to_string(d) + ": " +
+                                       (c[4 * q] == PPC_ERR_BREAKDOWN ? "COCG breakdown" : "non-finite COCG residual"));
+                S.cocg_total += c[4 * q + 1];
+                S.cocg_max = std::max(S.cocg_max, c[4 * q + 1]);
+            }
+            if (p->b_cap > 0.0 && th_p.p[d] < 1.0) S.damped++;
+        }
     }
     for (int d = 0; d < D; ++d)
         if (active[d]) status = PPC_NOT_CONVERGED;

@@ -1226,32 +1226,30 @@ void launch_ic_propagation(ppc_problem* pr, const ppc_params* p, hipStream_t s) 
 // Harmonic solves of the designs in list (descriptors d_args, one per design): the
 // (design, harmonic) work items are grouped by the designs' COCG form (as the single-
 // design launch picks it, so a design's arithmetic does not depend on its batch) and
-// each group is one launch.  cw keeps the host work list alive for the copy.
-void launch_cocg_batch(const std::vector<ppc_problem*>& parts, const std::vector<int>& list,
-                       const ppc_params* p, int H, const CocgArgs* d_args, int2* d_work, std::vector<int2>& cw,
-                       hipStream_t s) {
-    struct Span {
-        int R;
-        size_t lds;
-        int begin, count;
-    };
-    std::vector<Span> spans;
-    cw.clear();
+// each group is one launch.  The plan uploads the work list and synchronises.
+void cocg_batch_plan(const std::vector<ppc_problem*>& parts, const std::vector<int>& list, const ppc_params* p,
+                     int H, int2* d_work, CocgBatchPlan& plan, hipStream_t s) {
+    plan.spans.clear();
+    plan.cw.clear();
     for (int R : {0, 1, 2, 4, 8}) {
-        Span sp{R, 0, (int)cw.size(), 0};
+        CocgBatchPlan::Span sp{R, 0, (int)plan.cw.size(), 0};
         for (int d : list) {
             const CocgArgs a = make_cocg_args(parts[d], p);
             size_t lds = 0;
             if (cocg_ell_rows(parts[d], a, lds) != R) continue;
             sp.lds = std::max(sp.lds, lds);
-            for (int q = 0; q < H; ++q) cw.push_back(make_int2(d, q));
+            for (int q = 0; q < H; ++q) plan.cw.push_back(make_int2(d, q));
         }
-        sp.count = (int)cw.size() - sp.begin;
-        if (sp.count > 0) spans.push_back(sp);
+        sp.count = (int)plan.cw.size() - sp.begin;
+        if (sp.count > 0) plan.spans.push_back(sp);
     }
-    if (cw.empty()) return;
-    PPC_HIP(hipMemcpyAsync(d_work, cw.data(), sizeof(int2) * cw.size(), hipMemcpyHostToDevice, s));
-    for (const Span& sp : spans) {
+    if (plan.cw.empty()) return;
+    PPC_HIP(hipMemcpyAsync(d_work, plan.cw.data(), sizeof(int2) * plan.cw.size(), hipMemcpyHostToDevice, s));
+    PPC_HIP(hipStreamSynchronize(s));
+}
+
+void cocg_batch_run(const CocgBatchPlan& plan, const CocgArgs* d_args, const int2* d_work, hipStream_t s) {
+    for (const auto& sp : plan.spans) {
         const int2* w = d_work + sp.begin;
         switch (sp.R) {
             case 1: launch_cocg_ell_batch<1>(d_args, w, sp.count, sp.lds, s); break;
@@ -1262,6 +1260,15 @@ void launch_cocg_batch(const std::vector<ppc_problem*>& parts, const std::vector
         }
     }
     PPC_HIP(hipGetLastError());
+}
+
+void launch_cocg_batch(const std::vector<ppc_problem*>& parts, const std::vector<int>& list,
+                       const ppc_params* p, int H, const CocgArgs* d_args, int2* d_work, std::vector<int2>& cw,
+                       hipStream_t s) {
+    CocgBatchPlan plan;
+    cocg_batch_plan(parts, list, p, H, d_work, plan, s);
+    cocg_batch_run(plan, d_args, d_work, s);
+    cw = plan.cw;
 }
 
 void launch_to_nodal(const ppc_problem* pr, int N, const double* Ufree, double* Unodal,

@@ -285,8 +285,9 @@ void fine_batch_prepare(FineBatch& b, const std::vector<ppc_problem*>& parts, co
     b.precision = p->precision;
 }
 
-// One launch per kernel shape over the chains of the active designs, longest chains first.
-void fine_batch_launch(FineBatch& b, const std::vector<char>& active, hipStream_t s) {
+// Work list of the active designs' chains, longest designs first, grouped by kernel shape,
+// uploaded to d_work; synchronises so that the host list may change afterwards.
+void fine_batch_plan(FineBatch& b, const std::vector<char>& active, hipStream_t s) {
     const int D = (int)b.shapes.size();
     std::vector<int> order;
     for (int d = 0; d < D; ++d)
@@ -298,8 +299,8 @@ void fine_batch_launch(FineBatch& b, const std::vector<char>& active, hipStream_
         if (std::find(keys.begin(), keys.end(), k) == keys.end()) keys.push_back(k);
     }
     std::vector<int2> work;
-    std::vector<std::pair<size_t, size_t>> spans;
-    std::vector<FineShape> shapes;
+    b.spans.clear();
+    b.span_shapes.clear();
     for (int k : keys) {
         const size_t start = work.size();
         FineShape sh{};
@@ -308,8 +309,8 @@ void fine_batch_launch(FineBatch& b, const std::vector<char>& active, hipStream_
             if (b.shapes[d].lds >= sh.lds) sh = b.shapes[d];
             for (int c = 0; c < b.N; ++c) work.push_back(make_int2(d, c));
         }
-        spans.emplace_back(start, work.size() - start);
-        shapes.push_back(sh);
+        b.spans.emplace_back(start, work.size() - start);
+        b.span_shapes.push_back(sh);
     }
     if (work.empty()) return;
     if (work.size() > b.work_cap) {
@@ -317,17 +318,27 @@ void fine_batch_launch(FineBatch& b, const std::vector<char>& active, hipStream_
         PPC_HIP(hipMalloc(&b.d_work, sizeof(int2) * work.size()));
         b.work_cap = work.size();
     }
-    b.host_work = work;   // kept alive until the copy is complete
+    b.host_work = work;
     PPC_HIP(hipMemcpyAsync(b.d_work, b.host_work.data(), sizeof(int2) * work.size(), hipMemcpyHostToDevice, s));
-    for (size_t g = 0; g < spans.size(); ++g) {
-        const int2* w = b.d_work + spans[g].first;
-        const int nb = (int)spans[g].second;
+    PPC_HIP(hipStreamSynchronize(s));
+}
+
+// One launch per kernel shape over the planned work list.
+void fine_batch_run(const FineBatch& b, hipStream_t s) {
+    for (size_t g = 0; g < b.spans.size(); ++g) {
+        const int2* w = b.d_work + b.spans[g].first;
+        const int nb = (int)b.spans[g].second;
         if (b.precision == 0)
-            launch_batch_typed<double>(b.d_args, w, nb, shapes[g], s);
+            launch_batch_typed<double>(b.d_args, w, nb, b.span_shapes[g], s);
         else
-            launch_batch_typed<float>(b.d_args, w, nb, shapes[g], s);
+            launch_batch_typed<float>(b.d_args, w, nb, b.span_shapes[g], s);
     }
     PPC_HIP(hipGetLastError());
+}
+
+void fine_batch_launch(FineBatch& b, const std::vector<char>& active, hipStream_t s) {
+    fine_batch_plan(b, active, s);
+    fine_batch_run(b, s);
 }
 
 }  // namespace ppc

@@ -257,6 +257,9 @@ struct FineBatch {
     std::vector<FineShape> shapes;
     std::vector<int> sizes;
     std::vector<int2> host_work;
+    // the planned launches: spans of d_work and the kernel shape of each
+    std::vector<std::pair<size_t, size_t>> spans;
+    std::vector<FineShape> span_shapes;
     void release();
     ~FineBatch() { release(); }
 };
@@ -318,6 +321,10 @@ void launch_fine_sweep(ppc_problem* pr, const ppc_params* p, const double* U, do
 void fine_batch_prepare(FineBatch& b, const std::vector<ppc_problem*>& parts, const ppc_params* p,
                         hipStream_t s);
 void fine_batch_launch(FineBatch& b, const std::vector<char>& active, hipStream_t s);
+// the same in two parts: the work list of the active designs uploaded (synchronises), then
+// the kernel launches alone (what a captured graph replays)
+void fine_batch_plan(FineBatch& b, const std::vector<char>& active, hipStream_t s);
+void fine_batch_run(const FineBatch& b, hipStream_t s);
 FineArgs make_fine_args(ppc_problem* pr, const ppc_params* p, const double* U, double* F);
 FineShape fine_shape(const ppc_problem* pr, const ppc_params* p);
 void launch_fine_sweep_traj(ppc_problem* pr, const ppc_params* p, const double* U, double* F,
@@ -356,6 +363,20 @@ CocgArgs make_cocg_args(ppc_problem* pr, const ppc_params* p);
 void launch_cocg_batch(const std::vector<ppc_problem*>& parts, const std::vector<int>& list,
                        const ppc_params* p, int H, const CocgArgs* d_args, int2* d_work, std::vector<int2>& cw,
                        hipStream_t s);
+// the same in two parts: the (design, harmonic) work list uploaded (synchronises), then
+// the COCG launches alone
+struct CocgBatchPlan {
+    struct Span {
+        int R;
+        size_t lds;
+        int begin, count;
+    };
+    std::vector<Span> spans;
+    std::vector<int2> cw;
+};
+void cocg_batch_plan(const std::vector<ppc_problem*>& parts, const std::vector<int>& list, const ppc_params* p,
+                     int H, int2* d_work, CocgBatchPlan& plan, hipStream_t s);
+void cocg_batch_run(const CocgBatchPlan& plan, const CocgArgs* d_args, const int2* d_work, hipStream_t s);
 // PP-IC coarse propagation (eq. (5) with the update of eq. (4)): frozen coarse stiffness at
 // the current iterate U, then U_0 = U_N of the last propagation and, for n = 1..N in order,
 // U^{k+1}_n = F_n + Q^{-1} C (U^{k+1}_{n-1} - U^k_{n-1}), Q = C + Kbar, C = M/dT; the value
