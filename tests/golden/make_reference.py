@@ -10,7 +10,8 @@ free nodes in ascending node order), the eps history, the iteration count and th
 generator arguments that define the workload.  Cases ending in ``_ppic`` run PP-IC
 (eq. (5)) instead of PP-PC (c5small from the fine sweep from rest); ``_h3`` runs PP-PC
 solving only the harmonics p = 0, 1, 2 of each correction; ``_routes`` steps period after
-period from zero (route S), its iteration count being the periods stepped.
+period from zero (route S), its iteration count being the periods stepped.  ``c4subset``
+holds a seeded subset of the batched-designs generator on a short grid (see C4_SUBSET).
 """
 from __future__ import annotations
 
@@ -39,6 +40,39 @@ CASES = {
     "c2lin_small_ppic": (coax.c2lin, dict(nr=20, ntheta=40, N=10, m=20), 1e-12),
     "c2lin_small_routes": (coax.c2lin, dict(nr=20, ntheta=40, N=10, m=20), 1e-10),
 }
+
+
+# Seeded subset of the batched-designs generator on a short time grid (N = 8, m = 10): the
+# 8 smallest designs and 4 drawn with default_rng(44) among the others with nr <= 80.
+C4_SUBSET = [178, 188, 149, 8, 91, 197, 237, 74, 27, 55, 144, 184]
+
+
+def c4_subset():
+    return [coax.c4_designs(n_designs=256, N=8, m=10)[i] for i in C4_SUBSET]
+
+
+def make_c4_subset(procs):
+    """PP-PC of each subset design from rest (init "fine") with the 3 T safeguard."""
+    out = {}
+    t = time.time()
+    for i, prob in zip(C4_SUBSET, c4_subset()):
+        fe = FE(prob)
+        pool = periodic.make_pool(prob, procs) if procs > 1 else None
+        try:
+            U, hist, k = periodic.ppc(fe, tol=1e-12, init="fine", b_cap=3.0, pool=pool, max_iter=200)
+        finally:
+            if pool is not None:
+                pool.close()
+                pool.join()
+        out[f"U_{i}"] = U
+        out[f"hist_{i}"] = hist
+        out[f"iterations_{i}"] = k
+        out[f"free_{i}"] = fe.free.astype(np.int32)
+        print(f"  [c4subset] design {i} nr={prob.meta['nr']}: {k} iterations, eps {hist[-1]:.2e}, "
+              f"t={time.time() - t:.0f}s", flush=True)
+    path = os.path.join(HERE, "c4subset_oracle.npz")
+    np.savez_compressed(path, designs=np.array(C4_SUBSET, dtype=np.int32), **out)
+    print(f"wrote {path} in {time.time() - t:.1f}s")
 
 
 def make(name, procs):
@@ -79,11 +113,14 @@ def make(name, procs):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("cases", nargs="*", default=list(CASES))
+    ap.add_argument("cases", nargs="*", default=list(CASES) + ["c4subset"])
     ap.add_argument("--procs", type=int, default=min(8, os.cpu_count() or 1))
     a = ap.parse_args()
     for c in a.cases:
-        make(c, a.procs)
+        if c == "c4subset":
+            make_c4_subset(a.procs)
+        else:
+            make(c, a.procs)
 
 
 if __name__ == "__main__":

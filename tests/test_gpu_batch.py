@@ -90,3 +90,32 @@ def test_batch_c4_designs_subset_runs_and_agrees_with_single():
         assert iters[d] == k and diff == 0.0
         pr.close()
     bp.close()
+
+
+def test_generator_subset_matches_oracle():
+    """The 8 smallest and 4 seeded designs of the batched-designs generator (short grid,
+    N = 8 x 10), batched on the GPU from rest with the 3 T safeguard, against the oracle's
+    PP-PC of each design with the same start and safeguard."""
+    import paper_1905_13076_amd as P
+    from oracle.fe import FE
+    from tests.golden.make_reference import C4_SUBSET, c4_subset
+    from tests.gpu_common import load_golden
+    g = load_golden("c4subset")
+    designs = c4_subset()
+    bp = P.BatchProblem(handle(), designs)
+    prm = P.problem_params(designs[0], tol_ppc=1e-12, init_mode=3, b_cap=3.0, max_iters=200)
+    banner(f"generator subset: {len(designs)} designs")
+    Us, resid, iters, st, rc = bp.solve(prm)
+    assert rc == 0, st
+    worst = 0.0
+    for j, (i, prob) in enumerate(zip(C4_SUBSET, designs)):
+        fe = FE(prob)
+        Uo = g[f"U_{i}"]
+        e = rel(Us[j].cpu().numpy()[:, fe.free], Uo)
+        ko = int(g[f"iterations_{i}"])
+        banner(f"  design {i} nr={prob.meta['nr']}: iters {iters[j]} (oracle {ko}) rel {e:.2e}")
+        assert e <= 1e-10
+        assert abs(int(iters[j]) - ko) <= 1
+        worst = max(worst, e)
+    banner(f"  worst rel {worst:.2e}; corrections scaled by the safeguard: {st['damped']}")
+    bp.close()
