@@ -75,3 +75,46 @@ def test_autograd_matches_finite_differences():
         fd = (vals[0] - vals[1]) / (2 * h)
         banner(f"autograd k{i + 1}: adjoint {gb[mid, i]:.6e} fd {fd:.6e}")
         assert abs(fd - gb[mid, i]) <= 1e-5 * abs(fd)
+
+
+def test_adjoint_c2_mixed_state_and_brauer_fd():
+    """C5(ii): the C2 mesh and inputs.  Gradients at the mixed-precision periodic state
+    agree with those at the FP64 state (the adjoint solves are FP64 in both), and the
+    Brauer gradients match central differences of the loss over FP64 re-solves (a global
+    parameter moves the loss well above the solver's accuracy; a single one of the 14,280
+    elements does not, so element gradients are checked against differences on the small
+    meshes above)."""
+    import paper_1905_13076_amd as P
+    from paper_1905_13076_amd.autograd import periodic_eddy_loss
+    prob = coax.c2()
+    nmat = len(prob.mat_model)
+    pr = P.Problem(handle(), prob)
+    prm64 = P.problem_params(prob, tol_ppc=1e-12)
+    banner("adjoint c2: fp64 state")
+    U64, _, k64, _, rc = pr.solve(prm64)
+    assert rc == 0
+    loss64, ds64, dk64, ka64, _ = pr.adjoint(prm64, U64, nmat)
+    prmm = P.problem_params(prob, precision=1, tol_lin=1e-4, tol_ppc=1e-8, tol_newton=1e-10)
+    banner("adjoint c2: mixed state")
+    Um, _, km, _, rc = pr.solve(prmm)
+    assert rc == 0
+    lossm, dsm, dkm, kam, _ = pr.adjoint(prmm, Um, nmat)
+    eU = rel(Um.cpu().numpy(), U64.cpu().numpy())
+    banner(f"  state rel {eU:.1e}; loss {loss64:.6e} vs {lossm:.6e}; rel(dsigma) {rel(dsm, ds64):.1e} "
+           f"rel(dk) {rel(dkm, dk64):.1e}; adjoint iterations {ka64} / {kam}")
+    assert eU <= 1e-6
+    assert abs(lossm - loss64) <= 1e-6 * abs(loss64)
+    assert rel(dsm, ds64) <= 1e-6 and rel(dkm, dk64) <= 1e-6
+    assert np.all(dk64[0] == 0.0)
+    sigma = torch.tensor(prob.sigma, dtype=torch.float64)
+    brauer = torch.tensor(prob.mat_par[:, 1:4], dtype=torch.float64)
+    for i in range(3):
+        h = 1e-6 * prob.mat_par[1, 1 + i]
+        vals = []
+        for sgn in (1, -1):
+            b2 = brauer.clone()
+            b2[1, i] += sgn * h
+            vals.append(float(periodic_eddy_loss(sigma, b2, prob, prm64, handle())))
+        fd = (vals[0] - vals[1]) / (2 * h)
+        banner(f"  k{i + 1}: adjoint {dk64[1, i]:.6e} fd {fd:.6e}")
+        assert abs(fd - dk64[1, i]) <= 1e-5 * abs(fd)
