@@ -32,7 +32,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 COUNTERS = os.path.join(ROOT, "profiles", "fine_sweep_c2_fp64_counters.md")
-FINE_SRC = os.path.join(ROOT, "paper_1905_13076_amd", "csrc", "fine_chain.hpp")
+# the fine-sweep kernel's device code and the host code that picks its shape
+FINE_SRC = [os.path.join(ROOT, "paper_1905_13076_amd", "csrc", f) for f in ("fine_chain.hpp", "fine.hip")]
 
 
 def measured_traffic(tol_newton):
@@ -43,12 +44,12 @@ def measured_traffic(tol_newton):
     if not os.path.exists(COUNTERS):
         return None
     text = open(COUNTERS).read()
-    m = re.search(r"fine_chain.hpp sha1: ([0-9a-f]{40})", text)
+    m = re.search(r"fine-sweep sources sha1 \(fine_chain.hpp \+ fine.hip\): ([0-9a-f]{40})", text)
     t = re.search(r"traffic_bytes_per_launch: (\d+)", text)
     g = re.search(r"algorithmic_bytes_per_launch: (\d+)", text)
     if not (m and t and g):
         return None
-    if hashlib.sha1(open(FINE_SRC, "rb").read()).hexdigest() != m.group(1):
+    if hashlib.sha1(b"".join(open(f, "rb").read() for f in FINE_SRC)).hexdigest() != m.group(1):
         return None
     tn = re.search(r"tol_newton: ([0-9.eE+-]+)", text)
     if not tn or float(tn.group(1)) != tol_newton:

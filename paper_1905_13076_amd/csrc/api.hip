@@ -609,24 +609,34 @@ int solve_batch_device(ppc_handle* h, ppc_problem* bp, const ppc_params* p, cons
             }
         PPC_HIP(hipMemcpyAsync(hs_p.p, scal.p, sizeof(double) * 3 * D, hipMemcpyDeviceToHost, s));
     };
+    // the designs' own kernels before and after the shared COCG launches run side by side
+    // on the handle's lanes (each design's work stays on one lane, in order)
     auto coarse_ops = [&]() {
-        for (int d : corr) {
-            Workspace& w = parts[d]->ws;
-            launch_coarse_pre(parts[d], p, p->lin_point == 1 ? w.F : w.U, w.J, false, s);
+        {
+            Lanes lanes(h, s);
+            for (size_t i = 0; i < corr.size(); ++i) {
+                Workspace& w = parts[corr[i]]->ws;
+                launch_coarse_pre(parts[corr[i]], p, p->lin_point == 1 ? w.F : w.U, w.J, false, lanes.lane((int)i));
+            }
+            lanes.join();
         }
-        cocg_batch_run(cplan, static_cast<CocgArgs*>(cargs.p), static_cast<int2*>(cwork.p), s);
-        for (int d : corr) {
+        cocg_batch_run(cplan, static_cast<CocgArgs*>(cargs.p), static_cast<int2*>(cwork.p), s, h);
+        Lanes lanes(h, s);
+        for (size_t i = 0; i < corr.size(); ++i) {
+            const int d = corr[i];
             Workspace& w = parts[d]->ws;
+            hipStream_t sd = lanes.lane((int)i);
             if (p->b_cap > 0.0) {
-                launch_coarse_post(parts[d], p, w.R, false, s);
-                launch_safeguarded_update(parts[d], N, p->b_cap, w.R, w.U, w.scal + 8, s);
-                PPC_HIP(hipMemcpyAsync(th_p.p + d, w.scal + 8, sizeof(double), hipMemcpyDeviceToHost, s));
+                launch_coarse_post(parts[d], p, w.R, false, sd);
+                launch_safeguarded_update(parts[d], N, p->b_cap, w.R, w.U, w.scal + 8, sd);
+                PPC_HIP(hipMemcpyAsync(th_p.p + d, w.scal + 8, sizeof(double), hipMemcpyDeviceToHost, sd));
             } else {
-                launch_coarse_post(parts[d], p, w.U, true, s);
+                launch_coarse_post(parts[d], p, w.U, true, sd);
             }
             PPC_HIP(hipMemcpyAsync(cc_p.p + 4 * (size_t)H * d, w.ccount, 4 * (size_t)Hs * sizeof(int),
-                                   hipMemcpyDeviceToHost, s));
+                                   hipMemcpyDeviceToHost, sd));
         }
+        lanes.join();
     };
     std::vector<int> iters(D, p->max_iters);
     int status = PPC_OK;
@@ -975,6 +985,9 @@ int ppc_create(int32_t device, ppc_handle** out) {
         try {
             PPC_HIP(hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking));
             for (auto& ev : h->ev) PPC_HIP(hipEventCreate(&ev));
+            for (auto& st : h->side) PPC_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+            PPC_HIP(hipEventCreateWithFlags(&h->fork, hipEventDisableTiming));
+            for (auto& ev : h->join) PPC_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
         } catch (...) {
             ppc_destroy(h);
             throw;
@@ -993,6 +1006,11 @@ int ppc_destroy(ppc_handle* h) {
     (void)hipSetDevice(h->device);
     for (auto& ev : h->ev)
         if (ev) (void)hipEventDestroy(ev);
+    for (auto& ev : h->join)
+        if (ev) (void)hipEventDestroy(ev);
+    if (h->fork) (void)hipEventDestroy(h->fork);
+    for (auto& st : h->side)
+        if (st) (void)hipStreamDestroy(st);
     if (h->stream) (void)hipStreamDestroy(h->stream);
     delete h;
     return PPC_OK;

@@ -1248,17 +1248,46 @@ void cocg_batch_plan(const std::vector<ppc_problem*>& parts, const std::vector<i
     PPC_HIP(hipStreamSynchronize(s));
 }
 
-void cocg_batch_run(const CocgBatchPlan& plan, const CocgArgs* d_args, const int2* d_work, hipStream_t s) {
-    for (const auto& sp : plan.spans) {
+Lanes::Lanes(ppc_handle* h_, hipStream_t s_) : h(h_), s(s_) {
+    if (h) PPC_HIP(hipEventRecord(h->fork, s));
+}
+
+hipStream_t Lanes::lane(int i) {
+    const int l = h ? i % (1 + ppc_handle::kSide) : 0;
+    if (l == 0) return s;
+    if (!used[l - 1]) {
+        PPC_HIP(hipStreamWaitEvent(h->side[l - 1], h->fork, 0));
+        used[l - 1] = true;
+    }
+    return h->side[l - 1];
+}
+
+void Lanes::join() {
+    for (int i = 0; i < ppc_handle::kSide; ++i)
+        if (used[i]) {
+            PPC_HIP(hipEventRecord(h->join[i], h->side[i]));
+            PPC_HIP(hipStreamWaitEvent(s, h->join[i], 0));
+            used[i] = false;
+        }
+}
+
+// One launch per COCG form; with a handle the forms run side by side on its lanes.
+void cocg_batch_run(const CocgBatchPlan& plan, const CocgArgs* d_args, const int2* d_work, hipStream_t s,
+                    ppc_handle* h) {
+    Lanes lanes(plan.spans.size() > 1 ? h : nullptr, s);
+    for (size_t g = 0; g < plan.spans.size(); ++g) {
+        const auto& sp = plan.spans[g];
         const int2* w = d_work + sp.begin;
+        hipStream_t sg = lanes.lane((int)g);
         switch (sp.R) {
-            case 1: launch_cocg_ell_batch<1>(d_args, w, sp.count, sp.lds, s); break;
-            case 2: launch_cocg_ell_batch<2>(d_args, w, sp.count, sp.lds, s); break;
-            case 4: launch_cocg_ell_batch<4>(d_args, w, sp.count, sp.lds, s); break;
-            case 8: launch_cocg_ell_batch<8>(d_args, w, sp.count, sp.lds, s); break;
-            default: hipLaunchKernelGGL(k_cocg_batch, dim3(sp.count), dim3(kCocgBlock), 0, s, d_args, w);
+            case 1: launch_cocg_ell_batch<1>(d_args, w, sp.count, sp.lds, sg); break;
+            case 2: launch_cocg_ell_batch<2>(d_args, w, sp.count, sp.lds, sg); break;
+            case 4: launch_cocg_ell_batch<4>(d_args, w, sp.count, sp.lds, sg); break;
+            case 8: launch_cocg_ell_batch<8>(d_args, w, sp.count, sp.lds, sg); break;
+            default: hipLaunchKernelGGL(k_cocg_batch, dim3(sp.count), dim3(kCocgBlock), 0, sg, d_args, w);
         }
     }
+    lanes.join();
     PPC_HIP(hipGetLastError());
 }
 

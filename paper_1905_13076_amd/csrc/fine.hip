@@ -7,15 +7,18 @@ namespace ppc {
 namespace {
 
 
-// Register rows (R in {1, 2, 4, 8} rows per thread, the smallest with R rows_block >= n, in
-// workgroups of rows_block threads) when p, r, the FP32 diagonal and the tail sums fit in
+// Register rows (R rows per thread, the smallest with R rows_block >= n, in workgroups of
+// rows_block threads) when p, r, the FP32 diagonal and the tail sums fit in
 // LDS; otherwise (or with block_req = 1024) the memory path with 1024 threads and as much
 // of p / the inverse diagonal in LDS as fits.
 FineShape pick_shape(int n, size_t n_pad, int n_tail, size_t elem, int block_req, int rows_block) {
     const size_t tail = (size_t)std::max(n_tail, 1) * elem;
     if (block_req != kFineBlock) {
-        for (int R : {1, 2, 4, 8}) {
+        // 1024 threads take any R up to 8 (no padded rows beyond the next 1024), the
+        // smaller workgroups powers of two
+        for (int R = 1; R <= 8; ++R) {
             if ((long)R * rows_block < n) continue;
+            if (rows_block != kFineBlock && (R & (R - 1)) != 0) continue;
             const size_t lds = 2 * n_pad * elem + n_pad * sizeof(float) + tail;
             if (lds <= kLdsBudget) return {R, rows_block, 0, lds};
             break;
@@ -42,7 +45,11 @@ void launch_typed(const FineArgs& a, int N, const FineShape& sh, hipStream_t s) 
     if (sh.R > 0 && sh.block != kFineBlock) launch_fine_rows_small(a, N, sh, sizeof(S) == 8, s);
     else if (sh.R == 1) launch_shape<S, 1, kFineBlock, 0>(a, N, sh.lds, s);
     else if (sh.R == 2) launch_shape<S, 2, kFineBlock, 0>(a, N, sh.lds, s);
+    else if (sh.R == 3) launch_shape<S, 3, kFineBlock, 0>(a, N, sh.lds, s);
     else if (sh.R == 4) launch_shape<S, 4, kFineBlock, 0>(a, N, sh.lds, s);
+    else if (sh.R == 5) launch_shape<S, 5, kFineBlock, 0>(a, N, sh.lds, s);
+    else if (sh.R == 6) launch_shape<S, 6, kFineBlock, 0>(a, N, sh.lds, s);
+    else if (sh.R == 7) launch_shape<S, 7, kFineBlock, 0>(a, N, sh.lds, s);
     else if (sh.R == 8) launch_shape<S, 8, kFineBlock, 0>(a, N, sh.lds, s);
     else if (sh.LP == 2) launch_shape<S, 0, kFineBlock, 2>(a, N, sh.lds, s);
     else if (sh.LP == 1) launch_shape<S, 0, kFineBlock, 1>(a, N, sh.lds, s);
@@ -218,7 +225,11 @@ void launch_adjoint_sweep(ppc_problem* pr, const ppc_params* p, const AdjArgs& b
                                     kFineBlock);
     if (sh.R == 1) launch_adj_shape<1, 0>(a, b, sh.lds, s);
     else if (sh.R == 2) launch_adj_shape<2, 0>(a, b, sh.lds, s);
+    else if (sh.R == 3) launch_adj_shape<3, 0>(a, b, sh.lds, s);
     else if (sh.R == 4) launch_adj_shape<4, 0>(a, b, sh.lds, s);
+    else if (sh.R == 5) launch_adj_shape<5, 0>(a, b, sh.lds, s);
+    else if (sh.R == 6) launch_adj_shape<6, 0>(a, b, sh.lds, s);
+    else if (sh.R == 7) launch_adj_shape<7, 0>(a, b, sh.lds, s);
     else if (sh.R == 8) launch_adj_shape<8, 0>(a, b, sh.lds, s);
     else if (sh.LP == 2) launch_adj_shape<0, 2>(a, b, sh.lds, s);
     else if (sh.LP == 1) launch_adj_shape<0, 1>(a, b, sh.lds, s);
@@ -246,7 +257,11 @@ void launch_batch_typed(const FineArgs* args, const int2* work, int nblocks, con
     if (sh.R > 0 && sh.block != kFineBlock) launch_fine_batch_rows_small(args, work, nblocks, sh, sizeof(S) == 8, s);
     else if (sh.R == 1) launch_batch_shape<S, 1, 0>(args, work, nblocks, sh.lds, s);
     else if (sh.R == 2) launch_batch_shape<S, 2, 0>(args, work, nblocks, sh.lds, s);
+    else if (sh.R == 3) launch_batch_shape<S, 3, 0>(args, work, nblocks, sh.lds, s);
     else if (sh.R == 4) launch_batch_shape<S, 4, 0>(args, work, nblocks, sh.lds, s);
+    else if (sh.R == 5) launch_batch_shape<S, 5, 0>(args, work, nblocks, sh.lds, s);
+    else if (sh.R == 6) launch_batch_shape<S, 6, 0>(args, work, nblocks, sh.lds, s);
+    else if (sh.R == 7) launch_batch_shape<S, 7, 0>(args, work, nblocks, sh.lds, s);
     else if (sh.R == 8) launch_batch_shape<S, 8, 0>(args, work, nblocks, sh.lds, s);
     else if (sh.LP == 2) launch_batch_shape<S, 0, 2>(args, work, nblocks, sh.lds, s);
     else if (sh.LP == 1) launch_batch_shape<S, 0, 1>(args, work, nblocks, sh.lds, s);
@@ -277,6 +292,7 @@ void fine_batch_prepare(FineBatch& b, const std::vector<ppc_problem*>& parts, co
         b.shapes[d] = fine_shape(parts[d], p);
         b.sizes.push_back(parts[d]->mesh.n_free);
     }
+    b.h = D > 0 ? parts[0]->h : nullptr;
     if (b.d_args) (void)hipFree(b.d_args);
     PPC_HIP(hipMalloc(&b.d_args, sizeof(FineArgs) * D));
     PPC_HIP(hipMemcpyAsync(b.d_args, host.data(), sizeof(FineArgs) * D, hipMemcpyHostToDevice, s));
@@ -323,16 +339,23 @@ void fine_batch_plan(FineBatch& b, const std::vector<char>& active, hipStream_t 
     PPC_HIP(hipStreamSynchronize(s));
 }
 
-// One launch per kernel shape over the planned work list.
+// One launch per kernel shape over the planned work list.  Several shapes run side by side:
+// group g goes to the main stream (g = 0) or a side stream, which waits for the main
+// stream's work so far and which the main stream waits for at the end, so every group can
+// fill the CUs the others leave free.
 void fine_batch_run(const FineBatch& b, hipStream_t s) {
-    for (size_t g = 0; g < b.spans.size(); ++g) {
+    const size_t G = b.spans.size();
+    Lanes lanes(G > 1 ? b.h : nullptr, s);
+    for (size_t g = 0; g < G; ++g) {
+        hipStream_t sg = lanes.lane((int)g);
         const int2* w = b.d_work + b.spans[g].first;
         const int nb = (int)b.spans[g].second;
         if (b.precision == 0)
-            launch_batch_typed<double>(b.d_args, w, nb, b.span_shapes[g], s);
+            launch_batch_typed<double>(b.d_args, w, nb, b.span_shapes[g], sg);
         else
-            launch_batch_typed<float>(b.d_args, w, nb, b.span_shapes[g], s);
+            launch_batch_typed<float>(b.d_args, w, nb, b.span_shapes[g], sg);
     }
+    lanes.join();
     PPC_HIP(hipGetLastError());
 }
 

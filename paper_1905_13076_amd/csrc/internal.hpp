@@ -159,6 +159,13 @@ struct ppc_handle {
     int device = 0;
     hipStream_t stream = nullptr;
     hipEvent_t ev[8] = {};
+    // side streams (default priority) for launches that may overlap on the device: the
+    // kernel-shape groups of a batched fine sweep; fork / join events order them with the
+    // main stream (and record the same dependencies under graph capture)
+    static constexpr int kSide = 3;
+    hipStream_t side[kSide] = {};
+    hipEvent_t fork = nullptr;
+    hipEvent_t join[kSide] = {};
     std::string last_error;
     int n_problems = 0;
 };
@@ -257,6 +264,7 @@ struct FineBatch {
     std::vector<FineShape> shapes;
     std::vector<int> sizes;
     std::vector<int2> host_work;
+    ppc_handle* h = nullptr;   // side streams and events for concurrent shape groups
     // the planned launches: spans of d_work and the kernel shape of each
     std::vector<std::pair<size_t, size_t>> spans;
     std::vector<FineShape> span_shapes;
@@ -376,7 +384,20 @@ struct CocgBatchPlan {
 };
 void cocg_batch_plan(const std::vector<ppc_problem*>& parts, const std::vector<int>& list, const ppc_params* p,
                      int H, int2* d_work, CocgBatchPlan& plan, hipStream_t s);
-void cocg_batch_run(const CocgBatchPlan& plan, const CocgArgs* d_args, const int2* d_work, hipStream_t s);
+void cocg_batch_run(const CocgBatchPlan& plan, const CocgArgs* d_args, const int2* d_work, hipStream_t s,
+                    ppc_handle* h = nullptr);
+
+// The main stream s and the handle's side streams as lanes for independent work: lane(i)
+// forks a side stream from s's work so far on first use; join() makes s wait for every
+// lane used (stream-ordered, so it also holds under graph capture).
+struct Lanes {
+    ppc_handle* h;
+    hipStream_t s;
+    bool used[ppc_handle::kSide] = {};
+    Lanes(ppc_handle* h_, hipStream_t s_);
+    hipStream_t lane(int i);
+    void join();
+};
 // PP-IC coarse propagation (eq. (5) with the update of eq. (4)): frozen coarse stiffness at
 // the current iterate U, then U_0 = U_N of the last propagation and, for n = 1..N in order,
 // U^{k+1}_n = F_n + Q^{-1} C (U^{k+1}_{n-1} - U^k_{n-1}), Q = C + Kbar, C = M/dT; the value

@@ -229,8 +229,8 @@ def test_c2_nonlinear_fp64_matches_oracle():
 
 
 # fine-sweep kernel paths: (mesh rings, ntheta, precision, forced memory path)
-#   nr=20  (761 free)   -> register rows (R=2, 512 threads) or forced memory path
-#   nr=60  (7,081)      -> memory path, p and inverse diagonal in LDS (FP64)
+#   nr=20  (761 free)   -> register rows (R=1, 1024 threads) or forced memory path
+#   nr=60  (7,081)      -> register rows (R=7, 1024 threads)
 #   nr=80  (12,641)     -> memory path, p in LDS only (FP64); p + diagonal (FP32)
 #   nr=100 (19,801)     -> memory path, nothing in LDS (FP64)
 @pytest.mark.parametrize("nr,prec,force", [
@@ -260,4 +260,28 @@ def test_fine_sweep_kernel_paths_match_oracle(nr, prec, force):
     F, newton, lin = pr.fine_sweep(prm, torch.tensor(_nodal(fe, U0), device="cuda"))
     e = rel(free_rows(F.cpu().numpy(), fe.free), Fo)
     banner(f"fine path nr={nr} prec={prec} force={force} rel={e:.2e} newton={newton.tolist()} lin={lin.tolist()}")
+    assert e <= 1e-10
+
+
+# register rows at 1024 threads: R = ceil(rows / 1024) for every R = 1..8
+@pytest.mark.parametrize("nr,ntheta,R", [(20, 40, 1), (25, 60, 2), (35, 80, 3), (40, 100, 4),
+                                         (45, 100, 5), (50, 110, 6), (60, 120, 7), (62, 124, 8)])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_register_row_counts_match_oracle(nr, ntheta, R, prec):
+    import torch
+    import paper_1905_13076_amd as P
+    from oracle.fe import FE
+    from oracle import periodic
+    prob = coax.c2(nr=nr, ntheta=ntheta, N=4, m=2)
+    fe = FE(prob)
+    assert (fe.n + 1023) // 1024 == R
+    rng = np.random.default_rng(nr + prec)
+    r = np.hypot(prob.xy[fe.free, 0], prob.xy[fe.free, 1])
+    U0 = np.outer(1.0 + 0.1 * rng.standard_normal(prob.N), 1e-4 * (3e-3 - r) / 3e-3)
+    Fo = periodic.fine_sweep(fe, U0)
+    pr = _problem(prob)
+    prm = P.problem_params(prob, precision=prec, fine_block=1024, tol_lin=1e-8 if prec == 0 else 1e-4)
+    F, newton, lin = pr.fine_sweep(prm, torch.tensor(_nodal(fe, U0), device="cuda"))
+    e = rel(free_rows(F.cpu().numpy(), fe.free), Fo)
+    banner(f"register rows R={R} ({fe.n} rows) prec={prec} rel={e:.2e}")
     assert e <= 1e-10
