@@ -349,11 +349,21 @@ __device__ int pcg_regs(const FineArgs& a, const S* __restrict__ jv, S* __restri
                     for (int k = 0; k < R; ++k) q[k] += v[u][k] * pg[u][k];
             }
         }
+        // FP32: this thread's rows of p (and below of z) stay in registers through the
+        // iteration, the LDS copy serving the other threads' gathers.  FP64 rereads them from
+        // LDS: the extra live registers cost more in spills than the reads save.
+        constexpr bool kCache = sizeof(S) == 4;
+        S pc[R];
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const int i = tid + k * B;
+            if constexpr (kCache) pc[k] = i < n ? p_l[i] : (S)0;
+        }
         S dot[2] = {0, 0};
 #pragma unroll
         for (int k = 0; k < R; ++k) {
             const int i = tid + k * B;
-            if (i < n && !((tailmask >> k) & 1u)) dot[0] += p_l[i] * q[k];
+            if (i < n && !((tailmask >> k) & 1u)) dot[0] += (kCache ? pc[k] : p_l[i]) * q[k];
         }
         if (tail1) {
             const S qt = tv * p_l[tc];
@@ -373,15 +383,18 @@ __device__ int pcg_regs(const FineArgs& a, const S* __restrict__ jv, S* __restri
         if (!(pq > (S)0)) break;                 // loss of positivity: Newton decides
         const S alpha = rz / pq;
         S l2[2] = {0, 0};
+        S zc[R];
 #pragma unroll
         for (int k = 0; k < R; ++k) {
             const int i = tid + k * B;
+            if constexpr (kCache) zc[k] = 0;
             if (i < n) {
                 if ((tailmask >> k) & 1u) q[k] = tail1 ? dot[1] : tq_l[a.ecol[NP + i]];
-                x[k] += alpha * p_l[i];
+                x[k] += alpha * (kCache ? pc[k] : p_l[i]);
                 const S rv = r_l[i] - alpha * q[k];
                 r_l[i] = rv;
                 const S z = (S)d_l[i] * rv;
+                if constexpr (kCache) zc[k] = z;
                 l2[0] += rv * z;
                 l2[1] += rv * rv;
             }
@@ -395,7 +408,10 @@ __device__ int pcg_regs(const FineArgs& a, const S* __restrict__ jv, S* __restri
 #pragma unroll
         for (int k = 0; k < R; ++k) {
             const int i = tid + k * B;
-            if (i < n) p_l[i] = (S)d_l[i] * r_l[i] + beta * p_l[i];
+            if (i < n) {
+                if constexpr (kCache) p_l[i] = zc[k] + beta * pc[k];
+                else p_l[i] = (S)d_l[i] * r_l[i] + beta * p_l[i];
+            }
         }
         __syncthreads();
     }
