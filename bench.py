@@ -75,9 +75,10 @@ def parse():
     ap.add_argument("--n-harm", type=int, default=0,
                     help="harmonics each PP-PC correction solves (0: all N/2+1); the others "
                          "take the jumps' harmonics")
-    ap.add_argument("--init", default="auto", choices=["auto", "rest"],
-                    help="U^0: auto (zero for nonlinear, coarse periodic for linear) or rest "
-                         "(one fine sweep from zero, U^0_n = F_n(0))")
+    ap.add_argument("--init", default="nested", choices=["nested", "auto", "rest"],
+                    help="U^0: nested (PP-PC on a 25 times coarser fine grid to eps <= 1e-2, "
+                         "the default), auto (zero for nonlinear, coarse periodic for linear) or "
+                         "rest (one fine sweep from zero, U^0_n = F_n(0))")
     ap.add_argument("--tol", type=float, default=1e-7,
                     help="PP-PC stopping tolerance on eps (the metric asks for 1e-6 relative error "
                          "against the FP64 oracle; 1e-7 reaches 6.8e-8 on C2)")
@@ -336,7 +337,7 @@ def main():
     if a.probe == "fine":
         return probe_fine(a, prob, ref)
     cpu = None
-    if a.cpu and ref is not None and a.method == "ppc" and a.init == "auto" and a.n_harm == 0:
+    if a.cpu and ref is not None and a.method == "ppc" and a.n_harm == 0:
         # before any GPU initialisation: the oracle's worker pool forks this process
         cpu = cpu_baseline(prob, ref, a.cpu_procs, a.tol)
     import numpy as np
@@ -354,7 +355,7 @@ def main():
     if a.precision == "mixed-fine":          # FP32 PCG fine solves, FP64 harmonic solves
         extra["coarse_precision"] = 0
     extra["method"] = 1 if a.method == "ppic" else 0
-    extra["init_mode"] = 3 if a.init == "rest" else 0
+    extra["init_mode"] = {"auto": 0, "rest": 3, "nested": 4}[a.init]
     extra["n_harm"] = a.n_harm
     if a.n_harm:
         extra["max_iters"] = 300

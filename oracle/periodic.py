@@ -21,13 +21,14 @@ TEST INFRASTRUCTURE ONLY: see the package docstring.
 """
 from __future__ import annotations
 
+import copy
 import math
 
 import numpy as np
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
-from .fe import BRAUER
+from .fe import BRAUER, FE
 from .timestep import NEWTON_TOL, fine_propagate, ie_step
 
 
@@ -194,6 +195,9 @@ def initial_iterate(fe, shift="ie", lin="tensor", mode="auto", pool=None):
     stiffness at u = 0.  mode "zero": U^0 = 0.  mode "fine": one fine sweep from zero,
     U^0_n = F_n(0) -- every subinterval starts from rest, so the samples carry the
     saturation the fine propagator produces instead of the one a linearisation predicts.
+    mode "nested": PP-PC of the same problem on a 25 times coarser fine grid
+    (max(1, m // 25) steps per subinterval) to eps <= 1e-2 -- a cheap first approximation
+    (reading; the fixed point does not depend on U^0).
     mode "auto": "coarse" when every material is linear, else "zero" -- at u = 0 a
     Brauer material has its unsaturated reluctivity, and a coarse solve with it can put
     tens of tesla into the steel, where exp(k2 b^2) overflows."""
@@ -202,6 +206,13 @@ def initial_iterate(fe, shift="ie", lin="tensor", mode="auto", pool=None):
         mode = "coarse" if np.all(prob.mat_model[np.unique(prob.mat_id)] == 0) else "zero"
     if mode == "zero":
         return np.zeros((prob.N, fe.n))
+    if mode == "nested":
+        # the periodic solution of the same problem with max(1, m // 25) fine steps per
+        # subinterval, by PP-PC to eps <= 1e-2 from the automatic start
+        coarse = copy.copy(prob)
+        coarse.m = max(1, prob.m // 25)
+        U, _, _ = ppc(FE(coarse), tol=1e-2, max_iter=200, shift=shift, lin=lin, pool=None)
+        return U
     if mode == "fine":
         return fine_sweep(fe, np.zeros((prob.N, fe.n)), pool=pool)
     if mode != "coarse":

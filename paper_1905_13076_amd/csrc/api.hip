@@ -301,13 +301,38 @@ int solve_device(ppc_handle* h, ppc_problem* pr, const ppc_params* p, const doub
     S.nnz = d.nnz;
     S.n_tri = d.n_tri;
     hipEvent_t* ev = h->ev;
+    double nested_ms = 0.0;
     PPC_HIP(hipEventRecord(ev[4], s));
     if (U_init_dev) {
         launch_to_free(pr, N, U_init_dev, w.U, s);
     } else {
         int mode = p->init_mode;
         if (mode == 0) mode = d.nonlinear ? 2 : 1;
-        if (mode == 2) {
+        if (mode == 4) {
+            // nested start: PP-PC of the same problem with max(1, m / 25) fine steps per
+            // subinterval to eps <= 1e-2 from the automatic start; its samples are U^0
+            ppc_params q = *p;
+            q.m = std::max(1, p->m / 25);
+            q.tol_ppc = std::max(p->tol_ppc, 1e-2);
+            q.init_mode = 0;
+            ppc_stats Sq{};
+            (void)solve_device(h, pr, &q, nullptr, nullptr, nullptr, nullptr, &Sq, s);
+            S.fine_launches += Sq.fine_launches;
+            S.fine_ms += Sq.fine_ms;
+            S.newton_total += Sq.newton_total;
+            S.lin_total += Sq.lin_total;
+            S.newton_max = std::max(S.newton_max, Sq.newton_max);
+            S.lin_max = std::max(S.lin_max, Sq.lin_max);
+            S.lin_capped += Sq.lin_capped;
+            S.resid_total += Sq.resid_total;
+            S.steps_total += Sq.steps_total;
+            S.cocg_total += Sq.cocg_total;
+            S.cocg_max = std::max(S.cocg_max, Sq.cocg_max);
+            S.coarse_solves += Sq.coarse_solves;
+            S.coarse_ms += Sq.coarse_ms;
+            nested_ms = Sq.total_ms;
+            PPC_HIP(hipEventRecord(ev[4], s));   // the nested solve reused the solve's events
+        } else if (mode == 2) {
             fill(w.U, (long)N * n, 0.0, s);
         } else if (mode == 3) {
             // one fine sweep from rest: U^0_n = F_n(0)
@@ -420,7 +445,7 @@ int solve_device(ppc_handle* h, ppc_problem* pr, const ppc_params* p, const doub
     PPC_HIP(hipEventRecord(ev[5], s));
     PPC_HIP(hipStreamSynchronize(s));
     S.max_b_steel = d.nonlinear ? w.host_scal[4] : 0.0;
-    S.total_ms = elapsed(ev[4], ev[5]);
+    S.total_ms = elapsed(ev[4], ev[5]) + nested_ms;
     S.status = status;
     if (iters_out) *iters_out = S.iterations;
     if (st) *st = S;
@@ -457,6 +482,7 @@ int solve_batch_device(ppc_handle* h, ppc_problem* bp, const ppc_params* p, cons
                        hipStream_t s) {
     PPC_HIP(hipSetDevice(h->device));
     if (p->method != 0) fail(PPC_ERR_ARG, "PP-IC (method 1) runs single-design problems only");
+    if (p->init_mode == 4) fail(PPC_ERR_ARG, "the nested start (init_mode 4) is for single-design solves");
     auto& parts = bp->parts;
     const int D = (int)parts.size();
     const int N = p->N, H = N / 2 + 1, R1 = p->max_iters + 1;

@@ -128,7 +128,7 @@ int validate_params(const ppc_params* p, std::string& msg) {
     if (p->m < 1) { msg = "m must be >= 1"; return PPC_ERR_ARG; }
     if (p->shift_mode < 0 || p->shift_mode > 1) { msg = "shift_mode must be 0 or 1"; return PPC_ERR_ARG; }
     if (p->lin_mode < 0 || p->lin_mode > 1) { msg = "lin_mode must be 0 or 1"; return PPC_ERR_ARG; }
-    if (p->init_mode < 0 || p->init_mode > 3) { msg = "init_mode must be 0, 1, 2 or 3"; return PPC_ERR_ARG; }
+    if (p->init_mode < 0 || p->init_mode > 4) { msg = "init_mode must be 0, 1, 2, 3 or 4"; return PPC_ERR_ARG; }
     if (p->precision < 0 || p->precision > 1) { msg = "precision must be 0 or 1"; return PPC_ERR_ARG; }
     if (p->graph < 0 || p->graph > 1) { msg = "graph must be 0 or 1"; return PPC_ERR_ARG; }
     if (p->method < 0 || p->method > 1) { msg = "method must be 0 (PP-PC) or 1 (PP-IC)"; return PPC_ERR_ARG; }

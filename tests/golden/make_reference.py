@@ -9,7 +9,7 @@ Each output ``<name>_oracle.npz`` holds the fixed point U (rows n = 0..N-1, colu
 free nodes in ascending node order), the eps history, the iteration count and the
 generator arguments that define the workload.  Cases ending in ``_ppic`` run PP-IC
 (eq. (5)) instead of PP-PC (c5small from the fine sweep from rest); ``_h3`` runs PP-PC
-solving only the harmonics p = 0, 1, 2 of each correction; ``_routes`` steps period after
+solving only the harmonics p = 0, 1, 2 of each correction, ``_nested`` from the nested start; ``_routes`` steps period after
 period from zero (route S), its iteration count being the periods stepped.  ``c4subset``
 holds a seeded subset of the batched-designs generator on a short grid (see C4_SUBSET).
 """
@@ -36,6 +36,7 @@ CASES = {
     "c5small": (coax.c5_small, {}, 1e-12),
     "c5small_ppic": (coax.c5_small, {}, 1e-12),
     "c5small_h3": (coax.c5_small, {}, 1e-12),
+    "c5small_nested": (coax.c5_small, {}, 1e-12),
     "c2lin_small": (coax.c2lin, dict(nr=20, ntheta=40, N=10, m=20), 1e-12),
     "c2lin_small_ppic": (coax.c2lin, dict(nr=20, ntheta=40, N=10, m=20), 1e-12),
     "c2lin_small_routes": (coax.c2lin, dict(nr=20, ntheta=40, N=10, m=20), 1e-10),
@@ -96,6 +97,8 @@ def make(name, procs):
             U, hist, k = periodic.ppic(fe, tol=tol, U_init=U0, pool=pool, callback=cb)
         elif name.endswith("_ppic"):
             U, hist, k = periodic.ppic(fe, tol=tol, pool=pool, callback=cb)
+        elif name.endswith("_nested"):  # start from the 25 times coarser fine grid's solution
+            U, hist, k = periodic.ppc(fe, tol=tol, pool=pool, callback=cb, init="nested")
         elif name.endswith("_h3"):      # truncated harmonic set: p = 0, 1, 2 solved
             U, hist, k = periodic.ppc(fe, tol=tol, pool=pool, callback=cb, n_harm=3)
         else:

@@ -137,7 +137,7 @@ def test_invalid_problems_are_rejected_on_host(case, code, needle):
     (dict(block=100), "block"), (dict(max_newton=0), "max_newton"), (dict(tol_ppc=float("nan")), "tol_ppc"),
     (dict(coarse_precision=2), "coarse_precision"), (dict(coarse_precision=-2), "coarse_precision"),
     (dict(graph=2), "graph"), (dict(b_cap=-1.0), "b_cap"), (dict(b_cap=float("inf")), "b_cap"),
-    (dict(init_mode=4), "init_mode"), (dict(method=2), "method"), (dict(method=-1), "method"),
+    (dict(init_mode=5), "init_mode"), (dict(method=2), "method"), (dict(method=-1), "method"),
     (dict(method=1, b_cap=3.0), "b_cap"), (dict(fine_block=128), "fine_block"),
     (dict(fine_block=512, block=1024), "fine_block"), (dict(n_harm=7), "n_harm"),
     (dict(n_harm=-1), "n_harm"), (dict(method=1, n_harm=3), "n_harm"),

@@ -285,3 +285,30 @@ def test_register_row_counts_match_oracle(nr, ntheta, R, prec):
     e = rel(free_rows(F.cpu().numpy(), fe.free), Fo)
     banner(f"register rows R={R} ({fe.n} rows) prec={prec} rel={e:.2e}")
     assert e <= 1e-10
+
+
+def test_nested_start_matches_oracle():
+    """init_mode 4 (PP-PC on the 25 times coarser fine grid to eps <= 1e-2, then on the real
+    grid): C5-small against the oracle's init "nested" (same iterations, same fixed point),
+    and C2 reaching the stored fixed point of the plain start."""
+    import paper_1905_13076_amd as P
+    from oracle.fe import FE
+    prob = coax.c5_small()
+    fe = FE(prob)
+    g = load_golden("c5small_nested")
+    pr = _problem(prob)
+    U, eps, k, st, rc = pr.solve(P.problem_params(prob, init_mode=4))
+    assert rc == 0
+    e = rel(free_rows(U.cpu().numpy(), fe.free), g["U"])
+    banner(f"c5small nested: iters {k} (oracle {int(g['iterations'])}) rel {e:.2e} "
+           f"fine launches {st['fine_launches']}")
+    assert e <= 1e-10 and abs(k - int(g["iterations"])) <= 1
+    prob2 = coax.c2()
+    fe2 = FE(prob2)
+    g2 = load_golden("c2")
+    pr2 = _problem(prob2)
+    U2, eps2, k2, st2, rc2 = pr2.solve(P.problem_params(prob2, init_mode=4, tol_ppc=1e-12))
+    assert rc2 == 0
+    e2 = rel(free_rows(U2.cpu().numpy(), fe2.free), g2["U"])
+    banner(f"c2 nested: iters {k2} (plain start: 34) rel {e2:.2e}")
+    assert e2 <= 1e-10

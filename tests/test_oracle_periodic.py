@@ -267,6 +267,19 @@ def test_truncated_harmonics_with_a_slow_transient_need_the_low_harmonics():
         periodic.ppc(fe, tol=1e-9, n_harm=1, max_iter=5 * kf)
 
 
+def test_nested_start_reaches_the_same_fixed_point_in_fewer_iterations():
+    """U^0 from PP-PC on a 25 times coarser fine grid (2 instead of 50 steps per
+    subinterval): the same periodic solution as from zero, in fewer iterations."""
+    fe = FE(coax.tiny(nr=6, ntheta=12, N=8, m=50, nonlinear=True, amp=500.0))
+    Uz, hz, kz = periodic.ppc(fe, tol=1e-12, init="zero")
+    Un, hn, kn = periodic.ppc(fe, tol=1e-12, init="nested")
+    assert rel(Un, Uz) <= 1e-10
+    assert kn < kz
+    # the start is the coarser grid's periodic state: closer than zero, not the answer
+    U0 = periodic.initial_iterate(fe, mode="nested")
+    assert 1e-6 < rel(U0, Uz) < 0.5
+
+
 def test_epsilon_definition():
     U = np.ones((2, 3))
     assert periodic.periodicity_residual(U, 0.5 * U) == pytest.approx(0.5)
