@@ -443,8 +443,10 @@ def main():
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": (traffic or {}).get("bytes"),
             "traffic_source": ("rocprofv3 FETCH_SIZE+WRITE_SIZE (copy-calibrated) of one C2 fine sweep "
-                               "from the oracle fixed point, profiles/fine_sweep_c2_fp64_counters.md; "
-                               f"algorithmic bytes of that launch {traffic['algorithmic_bytes_same_launch']}")
+                               "(50 steps per chain) from the oracle fixed point, "
+                               "profiles/fine_sweep_c2_fp64_counters.md; algorithmic bytes of that launch "
+                               f"{traffic['algorithmic_bytes_same_launch']} (the timed launches also "
+                               "include the nested start's 2-step sweeps)")
                               if traffic else None,
             "bytes_per_launch": bytes_launch,
             "launch_ms": launch_s * 1e3,
