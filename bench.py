@@ -223,7 +223,7 @@ def bench_batch(a):
         extra["coarse_precision"] = 0
     prm = P.problem_params(designs[0], tol_ppc=a.tol, precision=prec, tol_cocg=a.tol_cocg, max_newton=200,
                            tol_newton=a.tol_newton,
-                           init_mode=3, b_cap=3.0, **extra)
+                           init_mode=4 if a.init == "nested" else 3, b_cap=3.0, **extra)
     tuned = None
     if a.autotune:
         # untimed set-up: the fine-sweep workgroup size per size class
@@ -252,7 +252,8 @@ def bench_batch(a):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if prec == 0 else "f32+f64", "data": "synthetic",
         "config": {"workload": f"batched designs: {len(designs)} designs, nr {min(nrs)}-{max(nrs)} "
-                               f"(ntheta = 2 nr), N=40 x m=50, 21 harmonics each; from rest, b_cap 3 T",
+                               f"(ntheta = 2 nr), N=40 x m=50, 21 harmonics each; b_cap 3 T",
+                   "init": "nested (from rest on the coarser grid)" if a.init == "nested" else "from rest",
                    "precision": a.precision, "tol_ppc": a.tol, "tol_cocg": a.tol_cocg,
                    "tol_newton": a.tol_newton,
                    "iterations_max": int(max(iters)), "damped_corrections": st["damped"],

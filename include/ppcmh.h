@@ -103,9 +103,10 @@ typedef struct {
                                else 2), 1 linear coarse periodic solve at u = 0, 2 zero,
                                3 one fine sweep from rest, U^0_n = F_n(0) (for strongly
                                saturating designs, where a first correction from zero can
-                               overshoot), 4 nested: PP-PC of the same problem with
-                               max(1, m/25) fine steps per subinterval to eps <= 1e-2 (a
-                               cheap first approximation; single-design solves) */
+                               overshoot), 4 nested: PP-PC of the same problem (every
+                               design of a batch) with max(1, m/25) fine steps per
+                               subinterval to eps <= 1e-2, from rest when b_cap > 0 and from
+                               the automatic start otherwise (a cheap first approximation) */
     int32_t precision;      /* 0: FP64 fine solves; 1: FP32 PCG refined by FP64 Newton */
     double tol_ppc;         /* stop when ||J||_F / ||U||_F <= tol_ppc */
     int32_t max_iters;      /* maximum coarse corrections */

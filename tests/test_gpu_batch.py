@@ -24,7 +24,7 @@ def _designs():
     return out
 
 
-@pytest.mark.parametrize("prec,init", [(0, 0), (1, 0), (0, 3)])
+@pytest.mark.parametrize("prec,init", [(0, 0), (1, 0), (0, 3), (0, 4)])
 def test_batch_equals_single_design_solves(prec, init):
     import paper_1905_13076_amd as P
     designs = _designs()
