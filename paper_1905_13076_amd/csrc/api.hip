@@ -289,12 +289,15 @@ void check_params(const ppc_params* p) {
 }
 
 // Parameters of the nested start's solve: max(1, m / 25) fine steps per subinterval, eps
-// to 1e-2, from rest when the correction safeguard is on (strongly saturating designs) and
-// from the automatic start otherwise.
+// to 1e-2 (Newton to 1e-8 and harmonic solves to 1e-4 of their scales, well below that), from
+// rest when the correction safeguard is on (strongly saturating designs) and from the
+// automatic start otherwise.
 ppc_params nested_params(const ppc_params* p) {
     ppc_params q = *p;
     q.m = std::max(1, p->m / 25);
     q.tol_ppc = std::max(p->tol_ppc, 1e-2);
+    q.tol_newton = std::max(p->tol_newton, 1e-8);
+    q.tol_cocg = std::max(p->tol_cocg, 1e-4);
     q.init_mode = p->b_cap > 0.0 ? 3 : 0;
     return q;
 }
