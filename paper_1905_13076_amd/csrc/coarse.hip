@@ -1131,7 +1131,7 @@ int cocg_ell_rows(const ppc_problem* pr, const CocgArgs& a, size_t& lds) {
     if (a.mixed || !d.ecol16) return 0;
     lds = (pr->ws.n_pad + (size_t)std::max(d.n_tail, 1)) * sizeof(double2);
     if (lds > kLdsBudget) return 0;
-    for (int R : {1, 2, 4, 8})
+    for (int R : {1, 2, 4, 8, 12})
         if ((long)R * kCocgBlock >= d.n_free) return R;
     return 0;
 }
@@ -1183,6 +1183,7 @@ void launch_cocg_solves(const ppc_problem* pr, const CocgArgs& a, hipStream_t s)
         case 2: launch_cocg_ell<2>(a, lds, s); break;
         case 4: launch_cocg_ell<4>(a, lds, s); break;
         case 8: launch_cocg_ell<8>(a, lds, s); break;
+        case 12: launch_cocg_ell<12>(a, lds, s); break;
         default: hipLaunchKernelGGL(k_cocg, dim3(a.H), dim3(kCocgBlock), 0, s, a);
     }
     PPC_HIP(hipGetLastError());
@@ -1231,7 +1232,7 @@ void cocg_batch_plan(const std::vector<ppc_problem*>& parts, const std::vector<i
                      int H, int2* d_work, CocgBatchPlan& plan, hipStream_t s) {
     plan.spans.clear();
     plan.cw.clear();
-    for (int R : {0, 1, 2, 4, 8}) {
+    for (int R : {0, 1, 2, 4, 8, 12}) {
         CocgBatchPlan::Span sp{R, 0, (int)plan.cw.size(), 0};
         for (int d : list) {
             const CocgArgs a = make_cocg_args(parts[d], p);
@@ -1284,6 +1285,7 @@ void cocg_batch_run(const CocgBatchPlan& plan, const CocgArgs* d_args, const int
             case 2: launch_cocg_ell_batch<2>(d_args, w, sp.count, sp.lds, sg); break;
             case 4: launch_cocg_ell_batch<4>(d_args, w, sp.count, sp.lds, sg); break;
             case 8: launch_cocg_ell_batch<8>(d_args, w, sp.count, sp.lds, sg); break;
+            case 12: launch_cocg_ell_batch<12>(d_args, w, sp.count, sp.lds, sg); break;
             default: hipLaunchKernelGGL(k_cocg_batch, dim3(sp.count), dim3(kCocgBlock), 0, sg, d_args, w);
         }
     }

@@ -14,9 +14,10 @@ namespace {
 FineShape pick_shape(int n, size_t n_pad, int n_tail, size_t elem, int block_req, int rows_block) {
     const size_t tail = (size_t)std::max(n_tail, 1) * elem;
     if (block_req != kFineBlock) {
-        // 1024 threads take any R up to 8 (no padded rows beyond the next 1024), the
-        // smaller workgroups powers of two
-        for (int R = 1; R <= 8; ++R) {
+        // 1024 threads take any R up to 8 (no padded rows beyond the next 1024), and up to
+        // 12 in FP32 (in FP64 the LDS runs out first); the smaller workgroups powers of two
+        const int rmax = (rows_block == kFineBlock && elem == sizeof(float)) ? 12 : 8;
+        for (int R = 1; R <= rmax; ++R) {
             if ((long)R * rows_block < n) continue;
             if (rows_block != kFineBlock && (R & (R - 1)) != 0) continue;
             const size_t lds = 2 * n_pad * elem + n_pad * sizeof(float) + tail;
@@ -40,6 +41,22 @@ void launch_shape(const FineArgs& a, int N, size_t lds, hipStream_t s) {
     hipLaunchKernelGGL((k_fine_sweep<S, R, BLOCK, LP>), dim3(N), dim3(BLOCK), lds, s, a);
 }
 
+// R = 9..12 rows per thread at 1024 threads: FP32 only (an FP64 mesh that needs them does
+// not fit LDS and takes the memory path)
+template <typename S>
+void launch_wide(const FineArgs& a, int N, const FineShape& sh, hipStream_t s) {
+    if constexpr (sizeof(S) == 4) {
+        switch (sh.R) {
+            case 9: launch_shape<S, 9, kFineBlock, 0>(a, N, sh.lds, s); return;
+            case 10: launch_shape<S, 10, kFineBlock, 0>(a, N, sh.lds, s); return;
+            case 11: launch_shape<S, 11, kFineBlock, 0>(a, N, sh.lds, s); return;
+            case 12: launch_shape<S, 12, kFineBlock, 0>(a, N, sh.lds, s); return;
+            default: break;
+        }
+    }
+    fail(PPC_ERR_ARG, "no fine kernel with " + std::to_string(sh.R) + " rows per thread");
+}
+
 template <typename S>
 void launch_typed(const FineArgs& a, int N, const FineShape& sh, hipStream_t s) {
     if (sh.R > 0 && sh.block != kFineBlock) launch_fine_rows_small(a, N, sh, sizeof(S) == 8, s);
@@ -51,6 +68,7 @@ void launch_typed(const FineArgs& a, int N, const FineShape& sh, hipStream_t s) 
     else if (sh.R == 6) launch_shape<S, 6, kFineBlock, 0>(a, N, sh.lds, s);
     else if (sh.R == 7) launch_shape<S, 7, kFineBlock, 0>(a, N, sh.lds, s);
     else if (sh.R == 8) launch_shape<S, 8, kFineBlock, 0>(a, N, sh.lds, s);
+    else if (sh.R > 8) launch_wide<S>(a, N, sh, s);
     else if (sh.LP == 2) launch_shape<S, 0, kFineBlock, 2>(a, N, sh.lds, s);
     else if (sh.LP == 1) launch_shape<S, 0, kFineBlock, 1>(a, N, sh.lds, s);
     else launch_shape<S, 0, kFineBlock, 0>(a, N, 0, s);
@@ -252,6 +270,20 @@ void launch_batch_shape(const FineArgs* args, const int2* work, int nblocks, siz
 }
 
 template <typename S>
+void launch_batch_wide(const FineArgs* args, const int2* work, int nblocks, const FineShape& sh, hipStream_t s) {
+    if constexpr (sizeof(S) == 4) {
+        switch (sh.R) {
+            case 9: launch_batch_shape<S, 9, 0>(args, work, nblocks, sh.lds, s); return;
+            case 10: launch_batch_shape<S, 10, 0>(args, work, nblocks, sh.lds, s); return;
+            case 11: launch_batch_shape<S, 11, 0>(args, work, nblocks, sh.lds, s); return;
+            case 12: launch_batch_shape<S, 12, 0>(args, work, nblocks, sh.lds, s); return;
+            default: break;
+        }
+    }
+    fail(PPC_ERR_ARG, "no fine kernel with " + std::to_string(sh.R) + " rows per thread");
+}
+
+template <typename S>
 void launch_batch_typed(const FineArgs* args, const int2* work, int nblocks, const FineShape& sh,
                         hipStream_t s) {
     if (sh.R > 0 && sh.block != kFineBlock) launch_fine_batch_rows_small(args, work, nblocks, sh, sizeof(S) == 8, s);
@@ -263,6 +295,7 @@ void launch_batch_typed(const FineArgs* args, const int2* work, int nblocks, con
     else if (sh.R == 6) launch_batch_shape<S, 6, 0>(args, work, nblocks, sh.lds, s);
     else if (sh.R == 7) launch_batch_shape<S, 7, 0>(args, work, nblocks, sh.lds, s);
     else if (sh.R == 8) launch_batch_shape<S, 8, 0>(args, work, nblocks, sh.lds, s);
+    else if (sh.R > 8) launch_batch_wide<S>(args, work, nblocks, sh, s);
     else if (sh.LP == 2) launch_batch_shape<S, 0, 2>(args, work, nblocks, sh.lds, s);
     else if (sh.LP == 1) launch_batch_shape<S, 0, 1>(args, work, nblocks, sh.lds, s);
     else launch_batch_shape<S, 0, 0>(args, work, nblocks, 0, s);

@@ -94,9 +94,9 @@ def test_c1_coarse_correction_matches_oracle():
 
 
 @pytest.mark.parametrize("nr,ntheta,bar", [(12, 24, 1e-10), (30, 48, 1e-10), (48, 64, 1e-10),
-                                           (60, 100, 1e-10), (4, 1100, 1e-8)])
+                                           (60, 100, 1e-10), (66, 132, 1e-10), (4, 1100, 1e-8)])
 def test_coarse_correction_row_shapes_match_oracle(nr, ntheta, bar):
-    """The FP64 harmonic solves for every register shape of the ELL COCG (1, 2, 4 and 8
+    """The FP64 harmonic solves for every register shape of the ELL COCG (1, 2, 4, 8 and 12
     rows per thread) and for a centre row longer than a workgroup (the per-wave tail
     form), against the oracle's direct per-harmonic solves.  COCG stops at a residual of
     1e-13 relative, so the solution error is that times the condition number: the
@@ -312,3 +312,29 @@ def test_nested_start_matches_oracle():
     e2 = rel(free_rows(U2.cpu().numpy(), fe2.free), g2["U"])
     banner(f"c2 nested: iters {k2} (plain start: 34) rel {e2:.2e}")
     assert e2 <= 1e-10
+
+
+# FP32 register rows beyond 8 per thread (an FP64 mesh of this size does not fit LDS)
+@pytest.mark.parametrize("nr,ntheta,R", [(66, 132, 9), (75, 156, 12)])
+def test_wide_fp32_register_rows_match_oracle(nr, ntheta, R):
+    import torch
+    import paper_1905_13076_amd as P
+    from oracle.fe import FE
+    from oracle import periodic
+    prob = coax.c2(nr=nr, ntheta=ntheta, N=4, m=2)
+    fe = FE(prob)
+    assert (fe.n + 1023) // 1024 == R
+    rng = np.random.default_rng(nr)
+    r = np.hypot(prob.xy[fe.free, 0], prob.xy[fe.free, 1])
+    U0 = np.outer(1.0 + 0.1 * rng.standard_normal(prob.N), 1e-4 * (3e-3 - r) / 3e-3)
+    Fo = periodic.fine_sweep(fe, U0)
+    pr = _problem(prob)
+    prm = P.problem_params(prob, precision=1, fine_block=1024, tol_lin=1e-4)
+    F, newton, lin = pr.fine_sweep(prm, torch.tensor(_nodal(fe, U0), device="cuda"))
+    e = rel(free_rows(F.cpu().numpy(), fe.free), Fo)
+    banner(f"FP32 register rows R={R} ({fe.n} rows) rel={e:.2e}")
+    assert e <= 1e-10
+    # FP64 at this size takes the memory path: forcing register rows is an argument error
+    with pytest.raises(P.PPCError, match="fine_block"):
+        pr.fine_sweep(P.problem_params(prob, precision=0, fine_block=1024),
+                      torch.tensor(_nodal(fe, U0), device="cuda"))
