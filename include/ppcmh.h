@@ -141,7 +141,9 @@ typedef struct {
     int32_t fine_block;     /* register-row fine kernel workgroup: 0 = the size ppc_autotune
                                chose for this problem and precision, else 1024; 256, 512 or
                                1024 = that size (PPC_ERR_ARG when the mesh's rows do not fit:
-                               R rows per thread, R <= 8, R * fine_block >= free nodes) */
+                               R rows per thread with R * fine_block >= free nodes, R a power
+                               of two <= 8 at 256 and 512 threads, R <= 8 at 1024 (<= 12 in
+                               FP32), and p, r and the diagonal in LDS) */
     int32_t n_harm;         /* harmonics each PP-PC correction solves: 0 = all N/2 + 1 (eq.
                                (12)); 1..N/2+1 = p = 0..n_harm-1 only, every other harmonic of
                                the correction being that of the jumps (zero at the fixed point,
