@@ -319,6 +319,7 @@ void fine_batch_prepare(FineBatch& b, const std::vector<ppc_problem*>& parts, co
     const int D = (int)parts.size();
     std::vector<FineArgs> host(D);
     b.shapes.resize(D);
+    b.sizes.clear();
     for (int d = 0; d < D; ++d) {
         ensure_jbase(parts[d], p, s);
         host[d] = make_fine_args(parts[d], p, parts[d]->ws.U, parts[d]->ws.F);
