@@ -282,6 +282,98 @@ def coarse_correction(fe, U, J, shift="ie", lin="tensor", U_lin=None, n_harm=Non
     return harmonic_solve(fe, Kbar, R, T, shift, n_harm=n_harm, Jrows=J)
 
 
+def coarse_rows_times(prob):
+    """End time of row n's coarse step: T_n for n = 1..N-1 and T_N = T for row 0."""
+    t = np.arange(prob.N) * (prob.T / prob.N)
+    t[0] = prob.T
+    return t
+
+
+def coarse_sweep(fe, U, tol=1e-14):
+    """G(U_{n-1}) for every row n (row 0 from U_{N-1}): one implicit-Euler step of size
+    dT = T/N on the nonlinear problem (eq. (8) with the nonlinear stiffness), each solved
+    to tol by the same Newton as a fine step."""
+    prob = fe.prob
+    dT = prob.T / prob.N
+    t = coarse_rows_times(prob)
+    prev = np.roll(U, 1, axis=0)
+    return np.array([ie_step(fe, prev[r], t[r], dT, tol=tol)[0] for r in range(prob.N)])
+
+
+def nonlinear_coarse_residual(fe, W, b):
+    """Phi_n(W) = C (W_n - U_{n-1}) + K(W_n) W_n - f(T_n) with U = W + b, C = M/dT: the
+    implicit-Euler step residual of W_n = G(U_{n-1}) (rows n = 0..N-1, row 0 at T_N)."""
+    prob = fe.prob
+    dT = prob.T / prob.N
+    t = coarse_rows_times(prob)
+    prev = np.roll(W + b, 1, axis=0)
+    return np.array([fe.M @ (W[r] - prev[r]) / dT + fe.K_apply(W[r]) - fe.f(t[r])
+                     for r in range(prob.N)])
+
+
+def nonlinear_coarse_jacobian(fe, W):
+    """d Phi / d W: block-cyclic, C + dK(W_n)W_n/dW_n on the diagonal and -C below it
+    (row 0 couples to row N-1)."""
+    prob = fe.prob
+    N, dT = prob.N, prob.T / prob.N
+    C = (fe.M / dT).tocsr()
+    blocks = [[None] * N for _ in range(N)]
+    for r in range(N):
+        blocks[r][r] = C + fe.jacobian_curl(W[r])
+        blocks[r][(r - 1) % N] = -C
+    return sp.bmat(blocks, format="csc")
+
+
+def nonlinear_coarse_correction(fe, U, Fs, tol=1e-13, max_newton=40):
+    """Delta U of eq. (4) with the nonlinear coarse propagator G of eq. (8) (the coarse
+    problem the paper defers, Section 2 after eq. (10) and Section 5; reading: G_n(v) is
+    one implicit-Euler step of size dT from v to T_n with the full K(u)).
+
+    Eq. (4) reads U^{k+1}_n = G(U^{k+1}_{n-1}) + b_n with b_n = F_n(U^k_{n-1}) - G(U^k_{n-1})
+    cyclically.  With W_n = U^{k+1}_n - b_n = G(U^{k+1}_{n-1}) this is the block-cyclic
+    nonlinear system Phi(W) = 0 of nonlinear_coarse_residual, solved here by Newton's method
+    with the exact Jacobian and a sparse direct solve, from W = G(U^k) (where Phi_n equals
+    -C J_{n-1}), with backtracking on ||Phi||.  Stops when ||Phi|| <= tol * scale, scale =
+    ||C U^k||_F + ||C G(U^k)||_F + ||f||_F, or at the rounding floor of Phi's evaluation (a
+    Newton step at rounding level, or a stalled line search with ||Phi|| <= 1e-9 scale).
+    Returns U^{k+1} - U^k."""
+    prob = fe.prob
+    dT = prob.T / prob.N
+    V = coarse_sweep(fe, U)
+    b = Fs - V
+    W = V.copy()
+    scale = ((np.linalg.norm((fe.M @ U.T).T) + np.linalg.norm((fe.M @ V.T).T)) / dT
+             + np.linalg.norm(np.outer(prob.current(coarse_rows_times(prob)), fe.F)))
+    Phi = nonlinear_coarse_residual(fe, W, b)
+    rn = np.linalg.norm(Phi)
+    for _ in range(max_newton + 1):
+        if rn <= tol * scale:
+            break
+        d = spla.splu(nonlinear_coarse_jacobian(fe, W), permc_spec="MMD_AT_PLUS_A").solve(-Phi.ravel())
+        d = d.reshape(W.shape)
+        if np.linalg.norm(d) <= 4.0 * np.finfo(float).eps * np.linalg.norm(W):
+            W = W + d
+            break
+        lam = 1.0
+        while True:
+            Wt = W + lam * d
+            Pt = nonlinear_coarse_residual(fe, Wt, b)
+            rt = np.linalg.norm(Pt)
+            if rt <= (1.0 - 1e-4 * lam) * rn:
+                break
+            lam *= 0.5
+            if lam < 2.0 ** -20:
+                break
+        if lam < 2.0 ** -20:
+            if rn <= 1e-9 * scale:      # no decrease representable: rounding floor
+                break
+            raise RuntimeError(f"nonlinear coarse problem: line search failed at ||Phi||={rn:.3e}")
+        W, Phi, rn = Wt, Pt, rt
+    else:
+        raise RuntimeError(f"nonlinear coarse problem: no convergence, ||Phi||={rn:.3e}")
+    return W + b - U
+
+
 def brauer_bmax(fe, U):
     """max |B| over the Brauer elements and the samples (rows) of U (0 without steel)."""
     mask = fe.model == BRAUER
@@ -304,11 +396,14 @@ def safeguard_step(fe, U, dU, b_cap):
 
 def ppc(fe, tol=1e-12, max_iter=60, U_init=None, shift="ie", lin="tensor",
         newton_tol=NEWTON_TOL, pool=None, callback=None, init="auto", lin_point="F", b_cap=None,
-        n_harm=None):
+        n_harm=None, coarse="frozen"):
     """Plain PP-PC (eq. (4)).
 
     n_harm < N/2 + 1 solves only the first n_harm harmonics of each correction (the rest
     take the jumps' harmonics; see harmonic_solve).  The initial iterate uses them all.
+
+    coarse="nonlinear" replaces the frozen correction by the one of eq. (4) with the
+    nonlinear coarse propagator (nonlinear_coarse_correction); the fixed point is the same.
 
     lin_point selects the samples the frozen coarse stiffness is linearised at: "U" the
     current iterate U^k, "F" the fine results F^k of the same sweep (they coincide at the
@@ -337,7 +432,11 @@ def ppc(fe, tol=1e-12, max_iter=60, U_init=None, shift="ie", lin="tensor",
             return U, np.array(hist), k
         if k == max_iter:
             break
-        dU = coarse_correction(fe, U, J, shift, lin, U_lin=Fs if lin_point == "F" else None, n_harm=n_harm)
+        if coarse == "nonlinear":
+            dU = nonlinear_coarse_correction(fe, U, Fs)
+        else:
+            dU = coarse_correction(fe, U, J, shift, lin, U_lin=Fs if lin_point == "F" else None,
+                                   n_harm=n_harm)
         U = U + (safeguard_step(fe, U, dU, b_cap) * dU if b_cap else dU)
     raise RuntimeError(f"PP-PC did not converge: eps history {hist[-5:]}")
 

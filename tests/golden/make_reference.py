@@ -9,7 +9,9 @@ Each output ``<name>_oracle.npz`` holds the fixed point U (rows n = 0..N-1, colu
 free nodes in ascending node order), the eps history, the iteration count and the
 generator arguments that define the workload.  Cases ending in ``_ppic`` run PP-IC
 (eq. (5)) instead of PP-PC (c5small from the fine sweep from rest); ``_h3`` runs PP-PC
-solving only the harmonics p = 0, 1, 2 of each correction, ``_nested`` from the nested start; ``_routes`` steps period after
+solving only the harmonics p = 0, 1, 2 of each correction, ``_nested`` from the nested start; ``_nlc`` with
+the nonlinear coarse problem of eq. (4), also storing one of its corrections (U_k, F_k -> dU_k at
+iteration 2); ``_routes`` steps period after
 period from zero (route S), its iteration count being the periods stepped.  ``c4subset``
 holds a seeded subset of the batched-designs generator on a short grid (see C4_SUBSET).
 """
@@ -37,6 +39,7 @@ CASES = {
     "c5small_ppic": (coax.c5_small, {}, 1e-12),
     "c5small_h3": (coax.c5_small, {}, 1e-12),
     "c5small_nested": (coax.c5_small, {}, 1e-12),
+    "c5small_nlc": (coax.c5_small, {}, 1e-12),
     "c2lin_small": (coax.c2lin, dict(nr=20, ntheta=40, N=10, m=20), 1e-12),
     "c2lin_small_ppic": (coax.c2lin, dict(nr=20, ntheta=40, N=10, m=20), 1e-12),
     "c2lin_small_routes": (coax.c2lin, dict(nr=20, ntheta=40, N=10, m=20), 1e-10),
@@ -84,7 +87,11 @@ def make(name, procs):
     t = time.time()
     hist_print = []
 
+    extra = {}
+
     def cb(k, U, Fs, eps):
+        if k == 2 and name.endswith("_nlc"):
+            extra["U_k"], extra["F_k"] = U.copy(), Fs.copy()
         hist_print.append(eps)
         print(f"  [{name}] k={k} eps={eps:.3e} t={time.time() - t:.1f}s", flush=True)
 
@@ -99,6 +106,9 @@ def make(name, procs):
             U, hist, k = periodic.ppic(fe, tol=tol, pool=pool, callback=cb)
         elif name.endswith("_nested"):  # start from the 25 times coarser fine grid's solution
             U, hist, k = periodic.ppc(fe, tol=tol, pool=pool, callback=cb, init="nested")
+        elif name.endswith("_nlc"):     # nonlinear periodic coarse problem
+            U, hist, k = periodic.ppc(fe, tol=tol, pool=pool, callback=cb, coarse="nonlinear")
+            extra["dU_k"] = periodic.nonlinear_coarse_correction(fe, extra["U_k"], extra["F_k"])
         elif name.endswith("_h3"):      # truncated harmonic set: p = 0, 1, 2 solved
             U, hist, k = periodic.ppc(fe, tol=tol, pool=pool, callback=cb, n_harm=3)
         else:
@@ -109,7 +119,7 @@ def make(name, procs):
             pool.join()
     out = os.path.join(HERE, f"{name}_oracle.npz")
     np.savez_compressed(out, U=U, hist=hist, iterations=k, tol=tol,
-                        free=fe.free.astype(np.int32), generator=name)
+                        free=fe.free.astype(np.int32), generator=name, **extra)
     last = f"{hist[-1]:.3e}" if len(hist) else "-"
     print(f"wrote {out}: iterations={k} eps={last} in {time.time() - t:.1f}s")
 

@@ -323,3 +323,65 @@ def test_safeguarded_ppc_reaches_the_unguarded_fixed_point():
     U1, h1, k1 = periodic.ppc(fe, tol=1e-11, init="fine", b_cap=0.75 * bpeak, max_iter=120)
     assert rel(U1, U0) <= 1e-9
     assert k1 > k0
+
+
+# -- nonlinear periodic coarse problem (eq. (4) with the nonlinear G of eq. (8)) -------------
+def _nonlinear_coarse_step(fe, v, t):
+    """One implicit-Euler step of size dT from v to t, by the fine-step Newton."""
+    from oracle.timestep import ie_step
+    return ie_step(fe, v, t, fe.prob.T / fe.prob.N, tol=1e-14)[0]
+
+
+def test_nonlinear_coarse_correction_satisfies_eq4_row_by_row():
+    """The definition: U^{k+1}_n = F_n(U^k_{n-1}) + G(U^{k+1}_{n-1}) - G(U^k_{n-1}) for every
+    n cyclically, with each G evaluated here as a separate coarse step from the new and the
+    old samples (so a wrong row shift, sign or time in the block system fails)."""
+    fe = _tiny_nl(nr=6, ntheta=12, N=6, m=4, amp=500.0)
+    prob = fe.prob
+    U = periodic.initial_iterate(fe, mode="fine")
+    Fs = periodic.fine_sweep(fe, U)
+    U1 = U + periodic.nonlinear_coarse_correction(fe, U, Fs)
+    N, dT = prob.N, prob.T / prob.N
+    assert rel(U1, U) > 1e-3                      # a real correction, not a no-op
+    for n in range(1, N + 1):
+        r = n % N
+        lhs = U1[r]
+        rhs = Fs[r] + _nonlinear_coarse_step(fe, U1[n - 1], n * dT) - _nonlinear_coarse_step(fe, U[n - 1], n * dT)
+        assert np.linalg.norm(lhs - rhs) <= 1e-12 * np.linalg.norm(lhs), n
+
+
+def test_nonlinear_coarse_correction_of_a_linear_problem_is_the_block_cyclic_solve():
+    """Linear materials: G is affine and eq. (4) is the block-cyclic linear system of eq. (9)
+    with Kbar = K, G dU = Q J; solved here with the explicit matrix and a sparse LU."""
+    fe = FE(coax.tiny(nr=5, ntheta=10, N=8, m=3))
+    prob = fe.prob
+    U = periodic.initial_iterate(fe, mode="fine")
+    Fs = periodic.fine_sweep(fe, U)
+    J = Fs - U
+    dT = prob.T / prob.N
+    K = fe.K_matrix(fe.element_state(np.zeros(fe.n))[3])
+    Q = (fe.M / dT + K).tocsr()
+    G = periodic.block_cyclic_G(fe, K, prob.N, prob.T).tocsc()
+    dU_ref = spla.spsolve(G, np.concatenate([Q @ J[r] for r in range(prob.N)])).reshape(U.shape)
+    dU = periodic.nonlinear_coarse_correction(fe, U, Fs)
+    assert rel(dU, dU_ref) <= 1e-10
+
+
+def test_nonlinear_coarse_correction_vanishes_at_the_fixed_point():
+    """F_n(U_{n-1}) = U_n for all n (zero jumps): eq. (4) gives U^{k+1} = U^k."""
+    fe = _tiny_nl(nr=5, ntheta=10, N=6, m=3, amp=400.0)
+    US, _ = periodic.route_s(fe, tol=1e-14)
+    Fs = periodic.fine_sweep(fe, US)
+    assert rel(Fs, US) <= 1e-11
+    dU = periodic.nonlinear_coarse_correction(fe, US, Fs)
+    assert np.linalg.norm(dU) <= 1e-10 * np.linalg.norm(US)
+
+
+def test_ppc_with_the_nonlinear_coarse_problem_keeps_the_fixed_point():
+    """PP-PC with the nonlinear coarse correction reaches the periodic solution of
+    sequential time stepping (saturating sheath, from U^0 = 0)."""
+    fe = _tiny_nl(nr=6, ntheta=12, N=8, m=5, amp=400.0)
+    US, _ = periodic.route_s(fe, tol=1e-14)
+    U, hist, k = periodic.ppc(fe, tol=1e-12, init="zero", coarse="nonlinear")
+    assert rel(U, US) <= 1e-10
+    assert k <= 30 and hist[-1] <= 1e-12
