@@ -72,6 +72,11 @@ def parse():
                          "eq. (5), U_0^{k+1} = U_N^k with sequential coarse propagation; seq: "
                          "classical time stepping from zero, one chain of the fine kernel per "
                          "period, until two periods' samples agree to --tol")
+    ap.add_argument("--coarse", default="frozen", choices=["frozen", "nonlinear"],
+                    help="PP-PC coarse problem: frozen (time-averaged linearisation, one harmonic "
+                         "solve per correction) or nonlinear (eq. (4) with the implicit-Euler "
+                         "coarse step on the full K(u), Newton with GMRES preconditioned by the "
+                         "frozen solve)")
     ap.add_argument("--n-harm", type=int, default=0,
                     help="harmonics each PP-PC correction solves (0: all N/2+1); the others "
                          "take the jumps' harmonics")
@@ -338,7 +343,7 @@ def main():
     if a.probe == "fine":
         return probe_fine(a, prob, ref)
     cpu = None
-    if a.cpu and ref is not None and a.method == "ppc" and a.n_harm == 0:
+    if a.cpu and ref is not None and a.method == "ppc" and a.n_harm == 0 and a.coarse == "frozen":
         # before any GPU initialisation: the oracle's worker pool forks this process
         cpu = cpu_baseline(prob, ref, a.cpu_procs, a.tol)
     import numpy as np
@@ -358,6 +363,7 @@ def main():
     extra["method"] = 1 if a.method == "ppic" else 0
     extra["init_mode"] = {"auto": 0, "rest": 3, "nested": 4}[a.init]
     extra["n_harm"] = a.n_harm
+    extra["coarse_mode"] = 1 if a.coarse == "nonlinear" else 0
     if a.n_harm:
         extra["max_iters"] = 300
     if a.method == "ppic":
@@ -419,6 +425,7 @@ def main():
             "precision": a.precision,
             "method": a.method,
             "harmonics_solved": a.n_harm or prob.N // 2 + 1,
+            "coarse": a.coarse,
             "init": a.init,
             "tol_ppc": a.tol,
             "tol_cocg": a.tol_cocg,
@@ -430,6 +437,8 @@ def main():
             "pcg_per_newton": tot["lin_total"] / max(1, tot["newton_total"]),
             "cocg_total_per_state": sum(s["cocg_total"] for s in stats) / a.steps,
             "coarse_solves_per_state": sum(s["coarse_solves"] for s in stats) / a.steps,
+            "coarse_newton_per_state": sum(s["coarse_newton"] for s in stats) / a.steps,
+            "coarse_ms_per_state": sum(s["coarse_ms"] for s in stats) / a.steps,
             "fine_ms_per_state": fine_ms / a.steps,
             "coarse_ms_per_state": sum(s["coarse_ms"] for s in stats) / a.steps,
             "setup_s": setup_s,

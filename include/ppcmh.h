@@ -31,7 +31,7 @@
 extern "C" {
 #endif
 
-#define PPC_ABI_VERSION 1
+#define PPC_ABI_VERSION 2
 
 /* status codes */
 #define PPC_OK 0
@@ -153,6 +153,14 @@ typedef struct {
                                U += theta dU with the largest theta <= 1 that keeps |B| <= b_cap
                                in every Brauer element and sample, when the full correction
                                would exceed it (a frozen linear coarse model cannot saturate) */
+    int32_t coarse_mode;    /* PP-PC coarse problem: 0 = frozen (the time-averaged
+                               linearisation Kbar, one harmonic solve per correction); 1 =
+                               nonlinear: eq. (4) with G the implicit-Euler step of size dT on
+                               the full K(u) (eq. (8)), a block-cyclic nonlinear system solved
+                               by Newton's method to ||Phi|| <= max(tol_cocg ||Phi_0||,
+                               1e-14 ||C F||_F), each Newton step by flexible GMRES (at most 30
+                               vectors) preconditioned by the frozen harmonic solve.  Not with
+                               method 1, n_harm or b_cap; not for batched problems */
 } ppc_params;
 
 /* Counters and timings of the last solve (all chains, all iterations). */
@@ -178,6 +186,8 @@ typedef struct {
     int32_t n_free, nnz, n_tri, damped;   /* damped: corrections the b_cap safeguard scaled */
     int64_t resid_total;         /* residual evaluations (element + node passes) */
     int64_t steps_total;         /* implicit-Euler steps taken over every chain */
+    int32_t coarse_newton;       /* coarse_mode 1: Newton iterations of the coarse problems */
+    int32_t coarse_krylov;       /* coarse_mode 1: GMRES iterations (= harmonic-solve sets) */
 } ppc_stats;
 
 /* ABI version (PPC_ABI_VERSION). */

@@ -52,7 +52,7 @@ class Params(ctypes.Structure):
                 ("tol_cocg", c_double), ("max_cocg", c_int32), ("block", c_int32),
                 ("no_predictor", c_int32), ("lin_point", c_int32), ("coarse_precision", c_int32),
                 ("graph", c_int32), ("method", c_int32), ("fine_block", c_int32), ("n_harm", c_int32),
-                ("b_cap", c_double)]
+                ("b_cap", c_double), ("coarse_mode", c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -63,7 +63,8 @@ class Stats(ctypes.Structure):
                 ("coarse_ms", c_double), ("total_ms", c_double), ("jump", c_double),
                 ("eps", c_double), ("max_b_steel", c_double), ("n_free", c_int32),
                 ("nnz", c_int32), ("n_tri", c_int32), ("damped", c_int32),
-                ("resid_total", c_int64), ("steps_total", c_int64)]
+                ("resid_total", c_int64), ("steps_total", c_int64),
+                ("coarse_newton", c_int32), ("coarse_krylov", c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -90,12 +90,14 @@ float elapsed(hipEvent_t a, hipEvent_t b) {
 
 void workspace_free(Workspace& w) {
     void* ptrs[] = {w.fvec, w.fpcg, w.fjac, w.felem, w.jbase, w.ckm, w.fcount, w.U, w.F, w.J, w.R, w.kbar, w.kbar32,
-                    w.nubar, w.rhat, w.cwork, w.sig, w.ccount, w.twiddle, w.partial, w.scal, w.ic_e, w.ic_un};
+                    w.nubar, w.rhat, w.cwork, w.sig, w.ccount, w.twiddle, w.partial, w.scal, w.ic_e, w.ic_un,
+                    w.nlc_jb, w.nlc_jac, w.nlc_vec, w.nlc_kry, w.nlc_part, w.nlc_h};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (w.host_scal) (void)hipHostFree(w.host_scal);
     if (w.host_fcount) (void)hipHostFree(w.host_fcount);
     if (w.host_ccount) (void)hipHostFree(w.host_ccount);
+    if (w.nlc_host) (void)hipHostFree(w.nlc_host);
     w = Workspace{};
 }
 
@@ -299,6 +301,7 @@ ppc_params nested_params(const ppc_params* p) {
     q.tol_newton = std::max(p->tol_newton, 1e-8);
     q.tol_cocg = std::max(p->tol_cocg, 1e-4);
     q.init_mode = p->b_cap > 0.0 ? 3 : 0;
+    q.coarse_mode = 0;
     return q;
 }
 
@@ -390,8 +393,15 @@ int solve_device(ppc_handle* h, ppc_problem* pr, const ppc_params* p, const doub
         PPC_HIP(hipMemcpyAsync(w.host_scal, w.scal, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
         PPC_HIP(hipMemcpyAsync(w.host_fcount, w.fcount, 8 * (size_t)N * sizeof(int), hipMemcpyDeviceToHost, s));
     };
+    const bool nlc = p->coarse_mode == 1;
+    NlcCounts nc;
     auto coarse_ops = [&]() {
         const double* lin = p->lin_point == 1 ? w.F : w.U;
+        if (nlc) {
+            // nonlinear coarse problem: host-driven Newton-Krylov, never captured
+            launch_nonlinear_correction(pr, p, w.U, w.F, w.U, true, nc, nullptr, s);
+            return;
+        }
         if (ic) {
             launch_ic_propagation(pr, p, s);
         } else if (p->b_cap > 0.0) {
@@ -443,13 +453,24 @@ int solve_device(ppc_handle* h, ppc_problem* pr, const ppc_params* p, const doub
         }
         if (k == p->max_iters) break;
         PPC_HIP(hipEventRecord(ev[2], s));
-        run(g_coarse, k, coarse_ops);
+        if (nlc)
+            coarse_ops();
+        else
+            run(g_coarse, k, coarse_ops);
         PPC_HIP(hipEventRecord(ev[3], s));
         PPC_HIP(hipStreamSynchronize(s));
-        parse_cocg(w.host_ccount, n_solves, nullptr, &S.cocg_total, &S.cocg_max);
+        if (!nlc) parse_cocg(w.host_ccount, n_solves, nullptr, &S.cocg_total, &S.cocg_max);
         if (!ic && p->b_cap > 0.0 && w.host_scal[8] < 1.0) S.damped++;
         S.coarse_ms += elapsed(ev[2], ev[3]);
-        S.coarse_solves += ic ? N : 1;
+        S.coarse_solves += ic ? N : (nlc ? 0 : 1);
+    }
+    if (nlc) {
+        // one harmonic-solve launch per GMRES iteration
+        S.cocg_total += nc.cocg_total;
+        S.cocg_max = std::max(S.cocg_max, nc.cocg_max);
+        S.coarse_solves += nc.krylov;
+        S.coarse_newton = nc.newton;
+        S.coarse_krylov = nc.krylov;
     }
     S.iterations = std::min(k, p->max_iters);
     if (U_out_dev) launch_to_nodal(pr, N, w.U, U_out_dev, s);
@@ -497,6 +518,7 @@ int solve_batch_device(ppc_handle* h, ppc_problem* bp, const ppc_params* p, cons
                        hipStream_t s) {
     PPC_HIP(hipSetDevice(h->device));
     if (p->method != 0) fail(PPC_ERR_ARG, "PP-IC (method 1) runs single-design problems only");
+    if (p->coarse_mode != 0) fail(PPC_ERR_ARG, "the nonlinear coarse problem (coarse_mode 1) runs single-design problems only");
     auto& parts = bp->parts;
     const int D = (int)parts.size();
     const int N = p->N, H = N / 2 + 1, R1 = p->max_iters + 1;
@@ -1010,6 +1032,7 @@ int ppc_params_default(ppc_params* p) {
     p->graph = 1;
     p->method = 0;
     p->b_cap = 0.0;
+    p->coarse_mode = 0;
     return PPC_OK;
 }
 
@@ -1389,6 +1412,18 @@ int ppc_coarse_correction_device(ppc_handle* h, ppc_problem* pr, const ppc_param
         ensure_workspace(pr, p);
         launch_to_free(pr, p->N, U_dev, pr->ws.U, s);
         launch_to_free(pr, p->N, J_dev, pr->ws.J, s);
+        if (p->coarse_mode == 1) {
+            // F = U + J, then the nonlinear correction (U^{k+1} - U^k) into R
+            Workspace& w = pr->ws;
+            const long L = (long)p->N * pr->mesh.n_free;
+            PPC_HIP(hipMemcpyAsync(w.F, w.U, sizeof(double) * L, hipMemcpyDeviceToDevice, s));
+            launch_vec_add(L, w.J, w.F, s);
+            NlcCounts nc;
+            launch_nonlinear_correction(pr, p, w.U, w.F, w.R, false, nc, cocg_out, s);
+            launch_to_nodal(pr, p->N, w.R, dU_dev, s);
+            PPC_HIP(hipStreamSynchronize(s));
+            return PPC_OK;
+        }
         launch_coarse(pr, p, pr->ws.U, pr->ws.J, pr->ws.F, false, false, s);
         const int Hs = solved_harmonics(p, false);
         read_cocg(pr, Hs, s, cocg_out, nullptr, nullptr);

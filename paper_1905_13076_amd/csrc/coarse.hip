@@ -1200,6 +1200,23 @@ void launch_coarse(ppc_problem* pr, const ppc_params* p, const double* U, const 
     launch_coarse_post(pr, p, dU, accumulate, s);
 }
 
+void launch_coarse_setup(ppc_problem* pr, const ppc_params* p, const double* Ulin, hipStream_t s) {
+    const int N = p->N, H = N / 2 + 1;
+    launch_linearisation(pr, p, Ulin, s);
+    hipLaunchKernelGGL(k_twiddle, dim3((N + 255) / 256), dim3(256), 0, s, N, pr->ws.twiddle);
+    hipLaunchKernelGGL(k_shifts, dim3((H + 63) / 64), dim3(64), 0, s, N, p->T, p->shift_mode, pr->ws.sig);
+    PPC_HIP(hipGetLastError());
+}
+
+void launch_coarse_apply(ppc_problem* pr, const ppc_params* p, const double* r, double* z, hipStream_t s) {
+    const int n = pr->mesh.n_free, N = p->N, H = N / 2 + 1;
+    hipLaunchKernelGGL(k_dft, dim3((n + 255) / 256, H), dim3(256), 0, s, n, N, 0, r, pr->ws.twiddle, pr->ws.rhat);
+    CocgArgs a = make_cocg_args(pr, p);
+    a.H = H;
+    launch_cocg_solves(pr, a, s);
+    launch_coarse_post(pr, p, z, false, s);
+}
+
 void launch_ic_propagation(ppc_problem* pr, const ppc_params* p, hipStream_t s) {
     const DeviceMesh& d = pr->mesh;
     Workspace& w = pr->ws;

@@ -148,10 +148,22 @@ struct Workspace {
     double* host_scal = nullptr; // pinned host mirror
     int* host_fcount = nullptr;  // pinned [N][8] chain counters of the last sweep
     int* host_ccount = nullptr;  // pinned [N][4] coarse-solve counters
+    // nonlinear periodic coarse problem (allocated on first use; layouts [N][n_free])
+    double* nlc_jb = nullptr;    // [vals_pad] base Jacobian M/dT + linear elements
+    double* nlc_jac = nullptr;   // [N][vals_pad] Jacobian of each row's coarse step
+    double* nlc_vec = nullptr;   // [kNlcVec][N][n_free]: G(U^k), b, W, W trial, U, Phi, delta
+    double* nlc_kry = nullptr;   // [2 kNlcKrylov + 1][N][n_free] Krylov basis V, then Z
+    double* nlc_part = nullptr;  // reduction partials
+    double* nlc_h = nullptr;     // [4][kNlcKrylov + 1] dot products and coefficients
+    double* nlc_host = nullptr;  // pinned host mirror of nlc_h
     size_t n_pad = 0, nnz_pad = 0, ne_pad = 0, vals_pad = 0, nl_pad = 0;
 };
 
 void workspace_free(Workspace& w);
+
+// nonlinear coarse problem: work vectors and the Krylov space of one Newton step
+constexpr int kNlcVec = 7;
+constexpr int kNlcKrylov = 30;
 
 }  // namespace ppc
 
@@ -416,5 +428,30 @@ void launch_to_free(const ppc_problem* pr, int N, const double* Unodal, double* 
 void launch_safeguarded_update(ppc_problem* pr, int N, double cap, const double* dU, double* U,
                                double* out3, hipStream_t s);
 void launch_max_b(ppc_problem* pr, int N, const double* U, double* out, hipStream_t s);
+
+// The frozen block-cyclic coarse solve as an operator: set-up (Kbar at the samples Ulin,
+// twiddles, shifts), then z = G^{-1} r over all N/2 + 1 harmonics (G of eq. (9) with Kbar;
+// counters of harmonic p in ccount row p).
+void launch_coarse_setup(ppc_problem* pr, const ppc_params* p, const double* Ulin, hipStream_t s);
+void launch_coarse_apply(ppc_problem* pr, const ppc_params* p, const double* r, double* z, hipStream_t s);
+
+// One implicit-Euler step of size dT = T/N from every sample: G[(c + 1) mod N] = G(U[c]),
+// the nonlinear coarse propagator of eq. (8), by the fine-sweep kernel with m = 1 and the
+// base Jacobian jb rebuilt for dT.
+void launch_coarse_step_sweep(ppc_problem* pr, const ppc_params* p, const double* U, double* G,
+                              double* jb, hipStream_t s);
+
+// Nonlinear periodic coarse correction (eq. (4) with the nonlinear G of eq. (8)); see
+// nlcoarse.hip.  out = U^{k+1} (accumulate, out may be U) or U^{k+1} - U^k.
+struct NlcCounts {
+    int newton = 0, krylov = 0;
+    int64_t cocg_total = 0, step_newton = 0;
+    int cocg_max = 0;
+};
+void launch_nonlinear_correction(ppc_problem* pr, const ppc_params* p, const double* U, const double* F,
+                                 double* out, bool accumulate, NlcCounts& cnt, int32_t* cocg_out,
+                                 hipStream_t s);
+// y += x over L values
+void launch_vec_add(long L, const double* x, double* y, hipStream_t s);
 
 }  // namespace ppc

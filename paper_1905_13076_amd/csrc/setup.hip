@@ -144,6 +144,14 @@ int validate_params(const ppc_params* p, std::string& msg) {
         return PPC_ERR_ARG;
     }
     if (!(p->b_cap >= 0.0) || !std::isfinite(p->b_cap)) { msg = "b_cap must be finite and >= 0"; return PPC_ERR_ARG; }
+    if (p->coarse_mode < 0 || p->coarse_mode > 1) {
+        msg = "coarse_mode must be 0 (frozen) or 1 (nonlinear)";
+        return PPC_ERR_ARG;
+    }
+    if (p->coarse_mode == 1 && (p->method != 0 || p->n_harm != 0 || p->b_cap > 0.0)) {
+        msg = "coarse_mode 1 applies to PP-PC with all harmonics and without b_cap";
+        return PPC_ERR_ARG;
+    }
     if (p->coarse_precision < -1 || p->coarse_precision > 1) {
         msg = "coarse_precision must be -1, 0 or 1";
         return PPC_ERR_ARG;

@@ -36,7 +36,7 @@ def test_library_exports_every_declared_function():
     out = subprocess.run(["nm", "-D", "--defined-only", nat.LIB_PATH], capture_output=True, text=True).stdout
     exported = set(re.findall(r"\bT (ppc_\w+)", out))
     assert set(names) <= exported
-    assert lib.ppc_version() == 1
+    assert lib.ppc_version() == 2
 
 
 def test_struct_layout_matches_binding(tmp_path):
@@ -141,6 +141,9 @@ def test_invalid_problems_are_rejected_on_host(case, code, needle):
     (dict(method=1, b_cap=3.0), "b_cap"), (dict(fine_block=128), "fine_block"),
     (dict(fine_block=512, block=1024), "fine_block"), (dict(n_harm=7), "n_harm"),
     (dict(n_harm=-1), "n_harm"), (dict(method=1, n_harm=3), "n_harm"),
+    (dict(coarse_mode=2), "coarse_mode"), (dict(coarse_mode=-1), "coarse_mode"),
+    (dict(coarse_mode=1, method=1), "coarse_mode"), (dict(coarse_mode=1, n_harm=3), "coarse_mode"),
+    (dict(coarse_mode=1, b_cap=3.0), "coarse_mode"),
 ])
 def test_invalid_params_are_rejected_on_host(kw, needle):
     import paper_1905_13076_amd as P
