@@ -350,8 +350,11 @@ int ppc_fine_counts(const ppc_problem* pr, int32_t n_chains, int32_t* counts);
  * samples U and jumps J (DEVICE [N * n_nodes]; J[n] = F_n - U_n mod N) compute
  * dU (DEVICE [N * n_nodes]) solving Q dU_n - C dU_{n-1} = Q J_n cyclically, with
  * C = M/dT, Q = C + Kbar(U) (eq. (10)).  With params->n_harm the harmonics from n_harm
- * on are those of J instead.  cocg_out: host [N/2 + 1] or null (COCG iterations per
- * harmonic; 0 for the harmonics not solved). */
+ * on are those of J instead.  With params->coarse_mode = 1, dU = U^{k+1} - U^k of eq. (4)
+ * with the nonlinear coarse step instead, F = U + J being the fine results (host-driven
+ * Newton-GMRES; synchronises once per Krylov step).  cocg_out: host [N/2 + 1] or null (COCG
+ * iterations per harmonic, summed over the Krylov steps in coarse_mode 1; 0 for the
+ * harmonics not solved). */
 int ppc_coarse_correction_device(ppc_handle* h, ppc_problem* pr, const ppc_params* p,
                                  const double* U_dev, const double* J_dev, double* dU_dev,
                                  int32_t* cocg_out, void* stream);
