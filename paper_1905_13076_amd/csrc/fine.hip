@@ -207,26 +207,6 @@ void launch_fine_sweep(ppc_problem* pr, const ppc_params* p, const double* U, do
     PPC_HIP(hipGetLastError());
 }
 
-void launch_coarse_step_sweep(ppc_problem* pr, const ppc_params* p, const double* U, double* G,
-                              double* jb, hipStream_t s) {
-    const DeviceMesh& d = pr->mesh;
-    ppc_params q = *p;
-    q.m = 1;
-    q.no_predictor = 1;
-    const double dT = p->T / p->N;
-    const int nb = std::max(1, std::min((d.n_vals + 255) / 256, 4096));
-    hipLaunchKernelGGL(k_jbase, dim3(nb), dim3(256), 0, s, d.n_vals, d.n_tri, d.vslot, d.slot_ptr, d.slot_src,
-                       d.mat, pr->lawtab, d.k0, d.mval, 1.0 / dT, jb);
-    FineArgs a = make_fine_args(pr, &q, U, G);
-    a.jbase = jb;
-    const FineShape sh = fine_shape(pr, &q);
-    if (q.precision == 0)
-        launch_typed<double>(a, q.N, sh, s);
-    else
-        launch_typed<float>(a, q.N, sh, s);
-    PPC_HIP(hipGetLastError());
-}
-
 void launch_fine_sweep_traj(ppc_problem* pr, const ppc_params* p, const double* U, double* F,
                             double* traj, hipStream_t s) {
     ensure_jbase(pr, p, s);

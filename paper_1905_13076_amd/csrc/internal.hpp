@@ -150,6 +150,7 @@ struct Workspace {
     int* host_ccount = nullptr;  // pinned [N][4] coarse-solve counters
     // nonlinear periodic coarse problem (allocated on first use; layouts [N][n_free])
     double* nlc_jb = nullptr;    // [vals_pad] base Jacobian M/dT + linear elements
+    double nlc_jb_dt = 0.0;      // step the nlc_jb was built for (0: none)
     double* nlc_jac = nullptr;   // [N][vals_pad] Jacobian of each row's coarse step
     double* nlc_vec = nullptr;   // [kNlcVec][N][n_free]: G(U^k), b, W, W trial, U, Phi, delta
     double* nlc_kry = nullptr;   // [2 kNlcKrylov + 1][N][n_free] Krylov basis V, then Z
@@ -434,12 +435,6 @@ void launch_max_b(ppc_problem* pr, int N, const double* U, double* out, hipStrea
 // counters of harmonic p in ccount row p).
 void launch_coarse_setup(ppc_problem* pr, const ppc_params* p, const double* Ulin, hipStream_t s);
 void launch_coarse_apply(ppc_problem* pr, const ppc_params* p, const double* r, double* z, hipStream_t s);
-
-// One implicit-Euler step of size dT = T/N from every sample: G[(c + 1) mod N] = G(U[c]),
-// the nonlinear coarse propagator of eq. (8), by the fine-sweep kernel with m = 1 and the
-// base Jacobian jb rebuilt for dT.
-void launch_coarse_step_sweep(ppc_problem* pr, const ppc_params* p, const double* U, double* G,
-                              double* jb, hipStream_t s);
 
 // Nonlinear periodic coarse correction (eq. (4) with the nonlinear G of eq. (8)); see
 // nlcoarse.hip.  out = U^{k+1} (accumulate, out may be U) or U^{k+1} - U^k.

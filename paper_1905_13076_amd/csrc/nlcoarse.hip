@@ -142,11 +142,37 @@ __global__ void k_nlc_finish(long L, const double* __restrict__ W, const double*
         out[k] = accumulate ? W[k] + b[k] : (W[k] + b[k]) - U[k];
 }
 
+// One implicit-Euler step of size dT = T/N from every sample, G[(c + 1) mod N] = G(U[c]) (the
+// coarse propagator of eq. (8) on the full K(u)): the fine sweep with m = 1 and no predictor.
+// For its duration the workspace's base Jacobian is the coarse one (nlc_jb, built for dT when
+// needed), so the fine sweep's own base Jacobian stays as it is.
+void coarse_step_sweep(ppc_problem* pr, const ppc_params* p, const double* U, double* G, hipStream_t s) {
+    struct Swap {
+        Workspace& w;
+        explicit Swap(Workspace& w_) : w(w_) { flip(); }
+        ~Swap() { flip(); }
+        void flip() {
+            std::swap(w.jbase, w.nlc_jb);
+            std::swap(w.jbase_dt, w.nlc_jb_dt);
+        }
+    } swap(pr->ws);
+    ppc_params q = *p;
+    q.m = 1;
+    q.no_predictor = 1;
+    launch_fine_sweep(pr, &q, U, G, s);
+}
+
 dim3 vec_grid(long L) { return dim3((unsigned)std::max(1L, std::min((L + 255) / 256, 4096L))); }
 
 void ensure_nlc(ppc_problem* pr, const ppc_params* p) {
     Workspace& w = pr->ws;
-    if (w.nlc_jb) return;
+    if (w.nlc_host) return;                 // allocated last: the set is complete
+    for (double** ptr : {&w.nlc_jb, &w.nlc_jac, &w.nlc_vec, &w.nlc_kry, &w.nlc_part, &w.nlc_h})
+        if (*ptr) {                         // a set left partial by an allocation failure
+            (void)hipFree(*ptr);
+            *ptr = nullptr;
+        }
+    w.nlc_jb_dt = 0.0;
     const size_t L = (size_t)p->N * pr->mesh.n_free;
     auto alloc = [](double** ptr, size_t count) {
         if (hipMalloc(reinterpret_cast<void**>(ptr), std::max<size_t>(count, 1) * sizeof(double)) != hipSuccess)
@@ -196,7 +222,7 @@ void launch_nonlinear_correction(ppc_problem* pr, const ppc_params* p, const dou
         for (int q = 0; q < H; ++q) cocg_out[q] = 0;
 
     // G(U^k) and b = F - G(U^k); W starts at G(U^k)
-    launch_coarse_step_sweep(pr, p, U, G, w.nlc_jb, s);
+    coarse_step_sweep(pr, p, U, G, s);
     PPC_HIP(hipMemcpyAsync(w.host_fcount, w.fcount, 8 * (size_t)N * sizeof(int), hipMemcpyDeviceToHost, s));
     PPC_HIP(hipStreamSynchronize(s));
     for (int c = 0; c < N; ++c) {
