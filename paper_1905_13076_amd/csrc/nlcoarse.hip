@@ -254,9 +254,8 @@ void launch_nonlinear_correction(ppc_problem* pr, const ppc_params* p, const dou
         PPC_HIP(hipStreamSynchronize(s));
         h2[0] = w.nlc_host[0];
         h2[1] = w.nlc_host[1];
-        if (!std::isfinite(h2[0])) fail(PPC_ERR_NONFINITE, "non-finite residual in the nonlinear coarse problem");
         if (scale_c == 0.0) scale_c = std::sqrt(h2[1]);
-        return std::sqrt(h2[0]);
+        return std::sqrt(h2[0]);    // +inf or NaN when the state overflows the B-H law
     };
     // the dot products V_j . x for j < nv into hd + off (device)
     auto dots = [&](const double* Vb, int nv, const double* x, int off) {
@@ -265,6 +264,7 @@ void launch_nonlinear_correction(ppc_problem* pr, const ppc_params* p, const dou
     };
 
     double rn = residual(Wc);
+    if (!std::isfinite(rn)) fail(PPC_ERR_NONFINITE, "non-finite residual in the nonlinear coarse problem");
     const double rn0 = rn;
     const double target = std::max(p->tol_cocg * rn0, 1e-14 * scale_c);
     std::vector<double> Hm((size_t)K1 * kNlcKrylov), g(K1), cs(kNlcKrylov), sn(kNlcKrylov), y(kNlcKrylov);
@@ -337,7 +337,7 @@ void launch_nonlinear_correction(ppc_problem* pr, const ppc_params* p, const dou
         while (lam >= std::ldexp(1.0, -20)) {
             hipLaunchKernelGGL(k_nlc_axpby, vg, dim3(256), 0, s, L, 1.0, Wc, lam, D, Wt);
             rt = residual(Wt);
-            if (rt <= (1.0 - 1e-4 * lam) * rn) {
+            if (std::isfinite(rt) && rt <= (1.0 - 1e-4 * lam) * rn) {   // a non-finite trial is a rejected one
                 accepted = true;
                 break;
             }
