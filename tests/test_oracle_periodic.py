@@ -385,3 +385,30 @@ def test_ppc_with_the_nonlinear_coarse_problem_keeps_the_fixed_point():
     U, hist, k = periodic.ppc(fe, tol=1e-12, init="zero", coarse="nonlinear")
     assert rel(U, US) <= 1e-10
     assert k <= 30 and hist[-1] <= 1e-12
+
+
+def test_nonlinear_coarse_jacobian_matches_central_differences():
+    """The block-cyclic Jacobian of Phi against central differences of Phi itself, on a
+    saturating state with the coupling to the previous row in every block row (a misplaced
+    or transposed -C block, or a missing differential term, fails)."""
+    fe = _tiny_nl(nr=5, ntheta=10, N=4, m=3, amp=600.0)
+    prob = fe.prob
+    rng = np.random.default_rng(3)
+    US, _ = periodic.route_s(fe, tol=1e-12)
+    W = US * (1.0 + 0.3 * rng.standard_normal(US.shape))
+    b = 0.05 * rng.standard_normal(US.shape) * np.abs(US).max()
+    _, _, b2, _, _ = fe.element_state(W[1])
+    assert math.sqrt(b2.max()) > 1.0               # the Brauer law is in its nonlinear range
+    Jm = periodic.nonlinear_coarse_jacobian(fe, W)
+    v = rng.standard_normal(W.shape)
+    h = 1e-6 * np.linalg.norm(W) / np.linalg.norm(v)
+    fd = (periodic.nonlinear_coarse_residual(fe, W + h * v, b)
+          - periodic.nonlinear_coarse_residual(fe, W - h * v, b)) / (2.0 * h)
+    Jv = (Jm @ v.ravel()).reshape(W.shape)
+    assert rel(Jv, fd) <= 1e-6
+    # the coupling: row n depends on W_{n-1} through -C only
+    e = np.zeros_like(W)
+    e[prob.N - 1] = v[prob.N - 1]
+    Je = (Jm @ e.ravel()).reshape(W.shape)
+    C = fe.M / (prob.T / prob.N)
+    assert rel(Je[0], -(C @ v[prob.N - 1])) <= 1e-12
