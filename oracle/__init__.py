@@ -15,5 +15,8 @@ Parity status per function: every function is pinned by a CPU test against a
 closed form, an invariant, a special case or brute force, except the iteration
 *histories* of the nonlinear frozen-linearisation coarse rule (``ppc`` on a
 nonlinear problem), whose fixed point is pinned but whose per-iteration residuals
-are "parity unpinned" by the paper (it defers the nonlinear coarse treatment).
+are "parity unpinned" by the paper (it defers the nonlinear coarse treatment).  The
+alternative nonlinear coarse correction (``nonlinear_coarse_correction``) is pinned
+correction by correction: against eq. (4) evaluated row by row with separate coarse
+steps, and through its Jacobian against central differences.
 """
