@@ -70,3 +70,51 @@ def test_gradients_match_central_differences(nonlinear):
             assert abs(fd - dk[mid, i]) <= 1e-5 * abs(fd), (i, fd, dk[mid, i])
     else:
         assert np.all(dk == 0.0)
+
+
+def _c1_loss(m):
+    """Loss of the C1 periodic implicit-Euler solution with m steps per subinterval
+    (route L: the exact DFT solve of the cyclic fine system)."""
+    fe = FE(coax.c1(m=m))
+    _, u = periodic.route_l(fe)                 # rows j = 0..L-1, u_0 = u_L
+    return fe, u, adjoint.loss(fe, np.vstack([u, u[:1]]))
+
+
+def test_loss_equals_the_energy_balance_of_the_periodic_solution():
+    """Independent value of P from the source and the stiffness instead of the mass:
+    multiplying the periodic implicit-Euler equations (Section 2, eq. (1) in time) by
+    du_j and summing over a period telescopes the stored energy, so
+    T P = sum_j f_j.du_j - 1/2 sum_j du_j.K du_j.  A factor 2, a missing 1/T or dt in
+    place of 1/dt in the loss fails here."""
+    fe, u, P = _c1_loss(20)
+    prob = fe.prob
+    L = prob.N * prob.m
+    dt = prob.T / L
+    K = fe.K_matrix(np.full(prob.n_tri, coax.NU0))
+    du = u - np.roll(u, 1, axis=0)
+    t = np.arange(L) * dt
+    t[0] = prob.T
+    f = np.outer(prob.current(t), fe.F)
+    PT = (np.sum(f * du) - 0.5 * np.sum(du * (K @ du.T).T)) / prob.T
+    assert abs(P - PT) <= 1e-10 * abs(PT), (P, PT)
+
+
+def test_loss_converges_to_the_phasor_loss_at_first_order():
+    """Physics pin: for a linear problem driven by I sin(wt), the space-discrete periodic
+    solution is A(t) = Im(Ah e^{iwt}) with (K + iwM) Ah = I F, and the period average of
+    dA/dt^T M dA/dt is w^2/2 Re(Ah^H M Ah).  Implicit Euler is first order, so the
+    relative error of P halves with every halving of dt, and the Richardson value
+    2 P(dt/2) - P(dt) is second-order accurate."""
+    import math
+    import scipy.sparse.linalg as spla
+    fe, _, _ = _c1_loss(20)
+    prob = fe.prob
+    w = 2.0 * math.pi * prob.f0 * prob.orders[0]
+    K = fe.K_matrix(np.full(prob.n_tri, coax.NU0))
+    Ah = spla.splu((K + 1j * w * fe.M).tocsc()).solve(prob.amps[0] * fe.F.astype(np.complex128))
+    Pph = 0.5 * w * w * float(np.real(np.vdot(Ah, fe.M @ Ah)))
+    P = {m: _c1_loss(m)[2] for m in (20, 40, 80)}
+    e = {m: P[m] / Pph - 1.0 for m in P}
+    assert abs(e[20]) <= 0.05 * w * (prob.T / (prob.N * 20))     # O(w dt), small constant
+    assert 1.8 <= e[20] / e[40] <= 2.3 and 1.8 <= e[40] / e[80] <= 2.3, e
+    assert abs(2.0 * P[80] - P[40] - Pph) <= 2e-5 * Pph, (P, Pph)
