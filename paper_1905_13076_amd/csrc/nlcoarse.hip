@@ -270,6 +270,7 @@ void launch_nonlinear_correction(ppc_problem* pr, const ppc_params* p, const dou
     std::vector<double> Hm((size_t)K1 * kNlcKrylov), g(K1), cs(kNlcKrylov), sn(kNlcKrylov), y(kNlcKrylov);
     std::vector<double> hh(4 * K1);
     constexpr int kMaxNewton = 30;
+    bool at_floor = false;
     for (int it = 0; it < kMaxNewton && rn > target; ++it) {
         // flexible GMRES on Jac d = -Phi from d = 0, right-preconditioned by the frozen solve
         const double gm_target = std::max(1e-3 * rn, 0.5 * target);
@@ -294,6 +295,15 @@ void launch_nonlinear_correction(ppc_problem* pr, const ppc_params* p, const dou
             PPC_HIP(hipMemcpyAsync(w.nlc_host, hd, 3 * K1 * sizeof(double), hipMemcpyDeviceToHost, s));
             PPC_HIP(hipStreamSynchronize(s));
             std::copy(w.nlc_host, w.nlc_host + 3 * K1, hh.begin());
+            // a breakdown or a non-finite residual in a harmonic solve of the preconditioner
+            // would carry NaN into the Krylov basis: report it as the frozen correction does
+            for (int q = 0; q < H; ++q) {
+                const int st = w.host_ccount[4 * q];
+                if (st != 0)
+                    fail(st, std::string(st == PPC_ERR_BREAKDOWN ? "COCG breakdown" : "non-finite COCG residual") +
+                                 " in harmonic " + std::to_string(q) +
+                                 " of the nonlinear coarse problem's preconditioner");
+            }
             for (int q = 0; q < H; ++q) {
                 const int its = w.host_ccount[4 * q + 1];
                 cnt.cocg_total += its;
@@ -345,12 +355,19 @@ void launch_nonlinear_correction(ppc_problem* pr, const ppc_params* p, const dou
         }
         cnt.newton++;
         if (!accepted) {
-            if (rn <= 1e-11 * scale_c) break;    // no decrease representable: rounding floor
+            if (rn <= 1e-11 * scale_c) {        // no decrease representable: rounding floor
+                at_floor = true;
+                break;
+            }
             fail(PPC_ERR_NEWTON, "nonlinear coarse problem: line search failed");
         }
         std::swap(Wc, Wt);
         rn = rt;
     }
+    if (rn > target && !at_floor)
+        fail(PPC_ERR_NEWTON, "nonlinear coarse problem: no convergence in " + std::to_string(kMaxNewton) +
+                                 " Newton steps (||Phi|| = " + std::to_string(rn) + ", target " +
+                                 std::to_string(target) + ")");
     hipLaunchKernelGGL(k_nlc_finish, vg, dim3(256), 0, s, L, Wc, B, U, out, accumulate ? 1 : 0);
     PPC_HIP(hipGetLastError());
 }

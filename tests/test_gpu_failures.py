@@ -66,3 +66,27 @@ def test_failing_design_in_a_batch_is_named():
     banner(f"batch: {ei.value}")
     assert ei.value.code == -7 and "design 1" in str(ei.value)
     bp.close()
+
+
+def test_nonlinear_coarse_reports_a_failed_harmonic_solve():
+    """Nonlinear coarse problem (coarse_mode 1) with fine results F = U + J whose field
+    overflows the B-H law of the sheath: the frozen linearisation at F (lin_point 1) is
+    not finite, so the preconditioner's harmonic solves report a non-finite residual or a
+    breakdown, which the correction must name instead of running GMRES on NaN.  The
+    coarse residual itself stays finite (F enters it linearly), and every kernel exits."""
+    import paper_1905_13076_amd as P
+    from oracle.fe import FE
+    from tests.gpu_common import load_golden
+    prob = coax.c5_small()
+    fe = FE(prob)
+    U = load_golden("c5small_nlc")["U_k"]
+    pr = P.Problem(handle(), prob)
+    prm = P.problem_params(prob, coarse_mode=1, lin_point=1, tol_cocg=1e-6, tol_newton=1e-10)
+    with pytest.raises(P.PPCError) as ei:
+        pr.coarse_correction(prm, torch.tensor(fe.full(U), device="cuda"),
+                             torch.tensor(fe.full(40.0 * U), device="cuda"))
+    banner(f"nonlinear coarse: {ei.value}")
+    assert ei.value.code in (-5, -6) and "preconditioner" in str(ei.value)
+    # the problem stays usable: the same call with finite data succeeds
+    pr.coarse_correction(prm, torch.tensor(fe.full(U), device="cuda"),
+                         torch.tensor(fe.full(0.01 * U), device="cuda"))
