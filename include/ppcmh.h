@@ -31,7 +31,7 @@
 extern "C" {
 #endif
 
-#define PPC_ABI_VERSION 2
+#define PPC_ABI_VERSION 3
 
 /* status codes */
 #define PPC_OK 0
@@ -161,6 +161,11 @@ typedef struct {
                                1e-14 ||C F||_F), each Newton step by flexible GMRES (at most 30
                                vectors) preconditioned by the frozen harmonic solve.  Not with
                                method 1, n_harm or b_cap; not for batched problems */
+    int32_t lin_start;      /* start of each fine-step PCG solve: 0 = the Galerkin projection
+                               of the Newton system on the chain's last three Newton
+                               corrections (x0 in their span minimising the J-norm error; the
+                               same solution to the PCG tolerance, fewer iterations); 1 = zero.
+                               The adjoint's solves start from zero */
 } ppc_params;
 
 /* Counters and timings of the last solve (all chains, all iterations). */

@@ -52,7 +52,7 @@ class Params(ctypes.Structure):
                 ("tol_cocg", c_double), ("max_cocg", c_int32), ("block", c_int32),
                 ("no_predictor", c_int32), ("lin_point", c_int32), ("coarse_precision", c_int32),
                 ("graph", c_int32), ("method", c_int32), ("fine_block", c_int32), ("n_harm", c_int32),
-                ("b_cap", c_double), ("coarse_mode", c_int32)]
+                ("b_cap", c_double), ("coarse_mode", c_int32), ("lin_start", c_int32)]
 
 
 class Stats(ctypes.Structure):

@@ -1033,6 +1033,7 @@ int ppc_params_default(ppc_params* p) {
     p->method = 0;
     p->b_cap = 0.0;
     p->coarse_mode = 0;
+    p->lin_start = 0;
     return PPC_OK;
 }
 

@@ -9,10 +9,11 @@ namespace {
 
 // Register rows (R rows per thread, the smallest with R rows_block >= n, in workgroups of
 // rows_block threads) when p, r, the FP32 diagonal and the tail sums fit in
-// LDS; otherwise (or with block_req = 1024) the memory path with 1024 threads and as much
-// of p / the inverse diagonal in LDS as fits.
+// LDS; otherwise (or with block_req = 1024) the streaming memory path with 1024 threads,
+// p in LDS when it fits there beside the tail sums (LP = 1).
 FineShape pick_shape(int n, size_t n_pad, int n_tail, size_t elem, int block_req, int rows_block) {
-    const size_t tail = (size_t)std::max(n_tail, 1) * elem;
+    // tail-row sums: one per tail row and history vector (the Galerkin start's products)
+    const size_t tail = (size_t)kHist * std::max(n_tail, 1) * elem;
     if (block_req != kFineBlock) {
         // 1024 threads take any R up to 8 (no padded rows beyond the next 1024), and up to
         // 12 in FP32 (in FP64 the LDS runs out first); the smaller workgroups powers of two
@@ -25,9 +26,8 @@ FineShape pick_shape(int n, size_t n_pad, int n_tail, size_t elem, int block_req
             break;
         }
     }
-    if (2 * n_pad * elem <= kLdsBudget) return {0, kFineBlock, 2, 2 * n_pad * elem};
-    if (n_pad * elem <= kLdsBudget) return {0, kFineBlock, 1, n_pad * elem};
-    return {0, kFineBlock, 0, 0};
+    if (n_pad * elem + tail <= kLdsBudget) return {0, kFineBlock, 1, n_pad * elem + tail};
+    return {0, kFineBlock, 0, tail};
 }
 
 template <typename S, int R, int BLOCK, int LP>
@@ -69,9 +69,8 @@ void launch_typed(const FineArgs& a, int N, const FineShape& sh, hipStream_t s) 
     else if (sh.R == 7) launch_shape<S, 7, kFineBlock, 0>(a, N, sh.lds, s);
     else if (sh.R == 8) launch_shape<S, 8, kFineBlock, 0>(a, N, sh.lds, s);
     else if (sh.R > 8) launch_wide<S>(a, N, sh, s);
-    else if (sh.LP == 2) launch_shape<S, 0, kFineBlock, 2>(a, N, sh.lds, s);
     else if (sh.LP == 1) launch_shape<S, 0, kFineBlock, 1>(a, N, sh.lds, s);
-    else launch_shape<S, 0, kFineBlock, 0>(a, N, 0, s);
+    else launch_shape<S, 0, kFineBlock, 0>(a, N, sh.lds, s);
 }
 
 }  // namespace
@@ -171,6 +170,7 @@ FineArgs make_fine_args(ppc_problem* pr, const ppc_params* p, const double* U, d
     a.tail_ptr = d.tail_ptr;
     a.tail_col = d.tail_col;
     a.predictor = p->no_predictor == 0 ? 1 : 0;
+    a.lin_start = p->lin_start;
     a.traj = nullptr;
     return a;
 }
@@ -179,7 +179,8 @@ FineShape rows_shape(const ppc_problem* pr, const ppc_params* p, int rows_block)
     const size_t elem = p->precision == 0 ? sizeof(double) : sizeof(float);
     // the register-row SpMV reads 16-bit columns (built for n < 65536; R B <= 8192 rows)
     const int block = pr->mesh.ecol16 ? p->block : kFineBlock;
-    return pick_shape(pr->mesh.n_free, pr->ws.n_pad, pr->mesh.n_tail, elem, block, rows_block);
+    const size_t n_pad = ((size_t)pr->mesh.n_free + 63) / 64 * 64;   // the workspace's row padding
+    return pick_shape(pr->mesh.n_free, n_pad, pr->mesh.n_tail, elem, block, rows_block);
 }
 
 // Register-row workgroup size: params->fine_block when set, else the tuned size of this
@@ -249,9 +250,8 @@ void launch_adjoint_sweep(ppc_problem* pr, const ppc_params* p, const AdjArgs& b
     else if (sh.R == 6) launch_adj_shape<6, 0>(a, b, sh.lds, s);
     else if (sh.R == 7) launch_adj_shape<7, 0>(a, b, sh.lds, s);
     else if (sh.R == 8) launch_adj_shape<8, 0>(a, b, sh.lds, s);
-    else if (sh.LP == 2) launch_adj_shape<0, 2>(a, b, sh.lds, s);
     else if (sh.LP == 1) launch_adj_shape<0, 1>(a, b, sh.lds, s);
-    else launch_adj_shape<0, 0>(a, b, 0, s);
+    else launch_adj_shape<0, 0>(a, b, sh.lds, s);
     PPC_HIP(hipGetLastError());
 }
 
@@ -296,9 +296,8 @@ void launch_batch_typed(const FineArgs* args, const int2* work, int nblocks, con
     else if (sh.R == 7) launch_batch_shape<S, 7, 0>(args, work, nblocks, sh.lds, s);
     else if (sh.R == 8) launch_batch_shape<S, 8, 0>(args, work, nblocks, sh.lds, s);
     else if (sh.R > 8) launch_batch_wide<S>(args, work, nblocks, sh, s);
-    else if (sh.LP == 2) launch_batch_shape<S, 0, 2>(args, work, nblocks, sh.lds, s);
     else if (sh.LP == 1) launch_batch_shape<S, 0, 1>(args, work, nblocks, sh.lds, s);
-    else launch_batch_shape<S, 0, 0>(args, work, nblocks, 0, s);
+    else launch_batch_shape<S, 0, 0>(args, work, nblocks, sh.lds, s);
 }
 
 int shape_key(const FineShape& sh) { return sh.block * 256 + sh.R * 16 + sh.LP; }

@@ -61,7 +61,7 @@ enum { E_F0 = 0, E_W0 = 3, E_NU = 6, E_SF = 7 };
 // below kFloorCap * scale: it then sits at the rounding floor of its evaluation.
 constexpr double kFloorCap = 1e-9;
 enum { V_U = 0, V_UP = 1, V_R = 2, V_RT = 3, V_UPP = 4, V_UT = 5, V_CP = 6, V_UP3 = 7, V_UP4 = 8 };
-enum { P_R = 0, P_P = 1, P_Q = 2, P_X = 3, P_D = 4 };
+enum { P_R = 0, P_P = 1, P_Q = 2, P_X = 3, P_D = 4, P_H0 = 5, P_W0 = 5 + kHist };
 enum { C_STATUS = 0, C_NEWTON = 1, C_LIN = 2, C_NEWTON_MAX = 3, C_LIN_MAX = 4, C_CAPPED = 5,
        C_FAILSTEP = 6, C_RESID = 7 };
 
@@ -229,11 +229,16 @@ __device__ inline S tail_row_sum(const FineArgs& a, const S* __restrict__ jv, PV
 // (i = tid + k B, k < R) keep x and q in registers; p, r and the inverse diagonal (FP32:
 // it only shapes the preconditioner) live in LDS, so the SpMV gathers and every vector
 // pass stay on the CU and only the ELL values and columns stream from memory.
+//
+// With kh > 0 the iteration starts from x0 = sum_j cg_j V_j (hist: the chain's last Newton
+// corrections, wv: their products J V_j, both from galerkin_start): x starts there and r
+// at b - sum_j cg_j J V_j.  xout may be one of the V_j (read here before it is written).
 template <typename S, int R, int B>
 __device__ int pcg_regs(const FineArgs& a, const S* __restrict__ jv, S* __restrict__ p_l,
                         S* __restrict__ r_l, const float* __restrict__ d_l, S* __restrict__ tq_l,
-                        const double* __restrict__ Rres, double rs, S* __restrict__ xout, double tgt,
-                        S* lds_s, int& ph) {
+                        const double* __restrict__ Rres, double rs, S* xout, double tgt,
+                        S* lds_s, int& ph, const S* hist = nullptr, const S* wv = nullptr, int kh = 0,
+                        const double* cg = nullptr) {
     const int tid = threadIdx.x, n = a.n;
     const int lane = tid & 63, wave = tid >> 6, nw = B >> 6;
     const long NP = a.ell_pad;
@@ -259,7 +264,11 @@ __device__ int pcg_regs(const FineArgs& a, const S* __restrict__ jv, S* __restri
         x[k] = 0;
         q[k] = 0;
         if (i < n) {
-            const S rv = (S)(-Rres[i] * rs);
+            S rv = (S)(-Rres[i] * rs);
+            for (int j = 0; j < kh; ++j) {
+                x[k] += (S)cg[j] * hist[j * NP + i];
+                rv -= (S)cg[j] * wv[j * NP + i];
+            }
             const S z = (S)d_l[i] * rv;
             r_l[i] = rv;
             p_l[i] = z;
@@ -423,77 +432,301 @@ __device__ int pcg_regs(const FineArgs& a, const S* __restrict__ jv, S* __restri
     return it;
 }
 
-// Same algorithm with the vectors in memory: r, q, x in global memory; p in LDS when
-// LP >= 1 (the SpMV gathers then stay on the CU), the inverse diagonal in LDS when
-// LP == 2.  pl / dl are the LDS arrays (unused otherwise).
-template <typename S, int LP>
-__device__ int pcg_mem(const FineArgs& a, const S* __restrict__ jv, S* __restrict__ pv,
-                       S* __restrict__ pl, S* __restrict__ dl, const double* __restrict__ Rres,
-                       double rs, double tgt, S* lds_s, int& ph) {
+// Galerkin start of pcg_stream: coefficients cg (kh of them) of x0 = V c with
+// (V^T J V) c = V^T b over the last kh Newton corrections V_j = hist + j n_pad; J V_j is kept
+// in wv + j n_pad.  Two passes (the products, then the Galerkin sums from the stored
+// vectors) keep the live registers of each near those of one SpMV pass.
+template <typename S>
+__device__ inline void galerkin_start(const FineArgs& a, const S* __restrict__ jv, const S* hist, int kh,
+                                      S* __restrict__ wv, S* __restrict__ tq_l,
+                                      const double* __restrict__ Rres, double rs, double* lds_d, int& ph_d,
+                                      double (&cg)[kHist]) {
+    constexpr int V = 16 / (int)sizeof(S);
+    typedef S vS __attribute__((ext_vector_type(V)));
+    typedef int vI __attribute__((ext_vector_type(V)));
     const int B = blockDim.x, tid = threadIdx.x, n = a.n;
     const int lane = tid & 63, wave = tid >> 6, nw = B >> 6;
-    const long NP = a.ell_pad;
-    const long VP = a.n_pad;
+    const long NP = a.n_pad;
     const int W = a.W;
-    S* pr = pv + P_R * VP;
-    S* pp = LP >= 1 ? pl : pv + P_P * VP;
-    S* pq = pv + P_Q * VP;
-    S* px = pv + P_X * VP;
-    const S* pd = LP == 2 ? dl : pv + P_D * VP;
+    const int G = (int)(NP / V);
+    auto ld = [](const S* q, long i) { return *reinterpret_cast<const vS*>(q + i); };
+    auto st = [](S* q, long i, vS v) { *reinterpret_cast<vS*>(q + i) = v; };
+    for (int t = wave; t < a.ntail; t += nw)
+        for (int j = 0; j < kh; ++j) {
+            const S acc = tail_row_sum<S>(a, jv, hist + j * NP, t, lane);
+            if (lane == 0) tq_l[j * a.ntail + t] = acc;
+        }
+    __syncthreads();
+    // pass 1: W_j = J V_j
+    for (int g = tid; g < G; g += B) {
+        const int i0 = g * V;
+        vS w[kHist];
+#pragma unroll
+        for (int j = 0; j < kHist; ++j) w[j] = (vS)(S)0;
+        vI tl = (vI)0;
+#pragma unroll
+        for (int w0 = 0; w0 < kEllMaxWidth; w0 += 4) {
+            if (w0 >= W) break;
+            vS v[4];
+            vI c[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int ww = w0 + u;
+                if (ww < W) {
+                    v[u] = ld(jv, ww * NP + i0);
+                    c[u] = *reinterpret_cast<const vI*>(a.ecol + ww * NP + i0);
+                } else {
+                    v[u] = (vS)(S)0;
+                    c[u] = (vI)0;
+                }
+            }
+            if (w0 == 0)
+#pragma unroll
+                for (int k = 0; k < V; ++k) tl[k] = c[0][k] < 0 ? 1 + c[1][k] : 0;
+#pragma unroll
+            for (int j = 0; j < kHist; ++j) {
+                if (j >= kh) break;
+                const S* hj = hist + j * NP;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    vS gp;
+#pragma unroll
+                    for (int k = 0; k < V; ++k) gp[k] = hj[c[u][k] < 0 ? 0 : c[u][k]];
+                    w[j] += v[u] * gp;
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kHist; ++j) {
+            if (j >= kh) break;
+#pragma unroll
+            for (int k = 0; k < V; ++k)
+                if (tl[k] > 0) w[j][k] = tq_l[j * a.ntail + tl[k] - 1];
+            st(wv + j * NP, i0, w[j]);
+        }
+    }
+    __syncthreads();
+    // pass 2: V_i^T W_j (i <= j) and V_i^T b, in FP64
+    constexpr int NG = kHist * kHist + kHist;
+    double gs[NG];
+#pragma unroll
+    for (int q = 0; q < NG; ++q) gs[q] = 0.0;
+    for (int g = tid; g < G; g += B) {
+        const int i0 = g * V;
+        vS b;
+#pragma unroll
+        for (int k = 0; k < V; ++k) b[k] = i0 + k < n ? (S)(-Rres[i0 + k] * rs) : (S)0;
+        vS hv[kHist], wj[kHist];
+#pragma unroll
+        for (int j = 0; j < kHist; ++j) {
+            hv[j] = j < kh ? ld(hist + j * NP, i0) : (vS)(S)0;
+            wj[j] = j < kh ? ld(wv + j * NP, i0) : (vS)(S)0;
+        }
+#pragma unroll
+        for (int i = 0; i < kHist; ++i) {
+#pragma unroll
+            for (int j = i; j < kHist; ++j)
+#pragma unroll
+                for (int k = 0; k < V; ++k) gs[i * kHist + j] += (double)hv[i][k] * (double)wj[j][k];
+#pragma unroll
+            for (int k = 0; k < V; ++k) gs[kHist * kHist + i] += (double)hv[i][k] * (double)b[k];
+        }
+    }
+    // workgroup sums, four values at a time (the reduction buffer holds four)
+#pragma unroll
+    for (int q0 = 0; q0 < NG; q0 += 4) {
+        double t4[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) t4[u] = q0 + u < NG ? gs[q0 + u] : 0.0;
+        block_sum<double, 4>(t4, lds_d, ph_d);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (q0 + u < NG) gs[q0 + u] = t4[u];
+    }
+    // Cholesky of the kh x kh Galerkin matrix (unrolled over kHist, entries beyond kh
+    // inactive); a pivot at rounding level relative to its diagonal marks a dependent
+    // direction, whose coefficient stays 0
+    double L[kHist][kHist];
+    bool on[kHist];
+#pragma unroll
+    for (int j = 0; j < kHist; ++j) {
+#pragma unroll
+        for (int i = 0; i < kHist; ++i) L[i][j] = 0.0;
+        double d = gs[j * kHist + j];
+#pragma unroll
+        for (int m = 0; m < j; ++m) d -= L[j][m] * L[j][m];
+        on[j] = j < kh && d > (sizeof(S) == 4 ? 1e-5 : 1e-10) * gs[j * kHist + j] && isfinite(d);
+        if (on[j]) {
+            L[j][j] = sqrt(d);
+#pragma unroll
+            for (int i = j + 1; i < kHist; ++i) {
+                double e = gs[j * kHist + i];
+#pragma unroll
+                for (int m = 0; m < j; ++m) e -= L[i][m] * L[j][m];
+                L[i][j] = i < kh ? e / L[j][j] : 0.0;
+            }
+        }
+    }
+    double y[kHist];
+#pragma unroll
+    for (int j = 0; j < kHist; ++j) {
+        double e = gs[kHist * kHist + j];
+#pragma unroll
+        for (int m = 0; m < j; ++m) e -= L[j][m] * y[m];
+        y[j] = on[j] ? e / L[j][j] : 0.0;
+    }
+#pragma unroll
+    for (int j = kHist - 1; j >= 0; --j) {
+        double e = y[j];
+#pragma unroll
+        for (int m = j + 1; m < kHist; ++m) e -= L[m][j] * cg[m];
+        cg[j] = on[j] ? e / L[j][j] : 0.0;
+    }
+}
+
+// Same algorithm for meshes beyond the register rows, streaming the chain's vectors from
+// memory.  Each thread owns groups of V = 16 / sizeof(S) consecutive rows, so every value,
+// column and vector access is one 16-byte load or store per lane (four FP32 or two FP64
+// rows), and a group issues the loads of a round of ELL slots before the gathers that use
+// them.  Three passes per iteration, two workgroup reductions:
+//   q = J p (gathers of p; tail rows summed first by one wave each into LDS), p.q;
+//   x += alpha p, r -= alpha q, with r.Dr and r.r (D the Jacobi inverse diagonal);
+//   p = D r + beta p.
+// p lives in LDS when PL == 1 (the gathers then stay on the CU), else in memory.  The
+// inverse diagonal is formed here from the Jacobian's diagonal positions.  Rows of the
+// padded tail [n, n_pad) hold zero in every vector.
+//
+// Start: with kh > 0 the iteration starts from the Galerkin projection of the solution on
+// the span of the chain's last kh Newton corrections V_j (hist, kh <= kHist): x0 = V c with
+// (V^T J V) c = V^T b, the point of that span closest to the solution in the J-norm.  The
+// corrections of successive steps vary smoothly in time, so the projection removes most of
+// the right-hand side before the first iteration.  One pass forms J V_j (kept in wv) with
+// the Galerkin sums; a Cholesky factorisation that drops dependent directions gives c on
+// every thread alike; x0 and r0 = b - (J V) c follow in the initial pass.  The solution is
+// accumulated in xout, which may be the oldest history vector (read before it is written).
+template <typename S, int PL>
+__device__ int pcg_stream(const FineArgs& a, const S* __restrict__ jv, S* __restrict__ pv,
+                          S* __restrict__ p_l, S* __restrict__ tq_l, const double* __restrict__ Rres,
+                          double rs, double tgt, S* lds_s, int& ph, S* xout, const S* hist, int kh,
+                          S* __restrict__ wv, double* lds_d, int& ph_d) {
+    constexpr int V = 16 / (int)sizeof(S);
+    typedef S vS __attribute__((ext_vector_type(V)));
+    typedef int vI __attribute__((ext_vector_type(V)));
+    const int B = blockDim.x, tid = threadIdx.x, n = a.n;
+    const int lane = tid & 63, wave = tid >> 6, nw = B >> 6;
+    const long NP = a.n_pad;
+    const int W = a.W;
+    const int G = (int)(NP / V);
+    S* pr = pv + P_R * NP;
+    S* pq = pv + P_Q * NP;
+    S* px = xout;
+    S* pd = pv + P_D * NP;
+    S* pp = PL ? p_l : pv + P_P * NP;
+    auto ld = [](const S* q, long i) { return *reinterpret_cast<const vS*>(q + i); };
+    auto st = [](S* q, long i, vS v) { *reinterpret_cast<vS*>(q + i) = v; };
+    auto rhs = [&](int i0) {
+        vS b;
+#pragma unroll
+        for (int k = 0; k < V; ++k) b[k] = i0 + k < n ? (S)(-Rres[i0 + k] * rs) : (S)0;
+        return b;
+    };
+    double cg[kHist] = {0.0};
+    if (kh > 0) galerkin_start<S>(a, jv, hist, kh, wv, tq_l, Rres, rs, lds_d, ph_d, cg);
+    // ---- initial residual, diagonal, direction ------------------------------------------------
     S loc[2] = {0, 0};
-    for (int i = tid; i < n; i += B) {
-        const S rv = (S)(-Rres[i] * rs);
-        const S z = pd[i] * rv;
-        pr[i] = rv;
-        pp[i] = z;
-        px[i] = 0;
-        loc[0] += rv * z;
-        loc[1] += rv * rv;
+    for (int g = tid; g < G; g += B) {
+        const int i0 = g * V;
+        vS r = rhs(i0), x = (vS)(S)0, d;
+#pragma unroll
+        for (int j = 0; j < kHist; ++j) {
+            if (j >= kh) break;
+            x += (S)cg[j] * ld(hist + j * NP, i0);
+            r -= (S)cg[j] * ld(wv + j * NP, i0);
+        }
+#pragma unroll
+        for (int k = 0; k < V; ++k) d[k] = i0 + k < n ? (S)1 / jv[a.dpos[i0 + k]] : (S)0;
+        const vS z = d * r;
+        st(pr, i0, r);
+        st(pd, i0, d);
+        st(pp, i0, z);
+        st(px, i0, x);
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            loc[0] += r[k] * z[k];
+            loc[1] += r[k] * r[k];
+        }
     }
     block_sum<S, 2>(loc, lds_s, ph);
     S rz = loc[0];
     double rr = (double)loc[1];
     int it = 0;
     while (rr > tgt * tgt && it < a.max_lin) {
-        S dot[1] = {0};
-#pragma unroll 2
-        for (int i = tid; i < n; i += B) {
-            int col[kEllMaxWidth];
-            S val[kEllMaxWidth];
-#pragma unroll
-            for (int w = 0; w < kEllMaxWidth; ++w) {
-                col[w] = w < W ? a.ecol[w * NP + i] : 0;
-                val[w] = w < W ? jv[w * NP + i] : (S)0;
-            }
-            if (col[0] >= 0) {
-                S acc = 0;
-#pragma unroll
-                for (int w = 0; w < kEllMaxWidth; ++w)
-                    if (w < W) acc += val[w] * pp[col[w]];
-                pq[i] = acc;
-                dot[0] += pp[i] * acc;
-            }
-        }
+        // tail rows (longer than the ELL width): one wave per row, kept in LDS for the
+        // rows' owners below
         for (int t = wave; t < a.ntail; t += nw) {
             const S acc = tail_row_sum<S>(a, jv, pp, t, lane);
-            if (lane == 0) {
-                const int row = a.tail_row[t];
-                pq[row] = acc;
-                dot[0] += pp[row] * acc;
+            if (lane == 0) tq_l[t] = acc;
+        }
+        __syncthreads();
+        S dot[1] = {0};
+        for (int g = tid; g < G; g += B) {
+            const int i0 = g * V;
+            vS acc = (vS)(S)0;
+            vI tl = (vI)0;        // tail rows: slot 0 holds -1 and slot 1 the tail index
+            // slots in rounds of four: the value and column loads of a round in flight
+            // together, then its gathers, then its products
+#pragma unroll
+            for (int w0 = 0; w0 < kEllMaxWidth; w0 += 4) {
+                if (w0 >= W) break;
+                vS v[4];
+                vI c[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int w = w0 + u;
+                    if (w < W) {
+                        v[u] = ld(jv, w * NP + i0);
+                        c[u] = *reinterpret_cast<const vI*>(a.ecol + w * NP + i0);
+                    } else {
+                        v[u] = (vS)(S)0;
+                        c[u] = (vI)0;
+                    }
+                }
+                if (w0 == 0)
+#pragma unroll
+                    for (int k = 0; k < V; ++k) tl[k] = c[0][k] < 0 ? 1 + c[1][k] : 0;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    vS gp;
+#pragma unroll
+                    for (int k = 0; k < V; ++k) gp[k] = pp[c[u][k] < 0 ? 0 : c[u][k]];
+                    acc += v[u] * gp;
+                }
             }
+#pragma unroll
+            for (int k = 0; k < V; ++k)
+                if (tl[k] > 0) acc[k] = tq_l[tl[k] - 1];
+            st(pq, i0, acc);
+            const vS pown = ld(pp, i0);
+#pragma unroll
+            for (int k = 0; k < V; ++k) dot[0] += pown[k] * acc[k];
         }
         block_sum<S, 1>(dot, lds_s, ph);
         const S pqv = dot[0];
-        if (!(pqv > (S)0)) break;
+        if (!(pqv > (S)0)) break;                 // loss of positivity: Newton decides
         const S alpha = rz / pqv;
         S l2[2] = {0, 0};
-#pragma unroll 2
-        for (int i = tid; i < n; i += B) {
-            px[i] += alpha * pp[i];
-            const S rv = pr[i] - alpha * pq[i];
-            pr[i] = rv;
-            l2[0] += rv * (pd[i] * rv);
-            l2[1] += rv * rv;
+        for (int g = tid; g < G; g += B) {
+            const int i0 = g * V;
+            const vS x = ld(px, i0) + alpha * ld(pp, i0);
+            const vS r = ld(pr, i0) - alpha * ld(pq, i0);
+            const vS z = ld(pd, i0) * r;
+            st(px, i0, x);
+            st(pr, i0, r);
+#pragma unroll
+            for (int k = 0; k < V; ++k) {
+                l2[0] += r[k] * z[k];
+                l2[1] += r[k] * r[k];
+            }
         }
         block_sum<S, 2>(l2, lds_s, ph);
         ++it;
@@ -501,15 +734,18 @@ __device__ int pcg_mem(const FineArgs& a, const S* __restrict__ jv, S* __restric
         if (rr <= tgt * tgt) break;
         const S beta = l2[0] / rz;
         rz = l2[0];
-#pragma unroll 2
-        for (int i = tid; i < n; i += B) pp[i] = pd[i] * pr[i] + beta * pp[i];
+        for (int g = tid; g < G; g += B) {
+            const int i0 = g * V;
+            st(pp, i0, ld(pd, i0) * ld(pr, i0) + beta * ld(pp, i0));
+        }
         __syncthreads();
     }
     return it;
 }
 
 // R > 0: PCG rows in registers, p / diagonal / tail sums in dynamic LDS;
-// R == 0: PCG vectors in memory, with p (LP >= 1) and the diagonal (LP == 2) in LDS.
+// R == 0: PCG vectors streamed from memory, with p in LDS when LP == 1; the tail-row sums
+// in LDS after it.
 template <typename S, int R, int BLOCK, int LP>
 __device__ __forceinline__ void fine_chain(const FineArgs& a, const int c, unsigned char* dyn_lds,
                                            double* lds_d, S* lds_s) {
@@ -531,11 +767,9 @@ __device__ __forceinline__ void fine_chain(const FineArgs& a, const int c, unsig
     S* jv = reinterpret_cast<S*>(a.jac) + (long)c * a.vals_pad;
     double* el = a.elem + (long)c * 8 * a.nl_pad;
     S* p_l = reinterpret_cast<S*>(dyn_lds);
-    S* d_l = p_l + NP;                        // memory path: inverse diagonal (LP == 2)
     S* r_l = p_l + NP;                        // register path: r
     float* df_l = reinterpret_cast<float*>(r_l + NP);   // register path: FP32 diagonal
-    S* tq_l = reinterpret_cast<S*>(df_l + NP);
-    S* dinv = LP == 2 ? d_l : pv + P_D * NP;
+    S* tq_l = R > 0 ? reinterpret_cast<S*>(df_l + NP) : (LP == 1 ? p_l + NP : p_l);
 
     const double* U0 = a.U + (long)c * n;
     double* Tc = a.traj ? a.traj + (long)c * (a.m + 1) * n : nullptr;
@@ -550,6 +784,7 @@ __device__ __forceinline__ void fine_chain(const FineArgs& a, const int c, unsig
     const double inv_dt = 1.0 / a.dt;
     int status = 0, fail_step = -1;
     int newton_total = 0, lin_total = 0, newton_max = 0, lin_max = 0, capped = 0, resid_evals = 0;
+    int n_solves = 0;                         // Newton solves of this chain (history slots filled)
 
     for (int j = 1; j <= a.m && status == 0; ++j) {
         const double t = t0 + j * a.dt;
@@ -617,10 +852,8 @@ __device__ __forceinline__ void fine_chain(const FineArgs& a, const int c, unsig
             __syncthreads();
             if constexpr (R > 0) {
                 for (int i = threadIdx.x; i < n; i += blockDim.x) df_l[i] = (float)(1.0 / (double)jv[a.dpos[i]]);
-            } else {
-                for (int i = threadIdx.x; i < n; i += blockDim.x) dinv[i] = (S)1 / jv[a.dpos[i]];
+                __syncthreads();
             }
-            __syncthreads();
             const double ltarget = fmax(a.tol_lin * rn, 0.5 * target);
             // FP32 PCG solves for the unit right-hand side -R/||R|| (near convergence the
             // residual and its products would fall below FP32's range); the step px * xs
@@ -628,10 +861,20 @@ __device__ __forceinline__ void fine_chain(const FineArgs& a, const int c, unsig
             const double rs = (sizeof(S) == 4 && rn > 0.0) ? 1.0 / rn : 1.0;
             const double xs = (sizeof(S) == 4 && rn > 0.0) ? rn : 1.0;
             int k;
-            if constexpr (R > 0)
-                k = pcg_regs<S, R, BLOCK>(a, jv, p_l, r_l, df_l, tq_l, R_, rs, px, ltarget * rs, lds_s, ph_s);
-            else
-                k = pcg_mem<S, LP>(a, jv, pv, p_l, d_l, R_, rs, ltarget * rs, lds_s, ph_s);
+            // the solution goes to the oldest history slot; with lin_start 0 the last
+            // (at most kHist) corrections seed the start
+            px = pv + (long)(P_H0 + n_solves % kHist) * NP;
+            const int kh = a.lin_start == 0 ? (n_solves < kHist ? n_solves : kHist) : 0;
+            if constexpr (R > 0) {
+                double cg[kHist] = {0.0};
+                if (kh > 0) galerkin_start<S>(a, jv, pv + P_H0 * NP, kh, pv + P_W0 * NP, tq_l, R_, rs, lds_d, ph_d, cg);
+                k = pcg_regs<S, R, BLOCK>(a, jv, p_l, r_l, df_l, tq_l, R_, rs, px, ltarget * rs, lds_s, ph_s,
+                                          pv + P_H0 * NP, pv + P_W0 * NP, kh, cg);
+            } else {
+                k = pcg_stream<S, LP>(a, jv, pv, p_l, tq_l, R_, rs, ltarget * rs, lds_s, ph_s, px, pv + P_H0 * NP,
+                                      kh, pv + P_W0 * NP, lds_d, ph_d);
+            }
+            ++n_solves;
             __syncthreads();
             lin_total += k;
             lin_max = k > lin_max ? k : lin_max;
@@ -750,11 +993,9 @@ __device__ __forceinline__ void adjoint_chain(const FineArgs& a, const AdjArgs& 
     S* jv = reinterpret_cast<S*>(a.jac) + (long)c * a.vals_pad;
     double* el = a.elem + (long)c * 8 * a.nl_pad;
     S* p_l = reinterpret_cast<S*>(dyn_lds);
-    S* d_l = p_l + NP;
     S* r_l = p_l + NP;
     float* df_l = reinterpret_cast<float*>(r_l + NP);
-    S* tq_l = reinterpret_cast<S*>(df_l + NP);
-    S* dinv = LP == 2 ? d_l : pv + P_D * NP;
+    S* tq_l = R > 0 ? reinterpret_cast<S*>(df_l + NP) : (LP == 1 ? p_l + NP : p_l);
     const double* T0 = b.traj + (long)c * (m + 1) * n;
     const double* T1 = b.traj + (long)((c + 1) % N) * (m + 1) * n;
     const double* Lin = b.lam_in + (long)((c + 1) % N) * n;
@@ -781,16 +1022,15 @@ __device__ __forceinline__ void adjoint_chain(const FineArgs& a, const AdjArgs& 
         __syncthreads();
         if constexpr (R > 0) {
             for (int i = threadIdx.x; i < n; i += blockDim.x) df_l[i] = (float)(1.0 / (double)jv[a.dpos[i]]);
-        } else {
-            for (int i = threadIdx.x; i < n; i += blockDim.x) dinv[i] = (S)1 / jv[a.dpos[i]];
+            __syncthreads();
         }
-        __syncthreads();
         int k = 0;
         if (rn > 0.0) {
             if constexpr (R > 0)
                 k = pcg_regs<S, R, BLOCK>(a, jv, p_l, r_l, df_l, tq_l, rhs, 1.0, px, b.tol_lin * rn, lds_s, ph_s);
             else
-                k = pcg_mem<S, LP>(a, jv, pv, p_l, d_l, rhs, 1.0, b.tol_lin * rn, lds_s, ph_s);
+                k = pcg_stream<S, LP>(a, jv, pv, p_l, tq_l, rhs, 1.0, b.tol_lin * rn, lds_s, ph_s, px, pv, 0,
+                                      pv, lds_d, ph_d);
         } else {
             for (int i = threadIdx.x; i < n; i += blockDim.x) px[i] = 0;
         }

@@ -239,6 +239,7 @@ struct FineArgs {
     // ELL pattern of the fine-sweep SpMV
     int W, ntail, nvals;
     int predictor;
+    int lin_start;          // 0: Galerkin start of the streaming PCG from the last corrections; 1: zero
     double* traj;            // [N][m+1][n] fine trajectory of each chain, or null
     long ell_pad;
     const int* ecol;
@@ -317,7 +318,8 @@ struct CocgArgs {
 };
 
 constexpr int kFineVec = 9;   // u, u_prev, R, R_trial, u_{j-2}, trial state, M u_prev / dt, u_{j-3}, u_{j-4}
-constexpr int kPcgVec = 5;    // r, p, q, x, dinv
+constexpr int kHist = 3;      // Newton corrections kept for the Galerkin start of the streaming PCG
+constexpr int kPcgVec = 5 + 2 * kHist;   // r, p, q, x, dinv, the corrections, their J products
 
 // set-up (setup.hip)
 void build_problem(ppc_problem* pr, const ppc_mesh* mesh, const ppc_material* mat,

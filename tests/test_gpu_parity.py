@@ -263,6 +263,33 @@ def test_fine_sweep_kernel_paths_match_oracle(nr, prec, force):
     assert e <= 1e-10
 
 
+# Galerkin start (lin_start 0) against the zero start, on chains long enough to fill the
+# three-correction history: register rows (nr = 20, 60) and the streaming memory path
+# (nr = 80 with p in LDS, nr = 100 with p in memory), FP64 and mixed
+@pytest.mark.parametrize("nr,prec", [(20, 0), (60, 1), (80, 0), (80, 1), (100, 0), (100, 1)])
+def test_galerkin_start_matches_oracle(nr, prec):
+    import torch
+    import paper_1905_13076_amd as P
+    from oracle.fe import FE
+    from oracle import periodic
+    prob = coax.c2(nr=nr, ntheta=2 * nr, N=4, m=8)
+    fe = FE(prob)
+    rng = np.random.default_rng(7 * nr + prec)
+    r = np.hypot(prob.xy[fe.free, 0], prob.xy[fe.free, 1])
+    U0 = np.outer(1.0 + 0.1 * rng.standard_normal(prob.N), 1e-4 * (3e-3 - r) / 3e-3)
+    Fo = periodic.fine_sweep(fe, U0)
+    pr = _problem(prob)
+    Ud = torch.tensor(_nodal(fe, U0), device="cuda")
+    lin = {}
+    for ls in (0, 1):
+        prm = P.problem_params(prob, precision=prec, lin_start=ls, tol_lin=1e-8 if prec == 0 else 1e-4)
+        F, newton, lin[ls] = pr.fine_sweep(prm, Ud)
+        e = rel(free_rows(F.cpu().numpy(), fe.free), Fo)
+        banner(f"galerkin start nr={nr} prec={prec} lin_start={ls} rel={e:.2e} newton={int(newton.sum())} "
+               f"pcg={int(lin[ls].sum())}")
+        assert e <= 1e-10
+
+
 # register rows at 1024 threads: R = ceil(rows / 1024) for every R = 1..8
 @pytest.mark.parametrize("nr,ntheta,R", [(20, 40, 1), (25, 60, 2), (35, 80, 3), (40, 100, 4),
                                          (45, 100, 5), (50, 110, 6), (60, 120, 7), (62, 124, 8)])
