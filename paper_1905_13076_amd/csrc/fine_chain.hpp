@@ -424,10 +424,12 @@ __device__ int pcg_regs(const FineArgs& a, const S* __restrict__ jv, S* __restri
         }
         __syncthreads();
     }
+    // padded rows [n, n_pad) are written as zero: xout is a stored correction whose rows
+    // the Galerkin start reads in groups
 #pragma unroll
     for (int k = 0; k < R; ++k) {
         const int i = tid + k * B;
-        if (i < n) xout[i] = x[k];
+        if (i < NP) xout[i] = i < n ? x[k] : (S)0;
     }
     return it;
 }
@@ -521,6 +523,9 @@ __device__ inline void galerkin_start(const FineArgs& a, const S* __restrict__ j
         for (int j = 0; j < kHist; ++j) {
             hv[j] = j < kh ? ld(hist + j * NP, i0) : (vS)(S)0;
             wj[j] = j < kh ? ld(wv + j * NP, i0) : (vS)(S)0;
+#pragma unroll
+            for (int k = 0; k < V; ++k)
+                if (i0 + k >= n) hv[j][k] = (S)0;    // padded rows take no part
         }
 #pragma unroll
         for (int i = 0; i < kHist; ++i) {
@@ -643,6 +648,12 @@ __device__ int pcg_stream(const FineArgs& a, const S* __restrict__ jv, S* __rest
             x += (S)cg[j] * ld(hist + j * NP, i0);
             r -= (S)cg[j] * ld(wv + j * NP, i0);
         }
+#pragma unroll
+        for (int k = 0; k < V; ++k)
+            if (i0 + k >= n) {          // padded rows stay zero in every vector
+                x[k] = (S)0;
+                r[k] = (S)0;
+            }
 #pragma unroll
         for (int k = 0; k < V; ++k) d[k] = i0 + k < n ? (S)1 / jv[a.dpos[i0 + k]] : (S)0;
         const vS z = d * r;
