@@ -342,6 +342,31 @@ int ppc_fine_sweep_device(ppc_handle* h, ppc_problem* pr, const ppc_params* p,
                           const double* U_in_dev, double* F_out_dev, int32_t* newton_out,
                           int32_t* lin_out, void* stream);
 
+/* Size of the static device scratch of ppc_fine_sweep_noalloc, in MiB. */
+#define PPC_NOALLOC_SCRATCH_MB 96
+
+/* ppc_fine_sweep_device for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the same fine
+ * sweep with the same kernels and results, but every per-sweep buffer (free-row copies of
+ * U and F, base Jacobian, chain vectors, PCG vectors, Jacobian values, Brauer element
+ * planes, chain counters) lives in one static device array of PPC_NOALLOC_SCRATCH_MB MiB
+ * per GPU, held from the library's first ppc_create on that GPU until the process ends.
+ * The call allocates no device or pinned memory and does not touch the problem's
+ * workspace, so it may run between the problem's solves.  It still synchronises `stream`
+ * once to read the chain counters (status, newton_out, lin_out).
+ *   U_in_dev / F_out_dev  DEVICE [N * n_nodes], as ppc_fine_sweep_device
+ *   newton_out / lin_out  host [N] or null
+ * Every call on one GPU shares that GPU's scratch: calls that overlap in time on one GPU
+ * (other host threads, other handles, other streams) race and must be serialised by the
+ * caller.  Nothing in the scratch needs clearing between calls: each sweep writes every
+ * value it reads.  PPC_ERR_ARG when N > 1024 or the sweep needs more than the scratch holds
+ * (about N n (88 + 11 s) + N vals s + 8 vals bytes for n free nodes, vals ELL value
+ * positions and s = 8 (FP64) or 4 (mixed); 40 chains of 7,081 free nodes in FP64 take
+ * about 75 MB), before any device work. */
+int ppc_fine_sweep_noalloc(ppc_handle* h, ppc_problem* pr, const ppc_params* p,
+                           const double* U_in_dev, double* F_out_dev, int32_t* newton_out,
+                           int32_t* lin_out, void* stream);
+
 /* Per-chain counters of the last fine sweep run on this problem (by
  * ppc_fine_sweep_device, or the last sweep of a solve).  counts is host
  * [n_chains * 8], per chain: status, Newton iterations, PCG iterations, the largest

@@ -92,6 +92,8 @@ SIGNATURES = {
     "ppc_adjoint": (c_int, [c_void_p, c_void_p, POINTER(Params), PD, PD, PD, PD, PI, POINTER(Stats)]),
     "ppc_fine_sweep_device": (c_int, [c_void_p, c_void_p, POINTER(Params), c_void_p, c_void_p, PI, PI,
                                       c_void_p]),
+    "ppc_fine_sweep_noalloc": (c_int, [c_void_p, c_void_p, POINTER(Params), c_void_p, c_void_p, PI, PI,
+                                       c_void_p]),
     "ppc_fine_counts": (c_int, [c_void_p, c_int32, PI]),
     "ppc_autotune": (c_int, [c_void_p, c_void_p, c_void_p, PI, PD]),
     "ppc_time_stepping_device": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, PI,

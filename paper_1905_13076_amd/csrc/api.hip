@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "internal.hpp"
@@ -84,6 +85,31 @@ float elapsed(hipEvent_t a, hipEvent_t b) {
     float ms = 0.f;
     PPC_HIP(hipEventElapsedTime(&ms, a, b));
     return ms;
+}
+
+// Static device scratch of ppc_fine_sweep_noalloc: one copy per GPU the library runs on,
+// held until the process ends.  Host code never uses the array's name as an address: the
+// device address of each GPU's copy comes from hipGetSymbolAddress at ppc_create (with that
+// device current) and is kept in g_scratch_dev.
+constexpr size_t kScratchBytes = (size_t)PPC_NOALLOC_SCRATCH_MB << 20;
+constexpr int kScratchDevices = 64;
+constexpr int kNoAllocMaxChains = 1024;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_dev[kScratchDevices] = {};
+
+// The device address of this device's scratch copy; the device must be current.  Called
+// once per device (later calls return the stored address).
+unsigned char* scratch_address(int device) {
+    if (device < 0 || device >= kScratchDevices) fail(PPC_ERR_DEVICE, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[device]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) fail(PPC_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_dev[device] = static_cast<unsigned char*>(ptr);
+    }
+    return g_scratch_dev[device];
 }
 
 }  // namespace
@@ -1068,6 +1094,7 @@ int ppc_create(int32_t device, ppc_handle** out) {
         if (e != hipSuccess || count == 0) fail(PPC_ERR_DEVICE, "no usable GPU (hipGetDeviceCount)");
         if (device >= count) fail(PPC_ERR_ARG, "device index out of range");
         PPC_HIP(hipSetDevice(device));
+        (void)scratch_address(device);
         auto* h = new ppc_handle();
         h->device = device;
         try {
@@ -1312,6 +1339,42 @@ int ppc_fine_sweep_device(ppc_handle* h, ppc_problem* pr, const ppc_params* p, c
         const SweepCounts c = read_chain_counts(pr, p->N, s, newton_out, lin_out);
         check_sweep(c);
         launch_to_nodal(pr, p->N, pr->ws.F, F_out_dev, s);
+        PPC_HIP(hipStreamSynchronize(s));
+        return PPC_OK;
+    });
+}
+
+int ppc_fine_sweep_noalloc(ppc_handle* h, ppc_problem* pr, const ppc_params* p, const double* U_in_dev,
+                           double* F_out_dev, int32_t* newton_out, int32_t* lin_out, void* stream) {
+    return guarded(h, [&]() -> int {
+        check_handle_problem(h, pr);
+        check_params(p);
+        if (!U_in_dev || !F_out_dev) fail(PPC_ERR_ARG, "null U_in or F_out");
+        if (pr->batch) fail(PPC_ERR_ARG, "single-design entry point called with a batch problem");
+        if (p->N > kNoAllocMaxChains)
+            fail(PPC_ERR_ARG, "N = " + std::to_string(p->N) + " exceeds the " + std::to_string(kNoAllocMaxChains) +
+                                  " chains of the allocation-free fine sweep");
+        const size_t L = (size_t)p->N * (size_t)pr->mesh.n_free;
+        const size_t vecs = 2 * ((L * sizeof(double) + 255) / 256 * 256);     // U and F, free rows
+        const size_t need = vecs + fine_scratch_layout(pr, p, nullptr, nullptr);
+        if (need > kScratchBytes)
+            fail(PPC_ERR_ARG, "the allocation-free fine sweep needs " + std::to_string(need) + " bytes of its " +
+                                  std::to_string(kScratchBytes) + "-byte static scratch (N = " + std::to_string(p->N) +
+                                  ", " + std::to_string(pr->mesh.n_free) + " free nodes)");
+        PPC_HIP(hipSetDevice(h->device));
+        hipStream_t s = pick_stream(h, stream);
+        unsigned char* base = scratch_address(h->device);
+        double* Uf = reinterpret_cast<double*>(base);
+        double* Ff = reinterpret_cast<double*>(base + vecs / 2);
+        FineScratch sc;
+        (void)fine_scratch_layout(pr, p, base + vecs, &sc);
+        launch_to_free(pr, p->N, U_in_dev, Uf, s);
+        launch_fine_sweep_in(pr, p, Uf, Ff, sc, s);
+        int host_count[8 * kNoAllocMaxChains];
+        PPC_HIP(hipMemcpyAsync(host_count, sc.count, 8 * (size_t)p->N * sizeof(int), hipMemcpyDeviceToHost, s));
+        PPC_HIP(hipStreamSynchronize(s));
+        check_sweep(parse_chain_counts(host_count, p->N, newton_out, lin_out));
+        launch_to_nodal(pr, p->N, Ff, F_out_dev, s);
         PPC_HIP(hipStreamSynchronize(s));
         return PPC_OK;
     });

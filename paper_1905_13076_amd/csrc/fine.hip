@@ -221,6 +221,56 @@ void launch_fine_sweep_traj(ppc_problem* pr, const ppc_params* p, const double* 
     PPC_HIP(hipGetLastError());
 }
 
+size_t fine_scratch_layout(const ppc_problem* pr, const ppc_params* p, unsigned char* base, FineScratch* out) {
+    const DeviceMesh& d = pr->mesh;
+    const size_t N = (size_t)p->N;
+    const size_t s = p->precision == 0 ? sizeof(double) : sizeof(float);
+    auto pad = [](size_t x, size_t q) { return (x + q - 1) / q * q; };
+    FineScratch sc;
+    sc.n_pad = (long)pad((size_t)d.n_free, 64);
+    sc.vals_pad = (long)pad((size_t)d.n_vals, 64);
+    sc.nl_pad = (long)pad((size_t)std::max(d.n_nl, 1), 64);
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> unsigned char* {
+        unsigned char* q = base ? base + off : nullptr;
+        off += pad(std::max<size_t>(bytes, 1), 256);
+        return q;
+    };
+    sc.jbase = reinterpret_cast<double*>(take((size_t)sc.vals_pad * sizeof(double)));
+    sc.vec = reinterpret_cast<double*>(take(N * kFineVec * (size_t)sc.n_pad * sizeof(double)));
+    sc.pcg = take(N * kPcgVec * (size_t)sc.n_pad * s);
+    sc.jac = take(N * (size_t)sc.vals_pad * s);
+    sc.elem = reinterpret_cast<double*>(take(N * 8 * (size_t)sc.nl_pad * sizeof(double)));
+    sc.count = reinterpret_cast<int*>(take(N * 8 * sizeof(int)));
+    if (out) *out = sc;
+    return off;
+}
+
+void launch_fine_sweep_in(ppc_problem* pr, const ppc_params* p, const double* U, double* F,
+                          const FineScratch& sc, hipStream_t s) {
+    const DeviceMesh& d = pr->mesh;
+    const double dt = p->T / (double)(p->N * p->m);
+    const int nb = std::max(1, std::min((d.n_vals + 255) / 256, 4096));
+    hipLaunchKernelGGL(k_jbase, dim3(nb), dim3(256), 0, s, d.n_vals, d.n_tri, d.vslot, d.slot_ptr, d.slot_src,
+                       d.mat, pr->lawtab, d.k0, d.mval, 1.0 / dt, sc.jbase);
+    FineArgs a = make_fine_args(pr, p, U, F);
+    a.vec = sc.vec;
+    a.pcg = sc.pcg;
+    a.jac = sc.jac;
+    a.elem = sc.elem;
+    a.nl_pad = sc.nl_pad;
+    a.jbase = sc.jbase;
+    a.count = sc.count;
+    a.n_pad = sc.n_pad;
+    a.vals_pad = sc.vals_pad;
+    const FineShape sh = fine_shape(pr, p);
+    if (p->precision == 0)
+        launch_typed<double>(a, p->N, sh, s);
+    else
+        launch_typed<float>(a, p->N, sh, s);
+    PPC_HIP(hipGetLastError());
+}
+
 namespace {
 
 template <int R, int LP>

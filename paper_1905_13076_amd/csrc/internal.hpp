@@ -352,6 +352,25 @@ FineArgs make_fine_args(ppc_problem* pr, const ppc_params* p, const double* U, d
 FineShape fine_shape(const ppc_problem* pr, const ppc_params* p);
 void launch_fine_sweep_traj(ppc_problem* pr, const ppc_params* p, const double* U, double* F,
                             double* traj, hipStream_t s);
+// The per-sweep buffers of one fine sweep (base Jacobian, chain vectors, PCG vectors,
+// Jacobian values, Brauer element planes, chain counters) placed in one caller-provided
+// device region instead of the problem's workspace.
+struct FineScratch {
+    double* jbase = nullptr;
+    double* vec = nullptr;
+    void* pcg = nullptr;
+    void* jac = nullptr;
+    double* elem = nullptr;
+    int* count = nullptr;
+    long n_pad = 0, vals_pad = 0, nl_pad = 0;
+};
+// Lays the buffers out from `base` (256-byte aligned regions) and returns the bytes they
+// take; with base == nullptr only the size is computed.
+size_t fine_scratch_layout(const ppc_problem* pr, const ppc_params* p, unsigned char* base, FineScratch* out);
+// The fine sweep of launch_fine_sweep (same kernels and shapes) on those buffers: the base
+// Jacobian is rebuilt into sc.jbase, nothing is allocated.
+void launch_fine_sweep_in(ppc_problem* pr, const ppc_params* p, const double* U, double* F,
+                          const FineScratch& sc, hipStream_t s);
 // register-row workgroup sizes the library builds, and the shape one of them gives a mesh
 // (R = 0 when its rows do not fit registers and LDS at that size)
 constexpr int kRowBlocks[3] = {256, 512, 1024};

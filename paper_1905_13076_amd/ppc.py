@@ -226,6 +226,22 @@ class Problem:
             raise _err(self.handle.h, rc)
         return F, newton, lin
 
+    def fine_sweep_noalloc(self, prm, U, F=None):
+        """ppc_fine_sweep_noalloc: the fine sweep of fine_sweep() on the library's static
+        device scratch (no device allocation by the library).  U, F: CUDA [N, n_nodes]
+        (F is allocated here when not given).  Returns (F, newton, lin)."""
+        import torch
+        shape = (prm.N, self.n_nodes)
+        if F is None:
+            F = torch.empty(shape, dtype=torch.float64, device=U.device)
+        newton = np.zeros(prm.N, dtype=np.int32)
+        lin = np.zeros(prm.N, dtype=np.int32)
+        rc = lib().ppc_fine_sweep_noalloc(self.handle.h, self.p, byref(prm), _dev_ptr(U, shape),
+                                          _dev_ptr(F, shape), _pi(newton), _pi(lin), _stream())
+        if rc < 0:
+            raise _err(self.handle.h, rc)
+        return F, newton, lin
+
     def fine_counts(self, N):
         """Per-chain counters of the last fine sweep, int32 [N, 8]: status, Newton and PCG
         iterations, largest Newton / PCG count, capped PCG solves, failing step, residual
