@@ -90,6 +90,13 @@ typedef struct {
     const double* phase;    /* host, [n_h] (rad) */
 } ppc_excitation;
 
+/* Progress of a long solve: called on the host thread running ppc_solve /
+ * ppc_solve_device after each fine sweep, with m (the fine steps per subinterval of the
+ * solve in progress: a nested start reports its coarser grid first), the iteration k,
+ * eps^k (for a batch the largest over the designs still iterating) and the number of
+ * designs still iterating (1 for a single design).  It must not call into the library. */
+typedef void (*ppc_progress_fn)(int32_t m, int32_t iteration, double eps, int32_t active, void* user);
+
 /* Solver parameters.  Fill with ppc_params_default() and override. */
 typedef struct {
     double T;               /* period (s), > 0 (Section 2) */
@@ -166,6 +173,15 @@ typedef struct {
                                corrections (x0 in their span minimising the J-norm error; the
                                same solution to the PCG tolerance, fewer iterations); 1 = zero.
                                The adjoint's solves start from zero */
+    int32_t lin_forcing;    /* tolerance of each fine-step PCG solve: 0 = tol_lin relative to
+                               ||R||; 1 = forcing terms: after a step that needed several Newton
+                               iterations the first solve is held to max(tol_lin, 1e-3), later
+                               ones to eta = 0.9 (||R_k|| / ||R_{k-1}||)^2 (safeguarded, within
+                               [tol_lin, 0.1]), so that linear solves are not pushed far below
+                               what the Newton step can use.  Always at least 0.5 tol_newton
+                               scale; the step is solved to tol_newton either way */
+    ppc_progress_fn progress; /* null (default) or the progress callback of ppc_solve */
+    void* progress_user;      /* passed to progress unchanged */
 } ppc_params;
 
 /* Counters and timings of the last solve (all chains, all iterations). */
@@ -239,8 +255,9 @@ int ppc_problem_create(ppc_handle* h, const ppc_mesh* mesh, const ppc_material* 
  * one COCG launch; each design stops at its own eps <= tol_ppc.  Batched layouts:
  * U_init / U_out are the designs' [N * n_nodes_d] blocks concatenated in design order;
  * resid_out is [n_designs][max_iters + 1]; iters_out is [n_designs]; stats are summed
- * (eps: the largest final eps).  ppc_fine_sweep_device and ppc_coarse_correction_device
- * reject batched problems (PPC_ERR_ARG). */
+ * (eps: the largest final eps).  ppc_fine_sweep_device runs a batched sweep of every
+ * design; ppc_coarse_correction_device, ppc_fine_sweep_noalloc and ppc_fine_counts reject
+ * batched problems (PPC_ERR_ARG). */
 int ppc_problem_create_batch(ppc_handle* h, int32_t n_designs, const ppc_mesh* meshes,
                              const ppc_material* mats, const ppc_excitation* excs,
                              ppc_problem** out);
@@ -337,7 +354,10 @@ int ppc_adjoint(ppc_handle* h, ppc_problem* pr, const ppc_params* p, const doubl
 /* One fine sweep (Section 2, eqs. (2)-(3)): F_out[n mod N] = F_n(U_in[n-1]) for
  * n = 1..N, all chains in one launch.  U_in / F_out are DEVICE pointers
  * [N * n_nodes]; newton_out / lin_out are host [N] or null (per-chain Newton and PCG
- * iteration totals).  Returns PPC_ERR_NEWTON / PPC_ERR_NONFINITE if a chain failed. */
+ * iteration totals).  On a batched problem every design's chains run in one batched
+ * launch per kernel shape; U_in / F_out then hold design d's N x n_nodes_d rows after
+ * those of design d - 1 (the layout of ppc_solve on a batch), newton_out / lin_out are
+ * [n_designs * N].  Returns PPC_ERR_NEWTON / PPC_ERR_NONFINITE if a chain failed. */
 int ppc_fine_sweep_device(ppc_handle* h, ppc_problem* pr, const ppc_params* p,
                           const double* U_in_dev, double* F_out_dev, int32_t* newton_out,
                           int32_t* lin_out, void* stream);

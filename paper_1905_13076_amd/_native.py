@@ -44,6 +44,10 @@ class Excitation(ctypes.Structure):
                 ("phase", PD)]
 
 
+# void (*)(int32 m, int32 iteration, double eps, int32 active, void* user)
+PROGRESS = ctypes.CFUNCTYPE(None, c_int32, c_int32, c_double, c_int32, c_void_p)
+
+
 class Params(ctypes.Structure):
     _fields_ = [("T", c_double), ("N", c_int32), ("m", c_int32), ("shift_mode", c_int32),
                 ("lin_mode", c_int32), ("init_mode", c_int32), ("precision", c_int32),
@@ -52,7 +56,8 @@ class Params(ctypes.Structure):
                 ("tol_cocg", c_double), ("max_cocg", c_int32), ("block", c_int32),
                 ("no_predictor", c_int32), ("lin_point", c_int32), ("coarse_precision", c_int32),
                 ("graph", c_int32), ("method", c_int32), ("fine_block", c_int32), ("n_harm", c_int32),
-                ("b_cap", c_double), ("coarse_mode", c_int32), ("lin_start", c_int32)]
+                ("b_cap", c_double), ("coarse_mode", c_int32), ("lin_start", c_int32),
+                ("lin_forcing", c_int32), ("progress", PROGRESS), ("progress_user", c_void_p)]
 
 
 class Stats(ctypes.Structure):

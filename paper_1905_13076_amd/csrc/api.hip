@@ -473,6 +473,7 @@ int solve_device(ppc_handle* h, ppc_problem* pr, const ppc_params* p, const doub
         if (resid_out) resid_out[k] = eps;
         S.eps = eps;
         S.jump = std::sqrt(j0);
+        if (p->progress) p->progress(p->m, k, eps, 1, p->progress_user);
         if (eps <= p->tol_ppc) {
             status = PPC_OK;
             break;
@@ -772,6 +773,7 @@ int solve_batch_device(ppc_handle* h, ppc_problem* bp, const ppc_params* p, cons
         PPC_HIP(hipStreamSynchronize(s));
         S.fine_ms += elapsed(ev[0], ev[1]);
         std::vector<int> next;
+        double eps_k = 0.0;       // the largest eps of this iteration's designs
         for (int d = 0; d < D; ++d) {
             if (!active[d]) continue;
             std::copy(cnt_p.p + 8 * (size_t)N * d, cnt_p.p + 8 * (size_t)N * (d + 1), counts.begin());
@@ -781,6 +783,7 @@ int solve_batch_device(ppc_handle* h, ppc_problem* bp, const ppc_params* p, cons
             const double eps = uu > 0.0 ? std::sqrt(jj) / std::sqrt(uu) : (jj == 0.0 ? 0.0 : INFINITY);
             if (resid_out) resid_out[(size_t)d * R1 + k] = eps;
             S.eps = std::max(S.eps, eps);
+            eps_k = std::max(eps_k, eps);
             if (eps <= p->tol_ppc) {
                 active[d] = 0;
                 iters[d] = k;
@@ -788,6 +791,7 @@ int solve_batch_device(ppc_handle* h, ppc_problem* bp, const ppc_params* p, cons
                 next.push_back(d);
             }
         }
+        if (p->progress) p->progress(p->m, k, eps_k, (int)next.size(), p->progress_user);
         if (next.empty()) break;
         PPC_HIP(hipEventRecord(ev[2], s));
         std::vector<char> cset(D, 0);
@@ -1060,6 +1064,9 @@ int ppc_params_default(ppc_params* p) {
     p->b_cap = 0.0;
     p->coarse_mode = 0;
     p->lin_start = 0;
+    p->lin_forcing = 0;
+    p->progress = nullptr;
+    p->progress_user = nullptr;
     return PPC_OK;
 }
 
@@ -1330,9 +1337,38 @@ int ppc_fine_sweep_device(ppc_handle* h, ppc_problem* pr, const ppc_params* p, c
         check_handle_problem(h, pr);
         check_params(p);
         if (!U_in_dev || !F_out_dev) fail(PPC_ERR_ARG, "null U_in or F_out");
-        if (pr->batch) fail(PPC_ERR_ARG, "single-design entry point called with a batch problem");
         PPC_HIP(hipSetDevice(h->device));
         hipStream_t s = pick_stream(h, stream);
+        if (pr->batch) {
+            // every design's chains in one batched launch per kernel shape; U / F in the
+            // layout of the batched solve (design d's N x n_nodes_d rows after design d-1's)
+            auto& parts = pr->parts;
+            const int D = (int)parts.size(), N = p->N;
+            std::vector<size_t> off(D + 1, 0);
+            for (int d = 0; d < D; ++d) {
+                ensure_workspace(parts[d], p);
+                off[d + 1] = off[d] + (size_t)N * parts[d]->mesh.n_nodes;
+                launch_to_free(parts[d], N, U_in_dev + off[d], parts[d]->ws.U, s);
+            }
+            FineBatch fb;
+            fine_batch_prepare(fb, parts, p, s);
+            fine_batch_launch(fb, std::vector<char>(D, 1), s);
+            PPC_HIP(hipStreamSynchronize(s));
+            for (int d = 0; d < D; ++d) {
+                std::vector<int32_t> nw(N), ln(N);
+                const SweepCounts c = read_chain_counts(parts[d], N, s, nw.data(), ln.data());
+                if (c.status != 0)
+                    fail(c.status, "design " + std::to_string(d) + ", fine chain " + std::to_string(c.fail_chain + 1) +
+                                       " failed at step " + std::to_string(c.fail_step));
+                for (int k = 0; k < N; ++k) {
+                    if (newton_out) newton_out[(size_t)d * N + k] = nw[k];
+                    if (lin_out) lin_out[(size_t)d * N + k] = ln[k];
+                }
+                launch_to_nodal(parts[d], N, parts[d]->ws.F, F_out_dev + off[d], s);
+            }
+            PPC_HIP(hipStreamSynchronize(s));
+            return PPC_OK;
+        }
         ensure_workspace(pr, p);
         launch_to_free(pr, p->N, U_in_dev, pr->ws.U, s);
         launch_fine_sweep(pr, p, pr->ws.U, pr->ws.F, s);

@@ -498,7 +498,8 @@ __device__ __forceinline__ void cocg_ell_body(const CocgArgs& a, const int hp, d
         const double2 tkv = buffer_load<double2>(rtk, tid < t_len ? tid * 16u : kBufferNone);
         const unsigned tcol = (unsigned)__builtin_amdgcn_raw_buffer_load_b32(rtc, tid < t_len ? tid * 4u : kBufferNone, 0, 0);
         // q = (Kbar + sigma M) p in rounds of 4 complex loads: U slots x KC row groups
-        constexpr int KC = R < 4 ? R : 4;
+        // (KC divides R: 4, 3, 2 or 1 row groups per round, U = 4 / KC slots)
+        constexpr int KC = R % 4 == 0 ? 4 : (R % 3 == 0 ? 3 : (R % 2 == 0 ? 2 : 1));
         constexpr int U = 4 / KC;
 #pragma unroll
         for (int k = 0; k < R; ++k) q[k] = make_double2(0.0, 0.0);
@@ -718,8 +719,11 @@ __device__ __forceinline__ void cocg_mixed_body(const CocgArgs& a, const int p, 
         block_sum_d<3>(v, lds, ph);
         float2 rho = make_float2((float)v[0], (float)v[1]);
         const double in2 = v[2];
-        double irr = in2;
-        while (irr > kInnerTol * kInnerTol * in2 && total < a.max_it) {
+        double irr = in2, best = in2;
+        // the iterations left are shared among the refinements left, so that an inner solve
+        // that FP32 cannot finish (ill-conditioned harmonics) leaves room for the next one
+        const int inner_end = total + max(1, (a.max_it - total) / (kMaxRefine - refine + 1));
+        while (irr > kInnerTol * kInnerTol * in2 && total < inner_end) {
             double m2[2] = {0.0, 0.0};
             for (int base = wave * RPW; base < n; base += nw * RPW) {
                 const int i = base + grp;
@@ -777,6 +781,8 @@ __device__ __forceinline__ void cocg_mixed_body(const CocgArgs& a, const int p, 
             if (irr <= kInnerTol * kInnerTol * in2) break;
             if (v2[0] == 0.0 && v2[1] == 0.0) { status = PPC_ERR_BREAKDOWN; break; }
             if (!isfinite(irr)) { status = PPC_ERR_NONFINITE; break; }
+            best = fmin(best, irr);
+            if (irr > 1e8 * best) break;          // FP32 recurrence diverging: refine from here
             const double2 be = cdiv(make_double2(v2[0], v2[1]), make_double2(rho.x, rho.y));
             const float2 beta = make_float2((float)be.x, (float)be.y);
             rho = make_float2((float)v2[0], (float)v2[1]);
@@ -787,12 +793,17 @@ __device__ __forceinline__ void cocg_mixed_body(const CocgArgs& a, const int p, 
             }
             __syncthreads();
         }
-        // x += ||r|| d ; r = b - A x in FP64
+        // x += ||r|| d ; r = b - A x in FP64.  A refinement that does not lower the FP64
+        // residual is taken back (x -= ||r|| d, residual recomputed) and ends the solve: the
+        // FP32 inner solves cannot resolve this system any further.
         const double rsc = sqrt(rr);
+        bool stop = false;
+        double rr_new = rr;
+        for (int pass = 0; pass < 2; ++pass) {     // pass 1: take the refinement back
         for (int i = threadIdx.x; i < n; i += blockDim.x) {
             double2 xi = x[i];
-            xi.x += rsc * (double)xf[i].x;
-            xi.y += rsc * (double)xf[i].y;
+            xi.x += (pass ? -rsc : rsc) * (double)xf[i].x;
+            xi.y += (pass ? -rsc : rsc) * (double)xf[i].y;
             x[i] = xi;
         }
         __syncthreads();
@@ -827,7 +838,12 @@ __device__ __forceinline__ void cocg_mixed_body(const CocgArgs& a, const int p, 
             }
         }
         block_sum_d<1>(v3, lds, ph);
-        rr = v3[0];
+        rr_new = v3[0];
+        if (pass == 0 && rr_new < rr) break;       // progress: the refinement stays
+        if (pass == 1) stop = true;
+        }
+        rr = rr_new;
+        if (stop) break;
     }
     if (threadIdx.x == 0) {
         a.count[4 * p + 0] = status;
@@ -1131,7 +1147,7 @@ int cocg_ell_rows(const ppc_problem* pr, const CocgArgs& a, size_t& lds) {
     if (a.mixed || !d.ecol16) return 0;
     lds = (pr->ws.n_pad + (size_t)std::max(d.n_tail, 1)) * sizeof(double2);
     if (lds > kLdsBudget) return 0;
-    for (int R : {1, 2, 4, 8, 12})
+    for (int R : {1, 2, 3, 4, 5, 6, 7, 8, 12})
         if ((long)R * kCocgBlock >= d.n_free) return R;
     return 0;
 }
@@ -1181,7 +1197,11 @@ void launch_cocg_solves(const ppc_problem* pr, const CocgArgs& a, hipStream_t s)
     switch (cocg_ell_rows(pr, a, lds)) {
         case 1: launch_cocg_ell<1>(a, lds, s); break;
         case 2: launch_cocg_ell<2>(a, lds, s); break;
+        case 3: launch_cocg_ell<3>(a, lds, s); break;
         case 4: launch_cocg_ell<4>(a, lds, s); break;
+        case 5: launch_cocg_ell<5>(a, lds, s); break;
+        case 6: launch_cocg_ell<6>(a, lds, s); break;
+        case 7: launch_cocg_ell<7>(a, lds, s); break;
         case 8: launch_cocg_ell<8>(a, lds, s); break;
         case 12: launch_cocg_ell<12>(a, lds, s); break;
         default: hipLaunchKernelGGL(k_cocg, dim3(a.H), dim3(kCocgBlock), 0, s, a);
@@ -1249,7 +1269,7 @@ void cocg_batch_plan(const std::vector<ppc_problem*>& parts, const std::vector<i
                      int H, int2* d_work, CocgBatchPlan& plan, hipStream_t s) {
     plan.spans.clear();
     plan.cw.clear();
-    for (int R : {0, 1, 2, 4, 8, 12}) {
+    for (int R : {0, 1, 2, 3, 4, 5, 6, 7, 8, 12}) {
         CocgBatchPlan::Span sp{R, 0, (int)plan.cw.size(), 0};
         for (int d : list) {
             const CocgArgs a = make_cocg_args(parts[d], p);
@@ -1300,7 +1320,11 @@ void cocg_batch_run(const CocgBatchPlan& plan, const CocgArgs* d_args, const int
         switch (sp.R) {
             case 1: launch_cocg_ell_batch<1>(d_args, w, sp.count, sp.lds, sg); break;
             case 2: launch_cocg_ell_batch<2>(d_args, w, sp.count, sp.lds, sg); break;
+            case 3: launch_cocg_ell_batch<3>(d_args, w, sp.count, sp.lds, sg); break;
             case 4: launch_cocg_ell_batch<4>(d_args, w, sp.count, sp.lds, sg); break;
+            case 5: launch_cocg_ell_batch<5>(d_args, w, sp.count, sp.lds, sg); break;
+            case 6: launch_cocg_ell_batch<6>(d_args, w, sp.count, sp.lds, sg); break;
+            case 7: launch_cocg_ell_batch<7>(d_args, w, sp.count, sp.lds, sg); break;
             case 8: launch_cocg_ell_batch<8>(d_args, w, sp.count, sp.lds, sg); break;
             case 12: launch_cocg_ell_batch<12>(d_args, w, sp.count, sp.lds, sg); break;
             default: hipLaunchKernelGGL(k_cocg_batch, dim3(sp.count), dim3(kCocgBlock), 0, sg, d_args, w);

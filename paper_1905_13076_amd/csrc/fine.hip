@@ -171,6 +171,7 @@ FineArgs make_fine_args(ppc_problem* pr, const ppc_params* p, const double* U, d
     a.tail_col = d.tail_col;
     a.predictor = p->no_predictor == 0 ? 1 : 0;
     a.lin_start = p->lin_start;
+    a.lin_forcing = p->lin_forcing;
     a.traj = nullptr;
     return a;
 }

@@ -796,6 +796,7 @@ __device__ __forceinline__ void fine_chain(const FineArgs& a, const int c, unsig
     int status = 0, fail_step = -1;
     int newton_total = 0, lin_total = 0, newton_max = 0, lin_max = 0, capped = 0, resid_evals = 0;
     int n_solves = 0;                         // Newton solves of this chain (history slots filled)
+    int prev_newton = 1;                      // Newton iterations of the previous step
 
     for (int j = 1; j <= a.m && status == 0; ++j) {
         const double t = t0 + j * a.dt;
@@ -856,16 +857,31 @@ __device__ __forceinline__ void fine_chain(const FineArgs& a, const int c, unsig
         }
 
         int it = 0;
+        // forcing of the linear solves (lin_forcing 1): a step whose predecessor needed
+        // several Newton iterations sits in the nonlinear regime, where a tight first solve
+        // is wasted; later iterations follow the observed contraction (Eisenstat-Walker,
+        // choice 2: eta = 0.9 (||R_k|| / ||R_{k-1}||)^2, safeguarded by 0.9 eta_{k-1}^2),
+        // always within [tol_lin, 0.1]
+        double eta = (a.lin_forcing && prev_newton >= 2) ? fmax(a.tol_lin, 1e-3) : a.tol_lin;
+        double rn_last = rn;
         for (;; ++it) {
             if (rn <= target) break;
             if (it == a.max_newton) { status = PPC_ERR_NEWTON; fail_step = j; break; }
+            if (a.lin_forcing && it > 0) {
+                const double q = rn / rn_last;
+                double e = 0.9 * q * q;
+                const double sg = 0.9 * eta * eta;
+                if (sg > 0.1) e = fmax(e, sg);
+                eta = fmin(0.1, fmax(a.tol_lin, e));
+            }
+            rn_last = rn;
             assemble_nl<S>(a, el, jv);
             __syncthreads();
             if constexpr (R > 0) {
                 for (int i = threadIdx.x; i < n; i += blockDim.x) df_l[i] = (float)(1.0 / (double)jv[a.dpos[i]]);
                 __syncthreads();
             }
-            const double ltarget = fmax(a.tol_lin * rn, 0.5 * target);
+            const double ltarget = fmax(eta * rn, 0.5 * target);
             // FP32 PCG solves for the unit right-hand side -R/||R|| (near convergence the
             // residual and its products would fall below FP32's range); the step px * xs
             // is formed in FP64.  FP64 solves use R itself.
@@ -942,6 +958,7 @@ __device__ __forceinline__ void fine_chain(const FineArgs& a, const int c, unsig
         }
         newton_total += it;
         newton_max = it > newton_max ? it : newton_max;
+        prev_newton = it;
         if (Tc)
             for (int i = threadIdx.x; i < n; i += blockDim.x) Tc[(long)j * n + i] = u[i];
     }

@@ -240,6 +240,7 @@ struct FineArgs {
     int W, ntail, nvals;
     int predictor;
     int lin_start;          // 0: Galerkin start of the streaming PCG from the last corrections; 1: zero
+    int lin_forcing;        // 1: adaptive PCG tolerance per Newton iteration (forcing terms)
     double* traj;            // [N][m+1][n] fine trajectory of each chain, or null
     long ell_pad;
     const int* ecol;

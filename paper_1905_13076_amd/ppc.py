@@ -160,10 +160,13 @@ class Problem:
             pass
 
     # -- PP-PC solve ------------------------------------------------------------------------
-    def solve(self, prm, U_init=None, out=None):
+    def solve(self, prm, U_init=None, out=None, progress=None):
         """Periodic steady state on the device.  Returns (U [N, n_nodes] CUDA float64,
-        eps history (numpy), iterations, stats dict, status)."""
+        eps history (numpy), iterations, stats dict, status).  progress(m, k, eps, active),
+        if given, is called after every fine sweep (ppc_params.progress)."""
         import torch
+        if progress is not None:
+            return _with_progress(prm, progress, lambda: self.solve(prm, U_init, out))
         shape = (prm.N, self.n_nodes)
         if out is None:
             out = torch.empty(shape, dtype=torch.float64, device=f"cuda:{self.handle.device}")
@@ -331,6 +334,23 @@ class BatchProblem:
         except Exception:
             pass
 
+    def fine_sweep(self, prm, U):
+        """One batched fine sweep of every design (ppc_fine_sweep_device on the batch).
+        U: flat CUDA float64 [N * sum(n_nodes)] in the batched solve's layout.  Returns
+        (F flat, newton [D, N], lin [D, N])."""
+        import torch
+        total = prm.N * int(self.offsets[-1])
+        if U.numel() != total or U.dtype != torch.float64 or not U.is_contiguous() or U.device.type != "cuda":
+            raise ValueError(f"expected a contiguous float64 CUDA tensor of {total} values")
+        F = torch.empty_like(U)
+        newton = np.zeros((self.n_designs, prm.N), dtype=np.int32)
+        lin = np.zeros((self.n_designs, prm.N), dtype=np.int32)
+        rc = lib().ppc_fine_sweep_device(self.handle.h, self.p, byref(prm), c_void_p(U.data_ptr()),
+                                         c_void_p(F.data_ptr()), _pi(newton), _pi(lin), _stream())
+        if rc < 0:
+            raise _err(self.handle.h, rc)
+        return F, newton, lin
+
     def autotune(self, prm):
         """ppc_autotune by size class: (chosen size per design, ms [D, 3] of its class)."""
         b = np.zeros(self.n_designs, dtype=np.int32)
@@ -340,10 +360,13 @@ class BatchProblem:
             raise _err(self.handle.h, rc)
         return b, ms
 
-    def solve(self, prm, U_init=None):
+    def solve(self, prm, U_init=None, progress=None):
         """Returns (list of per-design U [N, n_nodes_d] CUDA views, eps [D, k+1] numpy,
-        iterations per design, stats dict, status)."""
+        iterations per design, stats dict, status).  progress(m, k, eps, active) as for
+        Problem.solve (eps: the largest of the iteration's designs)."""
         import torch
+        if progress is not None:
+            return _with_progress(prm, progress, lambda: self.solve(prm, U_init))
         total = int(self.offsets[-1])
         flat = torch.empty(prm.N * total, dtype=torch.float64, device=f"cuda:{self.handle.device}")
         resid = np.zeros((self.n_designs, prm.max_iters + 1), dtype=np.float64)
@@ -363,6 +386,16 @@ class BatchProblem:
             a, b = prm.N * int(self.offsets[d]), prm.N * int(self.offsets[d + 1])
             Us.append(flat[a:b].view(prm.N, int(self.n_nodes[d])))
         return Us, resid, iters, st.as_dict(), rc
+
+
+def _with_progress(prm, fn, call):
+    """Run call() with fn(m, k, eps, active) installed as prm.progress, then remove it."""
+    cb = nat.PROGRESS(lambda m, k, eps, active, user: fn(m, k, eps, active))
+    prm.progress = cb
+    try:
+        return call()
+    finally:
+        prm.progress = ctypes.cast(None, nat.PROGRESS)
 
 
 def problem_params(prob, **kw):

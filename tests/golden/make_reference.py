@@ -14,6 +14,8 @@ the nonlinear coarse problem of eq. (4), also storing one of its corrections (U_
 iteration 2); ``_routes`` steps period after
 period from zero (route S), its iteration count being the periods stepped.  ``c4subset``
 holds a seeded subset of the batched-designs generator on a short grid (see C4_SUBSET).
+``c3_sweep``, ``c3_coarse`` and ``c4_sweep`` hold sampled values of fine sweeps and a coarse
+correction at the large configurations' full mesh sizes (see LARGE_M).
 """
 from __future__ import annotations
 
@@ -79,6 +81,79 @@ def make_c4_subset(procs):
     print(f"wrote {path} in {time.time() - t:.1f}s")
 
 
+# Large cases, compared on sampled values: fine sweeps with m = 2 steps of the workloads' own
+# step size (C3: dt = 1e-6 over N = 200 chains; the batched designs: dt = 1e-5 over N = 40),
+# and one C3 coarse correction solving the harmonics p = 0, 1, 2 (the rest from the jumps).
+LARGE_M = 2
+C3_CHAINS = [1, 77, 200]
+C4_CHAINS = [1, 17, 40]
+# the sweep check adds the three designs with the most rings (nr 200, 199, 199: the streaming
+# memory path) to the subset
+C4_SWEEP_DESIGNS = C4_SUBSET + [213, 227, 206]
+
+
+def make_c3_sweep():
+    from oracle.timestep import fine_propagate
+    prob = coax.c3()
+    fe = FE(prob)
+    dt = prob.T / (prob.N * prob.m)
+    T = prob.N * LARGE_M * dt
+    U0 = coax.chain_starts(prob, fe.free, seed=3)
+    idx = coax.sample_index(fe.n, 4096, seed=31)
+    out = {"idx": idx, "chains": np.array(C3_CHAINS, dtype=np.int32), "m": LARGE_M, "T": T}
+    t = time.time()
+    for c in C3_CHAINS:
+        u = fine_propagate(fe, U0[c - 1], (c - 1) * T / prob.N, LARGE_M, dt)
+        out[f"F_{c}"] = u[idx]
+        out[f"norm_{c}"] = np.linalg.norm(u)
+        print(f"  [c3_sweep] chain {c}: t={time.time() - t:.0f}s", flush=True)
+    path = os.path.join(HERE, "c3_sweep_oracle.npz")
+    np.savez_compressed(path, **out)
+    print(f"wrote {path}")
+
+
+def make_c3_coarse():
+    prob = coax.c3()
+    fe = FE(prob)
+    U = coax.random_rows(prob.N, fe.n, seed=33, amp=2e-6)
+    J = coax.random_rows(prob.N, fe.n, seed=34, amp=1e-7)
+    t = time.time()
+    dU = periodic.coarse_correction(fe, U, J, n_harm=3)
+    rows = np.array([0, 57, 123], dtype=np.int32)
+    idx = coax.sample_index(fe.n, 4096, seed=35)
+    path = os.path.join(HERE, "c3_coarse_oracle.npz")
+    np.savez_compressed(path, rows=rows, idx=idx, dU=dU[rows][:, idx], norm=np.linalg.norm(dU),
+                        row_norms=np.linalg.norm(dU[rows], axis=1), n_harm=3)
+    print(f"wrote {path} in {time.time() - t:.0f}s")
+
+
+def make_c4_sweep():
+    from oracle.timestep import fine_propagate
+    designs = coax.c4_designs()
+    out = {"designs": np.array(C4_SWEEP_DESIGNS, dtype=np.int32), "chains": np.array(C4_CHAINS, dtype=np.int32),
+           "m": LARGE_M}
+    t = time.time()
+    for d in C4_SWEEP_DESIGNS:
+        prob = designs[d]
+        fe = FE(prob)
+        dt = prob.T / (prob.N * prob.m)
+        T = prob.N * LARGE_M * dt
+        U0 = coax.chain_starts(prob, fe.free, seed=1000 + d)
+        idx = coax.sample_index(fe.n, 1024, seed=2000 + d)
+        out[f"idx_{d}"] = idx
+        for c in C4_CHAINS:
+            u = fine_propagate(fe, U0[c - 1], (c - 1) * T / prob.N, LARGE_M, dt)
+            out[f"F_{d}_{c}"] = u[idx]
+            out[f"norm_{d}_{c}"] = np.linalg.norm(u)
+        print(f"  [c4_sweep] design {d} nr={prob.meta['nr']}: t={time.time() - t:.0f}s", flush=True)
+    path = os.path.join(HERE, "c4_sweep_oracle.npz")
+    np.savez_compressed(path, **out)
+    print(f"wrote {path}")
+
+
+LARGE = {"c3_sweep": make_c3_sweep, "c3_coarse": make_c3_coarse, "c4_sweep": make_c4_sweep}
+
+
 def make(name, procs):
     gen, kw, tol = CASES[name]
     prob = gen(**kw)
@@ -126,12 +201,14 @@ def make(name, procs):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("cases", nargs="*", default=list(CASES) + ["c4subset"])
+    ap.add_argument("cases", nargs="*", default=list(CASES) + ["c4subset"] + list(LARGE))
     ap.add_argument("--procs", type=int, default=min(8, os.cpu_count() or 1))
     a = ap.parse_args()
     for c in a.cases:
         if c == "c4subset":
             make_c4_subset(a.procs)
+        elif c in LARGE:
+            LARGE[c]()
         else:
             make(c, a.procs)
 

@@ -145,6 +145,7 @@ def test_invalid_problems_are_rejected_on_host(case, code, needle):
     (dict(coarse_mode=1, method=1), "coarse_mode"), (dict(coarse_mode=1, n_harm=3), "coarse_mode"),
     (dict(coarse_mode=1, b_cap=3.0), "coarse_mode"),
     (dict(lin_start=2), "lin_start"), (dict(lin_start=-1), "lin_start"),
+    (dict(lin_forcing=2), "lin_forcing"),
 ])
 def test_invalid_params_are_rejected_on_host(kw, needle):
     import paper_1905_13076_amd as P

@@ -94,10 +94,12 @@ def test_c1_coarse_correction_matches_oracle():
 
 
 @pytest.mark.parametrize("nr,ntheta,bar", [(12, 24, 1e-10), (30, 48, 1e-10), (48, 64, 1e-10),
-                                           (60, 100, 1e-10), (66, 132, 1e-10), (4, 1100, 1e-8)])
+                                           (40, 120, 1e-10), (60, 100, 1e-10), (60, 120, 1e-10),
+                                           (62, 124, 1e-10), (66, 132, 1e-10), (4, 1100, 1e-8)])
 def test_coarse_correction_row_shapes_match_oracle(nr, ntheta, bar):
-    """The FP64 harmonic solves for every register shape of the ELL COCG (1, 2, 4, 8 and 12
-    rows per thread) and for a centre row longer than a workgroup (the per-wave tail
+    """The FP64 harmonic solves for every register shape of the ELL COCG (1 to 8 and 12 rows
+    per thread: 265, 1,393, 3,009, 4,681, 5,901, 7,081, 7,565 and 8,581 rows) and for a
+    centre row longer than a workgroup (the per-wave tail
     form), against the oracle's direct per-harmonic solves.  COCG stops at a residual of
     1e-13 relative, so the solution error is that times the condition number: the
     1100-way centre fan of the last mesh (slivers of angle 2 pi / 1100) needs ~1700

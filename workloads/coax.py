@@ -271,3 +271,27 @@ def tiny(nr=4, ntheta=8, N=4, m=3, nonlinear=False, amp=None, sheath_sigma=2e6,
 
 
 CONFIGS = {"c1": c1, "c2": c2, "c3": c3, "c5": c5_small}
+
+
+def chain_starts(prob, free, seed, amp=1e-4):
+    """Seeded chain starts for fine-sweep parity cases, rows n = 0..N-1 over the free nodes
+    `free`: a radial profile amp (R - r)/R, R the outer radius, scaled per row by
+    1 + 0.1 g_n with g_n standard normal from default_rng(seed)."""
+    rng = np.random.default_rng(seed)
+    r = np.hypot(prob.xy[free, 0], prob.xy[free, 1])
+    R = float(np.hypot(prob.xy[:, 0], prob.xy[:, 1]).max())
+    return np.outer(1.0 + 0.1 * rng.standard_normal(prob.N), amp * (R - r) / R)
+
+
+def random_rows(N, n, seed, amp):
+    """Seeded samples for coarse-correction parity cases: amp times standard normal
+    values from default_rng(seed), shape [N, n]."""
+    return amp * np.random.default_rng(seed).standard_normal((N, n))
+
+
+def sample_index(n, count, seed):
+    """Sorted distinct indices into 0..n-1 at which large parity cases compare values:
+    index 0 (the centre node's row) plus count - 1 drawn by default_rng(seed)."""
+    rng = np.random.default_rng(seed)
+    pick = rng.choice(np.arange(1, n), size=min(count, n) - 1, replace=False)
+    return np.sort(np.concatenate([[0], pick])).astype(np.int64)
