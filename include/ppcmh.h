@@ -31,7 +31,7 @@
 extern "C" {
 #endif
 
-#define PPC_ABI_VERSION 3
+#define PPC_ABI_VERSION 4
 
 /* status codes */
 #define PPC_OK 0
@@ -168,10 +168,12 @@ typedef struct {
                                1e-14 ||C F||_F), each Newton step by flexible GMRES (at most 30
                                vectors) preconditioned by the frozen harmonic solve.  Not with
                                method 1, n_harm or b_cap; not for batched problems */
-    int32_t lin_start;      /* start of each fine-step PCG solve: 0 = the Galerkin projection
+    int32_t lin_start;      /* start of each fine-step PCG solve: 2 = the Galerkin projection
                                of the Newton system on the chain's last three Newton
                                corrections (x0 in their span minimising the J-norm error; the
-                               same solution to the PCG tolerance, fewer iterations); 1 = zero.
+                               same solution to the PCG tolerance, fewer iterations); 1 = zero;
+                               0 = by precision: the Galerkin start with FP64 PCG (precision
+                               0), zero with FP32 PCG (precision 1), whichever measured faster.
                                The adjoint's solves start from zero */
     int32_t lin_forcing;    /* tolerance of each fine-step PCG solve: 0 = tol_lin relative to
                                ||R||; 1 = forcing terms: after a step that needed several Newton
@@ -182,6 +184,16 @@ typedef struct {
                                scale; the step is solved to tol_newton either way */
     ppc_progress_fn progress; /* null (default) or the progress callback of ppc_solve */
     void* progress_user;      /* passed to progress unchanged */
+    double tol_adapt;       /* 0 (default): every fine sweep of ppc_solve solves its Newton steps
+                               to tol_newton.  theta > 0: the sweep of outer iteration k uses
+                               max(tol_newton, min(1e-6, theta eps_{k-1})), eps_{k-1} the
+                               previous iteration's ||J||_F / ||U||_F (1e-6 for the first
+                               sweep), so early iterations, whose iterate is still far from the
+                               fixed point, do not pay for fine solves far more accurate than
+                               that distance; once eps falls to tol_newton / theta the sweeps
+                               are the plain ones.  In [0, 1).  ppc_solve (each design of a
+                               batch by its own eps) only: ppc_fine_sweep and the adjoint's
+                               sweeps use tol_newton */
 } ppc_params;
 
 /* Counters and timings of the last solve (all chains, all iterations). */
@@ -347,7 +359,8 @@ int ppc_autotune(ppc_handle* h, ppc_problem* pr, const ppc_params* p, int32_t* b
  *   dsigma      host [n_tri] or null: dP/dsigma_e (per element)
  *   dbrauer     host [n_mat * 3] or null: dP/d(k1, k2, k3) per material (0 for linear)
  *   iters_out   host or null: adjoint coarse corrections applied
- * Single designs only (PPC_ERR_ARG for a batched problem). */
+ * With dsigma and dbrauer both null only the loss is computed (one forward replay, no
+ * adjoint iteration).  Single designs only (PPC_ERR_ARG for a batched problem). */
 int ppc_adjoint(ppc_handle* h, ppc_problem* pr, const ppc_params* p, const double* U_periodic,
                 double* loss, double* dsigma, double* dbrauer, int32_t* iters_out, ppc_stats* stats);
 

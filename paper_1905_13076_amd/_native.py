@@ -57,7 +57,8 @@ class Params(ctypes.Structure):
                 ("no_predictor", c_int32), ("lin_point", c_int32), ("coarse_precision", c_int32),
                 ("graph", c_int32), ("method", c_int32), ("fine_block", c_int32), ("n_harm", c_int32),
                 ("b_cap", c_double), ("coarse_mode", c_int32), ("lin_start", c_int32),
-                ("lin_forcing", c_int32), ("progress", PROGRESS), ("progress_user", c_void_p)]
+                ("lin_forcing", c_int32), ("progress", PROGRESS), ("progress_user", c_void_p),
+                ("tol_adapt", c_double)]
 
 
 class Stats(ctypes.Structure):

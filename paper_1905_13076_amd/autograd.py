@@ -2,8 +2,10 @@
 loss of the periodic steady state as a differentiable function of the element
 conductivities and the Brauer constants (k1, k2, k3) of every material.
 
-forward: copy the design with the given parameters to the device, solve its periodic
-steady state by PP-PC and run the adjoint (ppc_adjoint) for the loss and its gradient;
+forward: copy the design with the given parameters to the device (the library copies a
+design's materials at creation, so new parameters mean a new problem), solve its periodic
+steady state by PP-PC and evaluate the loss; when a gradient will be asked for, the same
+ppc_adjoint call runs the adjoint iteration for it, otherwise it stops after the loss;
 backward: scale the stored gradient.  All arithmetic runs in the HIP library."""
 from __future__ import annotations
 
@@ -38,11 +40,13 @@ class PeriodicEddyLoss(torch.autograd.Function):
             U, eps, k, st, rc = pr.solve(prm)
             if rc != 0:
                 raise RuntimeError(f"periodic solve did not converge (status {rc})")
-            loss, dsig, dk, kadj, _ = pr.adjoint(prm, U, len(prob.mat_model))
+            grads = bool(ctx.needs_input_grad[0] or ctx.needs_input_grad[1])
+            loss, dsig, dk, kadj, _ = pr.adjoint(prm, U, len(prob.mat_model), grads=grads)
         finally:
             pr.close()
-        ctx.save_for_backward(torch.as_tensor(dsig, dtype=sigma.dtype, device=sigma.device),
-                              torch.as_tensor(dk, dtype=brauer.dtype, device=brauer.device))
+        if grads:
+            ctx.save_for_backward(torch.as_tensor(dsig, dtype=sigma.dtype, device=sigma.device),
+                                  torch.as_tensor(dk, dtype=brauer.dtype, device=brauer.device))
         return torch.as_tensor(loss, dtype=sigma.dtype, device=sigma.device)
 
     @staticmethod

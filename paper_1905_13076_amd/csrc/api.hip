@@ -413,8 +413,12 @@ int solve_device(ppc_handle* h, ppc_problem* pr, const ppc_params* p, const doub
     // PP-IC: the first propagation starts from U_N = U^0_0
     if (ic) PPC_HIP(hipMemcpyAsync(w.ic_un, w.U, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
     GraphExec g_fine, g_coarse;
+    // adaptive Newton tolerance: each sweep reads the squared norms ||J||^2, ||U||^2 that
+    // the previous iteration's jump kernel left in w.scal; zero before the first sweep
+    const double* adapt = p->tol_adapt > 0.0 ? w.scal : nullptr;
+    if (adapt) PPC_HIP(hipMemsetAsync(w.scal, 0, 2 * sizeof(double), s));
     auto fine_ops = [&]() {
-        launch_fine_sweep(pr, p, w.U, w.F, s);
+        launch_fine_sweep(pr, p, w.U, w.F, s, adapt);
         launch_jumps(pr, N, w.U, w.F, w.J, w.scal, s);
         PPC_HIP(hipMemcpyAsync(w.host_scal, w.scal, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
         PPC_HIP(hipMemcpyAsync(w.host_fcount, w.fcount, 8 * (size_t)N * sizeof(int), hipMemcpyDeviceToHost, s));
@@ -678,8 +682,11 @@ int solve_batch_device(ppc_handle* h, ppc_problem* bp, const ppc_params* p, cons
     }
     coarse(coarse_init, true);
 
+    // adaptive Newton tolerance: each design's sweeps read the squared norms that the
+    // previous iteration's jump kernel left in scal (zero before the first sweep)
+    if (p->tol_adapt > 0.0) PPC_HIP(hipMemsetAsync(scal.p, 0, sizeof(double) * 3 * D, s));
     FineBatch fb;
-    fine_batch_prepare(fb, parts, p, s);
+    fine_batch_prepare(fb, parts, p, s, static_cast<const double*>(scal.p));
     if (!fine_init.empty()) {
         // one fine sweep from rest for these designs: U^0_n = F_n(0)
         std::vector<char> from_rest(D, 0);
@@ -971,6 +978,17 @@ int adjoint_device(ppc_handle* h, ppc_problem* pr, const ppc_params* p, const do
     check_sweep(read_chain_counts(pr, N, s, nullptr, nullptr));
     S.fine_launches++;
     launch_loss(pr, p, dtraj, static_cast<double*>(part.p), static_cast<double*>(out1.p), s);
+    if (!dsigma && !dbrauer) {
+        // the loss alone: no adjoint iteration
+        if (loss) PPC_HIP(hipMemcpyAsync(loss, out1.p, sizeof(double), hipMemcpyDeviceToHost, s));
+        PPC_HIP(hipEventRecord(ev[5], s));
+        PPC_HIP(hipStreamSynchronize(s));
+        S.total_ms = elapsed(ev[4], ev[5]);
+        S.status = PPC_OK;
+        if (iters_out) *iters_out = 0;
+        if (st) *st = S;
+        return PPC_OK;
+    }
     // backward PP-PC on the adjoint: Lambda_c = lambda_{cm+1}
     fill(dL, (long)N * n, 0.0, s);
     AdjArgs b{};
@@ -1067,6 +1085,7 @@ int ppc_params_default(ppc_params* p) {
     p->lin_forcing = 0;
     p->progress = nullptr;
     p->progress_user = nullptr;
+    p->tol_adapt = 0.0;
     return PPC_OK;
 }
 

@@ -170,9 +170,14 @@ FineArgs make_fine_args(ppc_problem* pr, const ppc_params* p, const double* U, d
     a.tail_ptr = d.tail_ptr;
     a.tail_col = d.tail_col;
     a.predictor = p->no_predictor == 0 ? 1 : 0;
-    a.lin_start = p->lin_start;
+    // 0 picks by precision: the Galerkin start pays in FP64 PCG, where solves run long
+    // enough for the saved iterations to outweigh its three Jacobian products, and
+    // costs time in FP32 PCG, whose looser solves save fewer iterations
+    a.lin_start = p->lin_start == 1 || (p->lin_start == 0 && p->precision != 0) ? 1 : 0;
     a.lin_forcing = p->lin_forcing;
     a.traj = nullptr;
+    a.adapt_scal = nullptr;
+    a.tol_adapt = p->tol_adapt;
     return a;
 }
 
@@ -198,9 +203,10 @@ FineShape fine_shape(const ppc_problem* pr, const ppc_params* p) {
 
 
 void launch_fine_sweep(ppc_problem* pr, const ppc_params* p, const double* U, double* F,
-                       hipStream_t s) {
+                       hipStream_t s, const double* adapt_scal) {
     ensure_jbase(pr, p, s);
-    const FineArgs a = make_fine_args(pr, p, U, F);
+    FineArgs a = make_fine_args(pr, p, U, F);
+    if (p->tol_adapt > 0.0) a.adapt_scal = adapt_scal;
     const FineShape sh = fine_shape(pr, p);
     if (p->precision == 0)
         launch_typed<double>(a, p->N, sh, s);
@@ -363,9 +369,10 @@ void FineBatch::release() {
     work_cap = 0;
 }
 
-// Upload one FineArgs per design (U / F are each design's own state arrays).
+// Upload one FineArgs per design (U / F are each design's own state arrays).  With
+// adapt_scal and params->tol_adapt, design d's sweeps read its jump norms at adapt_scal + 3 d.
 void fine_batch_prepare(FineBatch& b, const std::vector<ppc_problem*>& parts, const ppc_params* p,
-                        hipStream_t s) {
+                        hipStream_t s, const double* adapt_scal) {
     const int D = (int)parts.size();
     std::vector<FineArgs> host(D);
     b.shapes.resize(D);
@@ -373,6 +380,7 @@ void fine_batch_prepare(FineBatch& b, const std::vector<ppc_problem*>& parts, co
     for (int d = 0; d < D; ++d) {
         ensure_jbase(parts[d], p, s);
         host[d] = make_fine_args(parts[d], p, parts[d]->ws.U, parts[d]->ws.F);
+        if (adapt_scal && p->tol_adapt > 0.0) host[d].adapt_scal = adapt_scal + 3 * d;
         b.shapes[d] = fine_shape(parts[d], p);
         b.sizes.push_back(parts[d]->mesh.n_free);
     }

@@ -797,6 +797,16 @@ __device__ __forceinline__ void fine_chain(const FineArgs& a, const int c, unsig
     int newton_total = 0, lin_total = 0, newton_max = 0, lin_max = 0, capped = 0, resid_evals = 0;
     int n_solves = 0;                         // Newton solves of this chain (history slots filled)
     int prev_newton = 1;                      // Newton iterations of the previous step
+    // Newton tolerance of this sweep: fixed, or (adapt_scal set) loosened in proportion to
+    // the outer iteration's last relative jump, never looser than kAdaptCap; a first sweep
+    // (no jumps yet: ||U|| = 0) takes the cap
+    double tol_nt = a.tol_newton;
+    if (a.adapt_scal) {
+        const double jj = a.adapt_scal[0], uu = a.adapt_scal[1];
+        double e = (uu > 0.0 && jj >= 0.0) ? a.tol_adapt * sqrt(jj / uu) : kAdaptCap;
+        if (!(e <= kAdaptCap)) e = kAdaptCap;
+        tol_nt = fmax(tol_nt, e);
+    }
 
     for (int j = 1; j <= a.m && status == 0; ++j) {
         const double t = t0 + j * a.dt;
@@ -812,7 +822,7 @@ __device__ __forceinline__ void fine_chain(const FineArgs& a, const int c, unsig
         double v1[1] = {mass_prev(a, up, inv_dt, cp)};
         block_sum<double, 1>(v1, lds_d, ph_d);
         const double scale = fabs(cur) * a.fnorm + sqrt(v1[0]);
-        const double target = a.tol_newton * scale;
+        const double target = tol_nt * scale;
 
         nl_element_pass(a, u, el);
         ++resid_evals;

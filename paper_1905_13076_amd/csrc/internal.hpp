@@ -239,9 +239,14 @@ struct FineArgs {
     // ELL pattern of the fine-sweep SpMV
     int W, ntail, nvals;
     int predictor;
-    int lin_start;          // 0: Galerkin start of the streaming PCG from the last corrections; 1: zero
+    int lin_start;          // 0: Galerkin start of the PCG from the last corrections; 1: zero
     int lin_forcing;        // 1: adaptive PCG tolerance per Newton iteration (forcing terms)
     double* traj;            // [N][m+1][n] fine trajectory of each chain, or null
+    // tolerance that follows the outer iteration: with adapt_scal set (the squared norms
+    // ||J||^2, ||U||^2 of the previous iteration's jumps and iterate) each step's Newton
+    // tolerance is max(tol_newton, min(kAdaptCap, tol_adapt * ||J|| / ||U||))
+    const double* adapt_scal;
+    double tol_adapt;
     long ell_pad;
     const int* ecol;
     const unsigned short* ecol16;
@@ -319,7 +324,8 @@ struct CocgArgs {
 };
 
 constexpr int kFineVec = 9;   // u, u_prev, R, R_trial, u_{j-2}, trial state, M u_prev / dt, u_{j-3}, u_{j-4}
-constexpr int kHist = 3;      // Newton corrections kept for the Galerkin start of the streaming PCG
+constexpr int kHist = 3;      // Newton corrections kept for the Galerkin start of the PCG
+constexpr double kAdaptCap = 1e-6;   // loosest Newton tolerance of an adaptive fine sweep
 constexpr int kPcgVec = 5 + 2 * kHist;   // r, p, q, x, dinv, the corrections, their J products
 
 // set-up (setup.hip)
@@ -341,9 +347,9 @@ void ensure_workspace(ppc_problem* pr, const ppc_params* p);
 
 // fine sweep (fine.hip): F[n mod N] = F_n(U[n-1]) for all chains, one launch
 void launch_fine_sweep(ppc_problem* pr, const ppc_params* p, const double* U, double* F,
-                       hipStream_t s);
+                       hipStream_t s, const double* adapt_scal = nullptr);
 void fine_batch_prepare(FineBatch& b, const std::vector<ppc_problem*>& parts, const ppc_params* p,
-                        hipStream_t s);
+                        hipStream_t s, const double* adapt_scal = nullptr);
 void fine_batch_launch(FineBatch& b, const std::vector<char>& active, hipStream_t s);
 // the same in two parts: the work list of the active designs uploaded (synchronises), then
 // the kernel launches alone (what a captured graph replays)

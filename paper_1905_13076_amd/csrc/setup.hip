@@ -165,8 +165,12 @@ int validate_params(const ppc_params* p, std::string& msg) {
     if (!finite(p->tol_cocg) || !(p->tol_cocg > 0.0) || p->tol_cocg >= 1.0) { msg = "tol_cocg must be in (0, 1)"; return PPC_ERR_ARG; }
     if (p->max_cocg < 1) { msg = "max_cocg must be >= 1"; return PPC_ERR_ARG; }
     if (p->no_predictor < 0 || p->no_predictor > 1) { msg = "no_predictor must be 0 or 1"; return PPC_ERR_ARG; }
-    if (p->lin_start < 0 || p->lin_start > 1) { msg = "lin_start must be 0 or 1"; return PPC_ERR_ARG; }
+    if (p->lin_start < 0 || p->lin_start > 2) { msg = "lin_start must be 0, 1 or 2"; return PPC_ERR_ARG; }
     if (p->lin_forcing < 0 || p->lin_forcing > 1) { msg = "lin_forcing must be 0 or 1"; return PPC_ERR_ARG; }
+    if (!finite(p->tol_adapt) || p->tol_adapt < 0.0 || p->tol_adapt >= 1.0) {
+        msg = "tol_adapt must be in [0, 1)";
+        return PPC_ERR_ARG;
+    }
     if (p->lin_point < 0 || p->lin_point > 1) { msg = "lin_point must be 0 or 1"; return PPC_ERR_ARG; }
     if (p->block != 0 && (p->block < 64 || p->block > 1024 || (p->block % 64) != 0)) {
         msg = "block must be 0 or a multiple of 64 in [64, 1024]";

@@ -196,9 +196,10 @@ class Problem:
         return U, resid[: k + 1].copy(), k, st.as_dict(), rc
 
     # -- adjoint -------------------------------------------------------------------------------
-    def adjoint(self, prm, U_periodic, n_mat):
+    def adjoint(self, prm, U_periodic, n_mat, grads=True):
         """Loss and gradients at a periodic state U_periodic ([N, n_nodes], host array or
-        CUDA tensor).  Returns (loss, dP/dsigma [n_tri], dP/dk [n_mat, 3], iterations, stats)."""
+        CUDA tensor).  Returns (loss, dP/dsigma [n_tri], dP/dk [n_mat, 3], iterations, stats);
+        with grads=False only the loss (the gradients are returned as None)."""
         if hasattr(U_periodic, "detach"):
             U_periodic = U_periodic.detach().cpu().numpy()
         Uh = _f64(U_periodic)
@@ -209,10 +210,13 @@ class Problem:
         dk = np.zeros(3 * n_mat)
         iters = c_int32()
         st = nat.Stats()
-        rc = lib().ppc_adjoint(self.handle.h, self.p, byref(prm), _pd(Uh), _pd(loss), _pd(dsig), _pd(dk),
+        rc = lib().ppc_adjoint(self.handle.h, self.p, byref(prm), _pd(Uh), _pd(loss),
+                               _pd(dsig) if grads else None, _pd(dk) if grads else None,
                                byref(iters), byref(st))
         if rc < 0:
             raise _err(self.handle.h, rc)
+        if not grads:
+            return float(loss[0]), None, None, iters.value, st.as_dict()
         return float(loss[0]), dsig, dk.reshape(n_mat, 3), iters.value, st.as_dict()
 
     # -- single pieces ------------------------------------------------------------------------

@@ -36,7 +36,7 @@ def test_library_exports_every_declared_function():
     out = subprocess.run(["nm", "-D", "--defined-only", nat.LIB_PATH], capture_output=True, text=True).stdout
     exported = set(re.findall(r"\bT (ppc_\w+)", out))
     assert set(names) <= exported
-    assert lib.ppc_version() == 3
+    assert lib.ppc_version() == 4
 
 
 def test_struct_layout_matches_binding(tmp_path):
@@ -144,8 +144,9 @@ def test_invalid_problems_are_rejected_on_host(case, code, needle):
     (dict(coarse_mode=2), "coarse_mode"), (dict(coarse_mode=-1), "coarse_mode"),
     (dict(coarse_mode=1, method=1), "coarse_mode"), (dict(coarse_mode=1, n_harm=3), "coarse_mode"),
     (dict(coarse_mode=1, b_cap=3.0), "coarse_mode"),
-    (dict(lin_start=2), "lin_start"), (dict(lin_start=-1), "lin_start"),
+    (dict(lin_start=3), "lin_start"), (dict(lin_start=-1), "lin_start"),
     (dict(lin_forcing=2), "lin_forcing"),
+    (dict(tol_adapt=-1e-3), "tol_adapt"), (dict(tol_adapt=1.0), "tol_adapt"),
 ])
 def test_invalid_params_are_rejected_on_host(kw, needle):
     import paper_1905_13076_amd as P

@@ -118,3 +118,18 @@ def test_adjoint_c2_mixed_state_and_brauer_fd():
         fd = (vals[0] - vals[1]) / (2 * h)
         banner(f"  k{i + 1}: adjoint {dk64[1, i]:.6e} fd {fd:.6e}")
         assert abs(fd - dk64[1, i]) <= 1e-5 * abs(fd)
+
+
+def test_loss_alone_equals_the_loss_of_the_adjoint_run():
+    """ppc_adjoint with no gradient outputs stops after the loss; that loss is the same
+    number the full adjoint run returns."""
+    import paper_1905_13076_amd as P
+    prob = coax.tiny(nr=6, ntheta=12, N=8, m=5, nonlinear=True, amp=400.0)
+    prm = P.problem_params(prob, tol_ppc=1e-13)
+    pr = P.Problem(handle(), prob)
+    U, eps, k, st, rc = pr.solve(prm)
+    l1, g1, k1, it1, _ = pr.adjoint(prm, U, len(prob.mat_model), grads=True)
+    l0, g0, k0, it0, _ = pr.adjoint(prm, U, len(prob.mat_model), grads=False)
+    banner(f"loss alone {l0:.15e} with gradients {l1:.15e}; adjoint iterations {it1} / {it0}")
+    assert l0 == l1 and g0 is None and it0 == 0 and it1 > 0
+    pr.close()
