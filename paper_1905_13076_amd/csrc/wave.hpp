@@ -83,8 +83,16 @@ __device__ inline void block_sum(T (&v)[K], T* lds, int& phase) {
 // The hardware range check covers the lane offset (voffset) only, so callers put the
 // whole byte offset there: a load at an offset >= bytes returns 0 without a memory
 // access, and kBufferNone marks a lane that loads nothing.
+// base and bytes must be the same in every lane of the wave.  Taking them through
+// readfirstlane states that to the compiler: where it cannot prove it (arguments read from
+// a device array, counters of a loop whose exit depends on a reduction) it would otherwise
+// keep the descriptor in vector registers and wrap every load in a loop over lanes.
 __device__ inline __amdgpu_buffer_rsrc_t buffer_rsrc(const void* base, unsigned bytes) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)bytes, 0x00020000);
+    const unsigned long long p = reinterpret_cast<unsigned long long>(base);
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)p);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(p >> 32));
+    void* u = reinterpret_cast<void*>(((unsigned long long)hi << 32) | lo);
+    return __builtin_amdgcn_make_buffer_rsrc(u, 0, (int)__builtin_amdgcn_readfirstlane(bytes), 0x00020000);
 }
 
 constexpr unsigned kBufferNone = 0x80000000u;
