@@ -225,10 +225,17 @@ __device__ inline S tail_row_sum(const FineArgs& a, const S* __restrict__ jv, PV
     return acc;
 }
 
-// Jacobi-PCG on J x = -R for meshes that fit the CU: the rows of each thread
-// (i = tid + k B, k < R) keep x and q in registers; p, r and the inverse diagonal (FP32:
-// it only shapes the preconditioner) live in LDS, so the SpMV gathers and every vector
-// pass stay on the CU and only the ELL values and columns stream from memory.
+// Jacobi-PCG on J x = -R for meshes that fit the CU: the rows of each thread keep x and q in
+// registers; p, r and the inverse diagonal (FP32: it only shapes the preconditioner) live
+// in LDS, so the SpMV gathers and every vector pass stay on the CU and only the ELL values
+// and columns stream from memory.
+//
+// Rows go to threads in groups of G = 16 / sizeof(S) consecutive rows (2 in FP64, 4 in
+// FP32): group q of thread t is rows G (t + q B) .. G (t + q B) + G - 1, so one 16-byte load
+// brings a slot's values for the whole group and one 4- or 8-byte load its 16-bit columns,
+// and the vector passes move a group through LDS in one 16-byte access.  Load instructions,
+// not bytes, set the cost of this SpMV on the CU, so this halves it against a load per row.
+// The R - G (R / G) rows left over go one per thread after the groups (row G Q B + t + j B).
 //
 // With kh > 0 the iteration starts from x0 = sum_j cg_j V_j (hist: the chain's last Newton
 // corrections, wv: their products J V_j, both from galerkin_start): x starts there and r
@@ -239,15 +246,26 @@ __device__ int pcg_regs(const FineArgs& a, const S* __restrict__ jv, S* __restri
                         const double* __restrict__ Rres, double rs, S* xout, double tgt,
                         S* lds_s, int& ph, const S* hist = nullptr, const S* wv = nullptr, int kh = 0,
                         const double* cg = nullptr) {
+    constexpr int G = 16 / (int)sizeof(S);
+    constexpr int Q = R / G;                  // row groups per thread
+    constexpr int L = R - Q * G;              // single rows per thread
+    constexpr int QA = Q > 0 ? Q : 1, LA = L > 0 ? L : 1;
+    using SG = S __attribute__((ext_vector_type(G)));
+    using FG = float __attribute__((ext_vector_type(G)));
+    using U4 = unsigned __attribute__((ext_vector_type(4)));
+    using U2 = unsigned __attribute__((ext_vector_type(2)));
     const int tid = threadIdx.x, n = a.n;
     const int lane = tid & 63, wave = tid >> 6, nw = B >> 6;
     const long NP = a.ell_pad;
     const int W = a.W;
+    // register slot k holds row row_of(k): the groups' rows first, then the single rows
+    auto row_of = [&](int k) -> int {
+        return k < Q * G ? G * (tid + (k / G) * B) + k % G : G * Q * B + tid + (k - Q * G) * B;
+    };
     S x[R], q[R];
-    unsigned tailmask = 0;
+    unsigned tailmask = 0, padmask = 0;       // bit k: row_of(k) is a tail row / lies at or past n
     const __amdgpu_buffer_rsrc_t rv_j = buffer_rsrc(jv, (unsigned)(W * NP * sizeof(S)));
     const __amdgpu_buffer_rsrc_t rv_c = buffer_rsrc(a.ecol16, (unsigned)(W * NP * 2));
-    const __amdgpu_buffer_rsrc_t rv_cp = buffer_rsrc(a.ecolp, (unsigned)(((W + 1) / 2) * NP * 4));
     // One tail row of at most B entries (the usual case): every thread takes one of its
     // entries and the first block reduction of an iteration carries the row's product
     // with p.q, so no wave runs a serial row sum.  Otherwise one wave per tail row.
@@ -257,123 +275,126 @@ __device__ int pcg_regs(const FineArgs& a, const S* __restrict__ jv, S* __restri
     const int t_row = tail1 ? a.tail_row[0] : 0;
     const __amdgpu_buffer_rsrc_t rv_tv = buffer_rsrc(jv + W * NP + t_beg, (unsigned)(t_len * sizeof(S)));
     const __amdgpu_buffer_rsrc_t rv_tc = buffer_rsrc(a.tail_col + t_beg, (unsigned)(t_len * 4));
+    // rows at or past n: p, r and the diagonal's copies there are never read as data, but
+    // the group passes touch them, so r and p are written as zero and the diagonal masked
     S loc[2] = {0, 0};
 #pragma unroll
     for (int k = 0; k < R; ++k) {
-        const int i = tid + k * B;
+        const int i = row_of(k);
         x[k] = 0;
         q[k] = 0;
+        S rv = 0;
         if (i < n) {
-            S rv = (S)(-Rres[i] * rs);
+            rv = (S)(-Rres[i] * rs);
             for (int j = 0; j < kh; ++j) {
                 x[k] += (S)cg[j] * hist[j * NP + i];
                 rv -= (S)cg[j] * wv[j * NP + i];
             }
-            const S z = (S)d_l[i] * rv;
+            if (a.ecol[i] < 0) tailmask |= 1u << k;
+        } else {
+            padmask |= 1u << k;
+        }
+        const S z = i < n ? (S)d_l[i] * rv : (S)0;
+        if (k < Q * G ? i - k % G < n : i < n) {
             r_l[i] = rv;
             p_l[i] = z;
-            loc[0] += rv * z;
-            loc[1] += rv * rv;
-            if (a.ecol[i] < 0) tailmask |= 1u << k;
         }
+        loc[0] += rv * z;
+        loc[1] += rv * rv;
     }
     block_sum<S, 2, B / 64>(loc, lds_s, ph);
     S rz = loc[0];
     double rr = (double)loc[1];
     int it = 0;
+    // the diagonal of a row, zero past n
+    auto dg = [&](int k, float d) -> S { return ((padmask >> k) & 1u) ? (S)0 : (S)d; };
     while (rr > tgt * tgt && it < a.max_lin) {
         // this thread's tail entry: loads issued first, used after the ELL rounds
         const S tv = buffer_load<S>(rv_tv, tid < t_len ? tid * (unsigned)sizeof(S) : kBufferNone);
         const unsigned tc = (unsigned)__builtin_amdgcn_raw_buffer_load_b32(rv_tc, tid < t_len ? tid * 4u : kBufferNone, 0, 0);
-        // ELL rows, slot-major, all LDS gathers of a round issued before its FMAs.  Every
-        // load is issued: rows >= n load nothing and slots >= W fall past the ELL arrays,
-        // both reading value 0 and column 0; tail rows hold zero values and column 0.
-        // Every row adds its slots in order 0..W-1, then exact zeros.
 #pragma unroll
         for (int k = 0; k < R; ++k) q[k] = 0;
-        if constexpr (sizeof(S) == 4) {
-            // FP32: slot pairs, one 32-bit load bringing the columns of slots 2w (low half)
-            // and 2w+1 (high half), so a pair costs two value loads and one column load
-            // per row; UP pairs of all R row groups per round (at most 4 pairs in flight).
-            constexpr int UP = R >= 4 ? 1 : 4 / R;
-            const int W2 = (W + 1) / 2;
-            for (int w2 = 0; w2 < W2; w2 += UP) {
-                S v0[UP][R], v1[UP][R], g0[UP][R], g1[UP][R];
-                unsigned cw[UP][R];
+        // ELL slots in rounds of U, all loads of a round issued before its LDS gathers and
+        // those before its FMAs.  A group past n loads nothing; slots >= W fall past the ELL
+        // arrays; both read value 0 and column 0, as do the padded rows of a group that
+        // straddles n.  Tail rows hold zero values and column 0.  Every row adds its slots
+        // in order 0..W-1, then exact zeros.
+        constexpr int NL = Q + L;             // value loads per slot
+        constexpr int U = NL >= 4 ? 1 : 4 / NL;
+        for (int w0 = 0; w0 < W; w0 += U) {
+            SG vg[U][QA];
+            unsigned cg2[U][QA][G / 2];       // G 16-bit columns, two per word
+            S vs[U][LA], pg[U][R];
+            unsigned cs[U][LA];
 #pragma unroll
-                for (int u = 0; u < UP; ++u)
+            for (int u = 0; u < U; ++u) {
 #pragma unroll
-                    for (int k = 0; k < R; ++k) {
-                        const int i = tid + k * B;
-                        const unsigned e0 = (unsigned)((2 * (w2 + u)) * NP + i);
-                        const unsigned ep = (unsigned)((w2 + u) * NP + i);
-                        v0[u][k] = buffer_load<S>(rv_j, i < n ? e0 * (unsigned)sizeof(S) : kBufferNone);
-                        v1[u][k] = buffer_load<S>(rv_j, i < n ? (e0 + (unsigned)NP) * (unsigned)sizeof(S) : kBufferNone);
-                        cw[u][k] = (unsigned)__builtin_amdgcn_raw_buffer_load_b32(rv_cp, i < n ? ep * 4u : kBufferNone, 0, 0);
+                for (int g = 0; g < Q; ++g) {
+                    const int i0 = G * (tid + g * B);
+                    const unsigned e = (unsigned)((w0 + u) * NP + i0);
+                    vg[u][g] = __builtin_bit_cast(SG, __builtin_amdgcn_raw_buffer_load_b128(
+                                                          rv_j, i0 < n ? e * (unsigned)sizeof(S) : kBufferNone, 0, 0));
+                    if constexpr (G == 2) {
+                        cg2[u][g][0] = (unsigned)__builtin_amdgcn_raw_buffer_load_b32(rv_c, i0 < n ? e * 2u : kBufferNone, 0, 0);
+                    } else {
+                        const U2 c2 = __builtin_bit_cast(U2, __builtin_amdgcn_raw_buffer_load_b64(rv_c, i0 < n ? e * 2u : kBufferNone, 0, 0));
+                        cg2[u][g][0] = c2.x;
+                        cg2[u][g][1] = c2.y;
                     }
-                __builtin_amdgcn_sched_barrier(0);
+                }
 #pragma unroll
-                for (int u = 0; u < UP; ++u)
-#pragma unroll
-                    for (int k = 0; k < R; ++k) {
-                        g0[u][k] = p_l[cw[u][k] & 0xffffu];
-                        g1[u][k] = p_l[cw[u][k] >> 16];
-                    }
-                __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-                for (int u = 0; u < UP; ++u)
-#pragma unroll
-                    for (int k = 0; k < R; ++k) {
-                        q[k] += v0[u][k] * g0[u][k];
-                        q[k] += v1[u][k] * g1[u][k];
-                    }
+                for (int j = 0; j < L; ++j) {
+                    const int i = G * Q * B + tid + j * B;
+                    const unsigned e = (unsigned)((w0 + u) * NP + i);
+                    vs[u][j] = buffer_load<S>(rv_j, i < n ? e * (unsigned)sizeof(S) : kBufferNone);
+                    cs[u][j] = __builtin_amdgcn_raw_buffer_load_b16(rv_c, i < n ? e * 2u : kBufferNone, 0, 0);
+                }
             }
-        } else {
-            // FP64: one slot of 16-bit columns at a time, U slots of all R row groups per
-            // round (U R = 8 loads of each stream in flight).  Packed column pairs measure
-            // no faster here: the FP64 value stream dominates and the wider rounds cost
-            // registers.
-            constexpr int U = R >= 8 ? 1 : 8 / R;
-            for (int w0 = 0; w0 < W; w0 += U) {
-                S v[U][R], pg[U][R];
-                unsigned col[U][R];
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-                for (int u = 0; u < U; ++u)
+            for (int u = 0; u < U; ++u) {
 #pragma unroll
-                    for (int k = 0; k < R; ++k) {
-                        const int i = tid + k * B;
-                        const unsigned e = (unsigned)((w0 + u) * NP + i);
-                        v[u][k] = buffer_load<S>(rv_j, i < n ? e * (unsigned)sizeof(S) : kBufferNone);
-                        col[u][k] = __builtin_amdgcn_raw_buffer_load_b16(rv_c, i < n ? e * 2u : kBufferNone, 0, 0);
-                    }
-                __builtin_amdgcn_sched_barrier(0);
+                for (int g = 0; g < Q; ++g)
 #pragma unroll
-                for (int u = 0; u < U; ++u)
+                    for (int h = 0; h < G; ++h)
+                        pg[u][g * G + h] = p_l[(cg2[u][g][h >> 1] >> (16 * (h & 1))) & 0xffffu];
 #pragma unroll
-                    for (int k = 0; k < R; ++k) pg[u][k] = p_l[col[u][k]];
-                __builtin_amdgcn_sched_barrier(0);
+                for (int j = 0; j < L; ++j) pg[u][Q * G + j] = p_l[cs[u][j]];
+            }
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-                for (int u = 0; u < U; ++u)
+            for (int u = 0; u < U; ++u) {
 #pragma unroll
-                    for (int k = 0; k < R; ++k) q[k] += v[u][k] * pg[u][k];
+                for (int g = 0; g < Q; ++g)
+#pragma unroll
+                    for (int h = 0; h < G; ++h) q[g * G + h] += vg[u][g][h] * pg[u][g * G + h];
+#pragma unroll
+                for (int j = 0; j < L; ++j) q[Q * G + j] += vs[u][j] * pg[u][Q * G + j];
             }
         }
-        // FP32: this thread's rows of p (and below of z) stay in registers through the
-        // iteration, the LDS copy serving the other threads' gathers.  FP64 rereads them from
-        // LDS: the extra live registers cost more in spills than the reads save.
+        // p of this thread's rows: groups in one 16-byte LDS read each (a group past n
+        // reads nothing: it may lie beyond the arrays).  FP32 keeps them in registers
+        // through the iteration; FP64 rereads them from LDS after each reduction, since
+        // the extra live registers cost more in spills than the reads save.
         constexpr bool kCache = sizeof(S) == 4;
         S pc[R];
 #pragma unroll
-        for (int k = 0; k < R; ++k) {
-            const int i = tid + k * B;
-            if constexpr (kCache) pc[k] = i < n ? p_l[i] : (S)0;
+        for (int g = 0; g < Q; ++g) {
+            const int i0 = G * (tid + g * B);
+            SG v = (SG)(S)0;
+            if (i0 < n) v = *reinterpret_cast<const SG*>(p_l + i0);
+#pragma unroll
+            for (int h = 0; h < G; ++h) pc[g * G + h] = v[h];
+        }
+#pragma unroll
+        for (int j = 0; j < L; ++j) {
+            const int i = G * Q * B + tid + j * B;
+            pc[Q * G + j] = i < n ? p_l[i] : (S)0;
         }
         S dot[2] = {0, 0};
 #pragma unroll
-        for (int k = 0; k < R; ++k) {
-            const int i = tid + k * B;
-            if (i < n && !((tailmask >> k) & 1u)) dot[0] += (kCache ? pc[k] : p_l[i]) * q[k];
-        }
+        for (int k = 0; k < R; ++k)
+            if (!((tailmask >> k) & 1u)) dot[0] += pc[k] * q[k];
         if (tail1) {
             const S qt = tv * p_l[tc];
             dot[1] = qt;
@@ -392,19 +413,39 @@ __device__ int pcg_regs(const FineArgs& a, const S* __restrict__ jv, S* __restri
         if (!(pq > (S)0)) break;                 // loss of positivity: Newton decides
         const S alpha = rz / pq;
         S l2[2] = {0, 0};
-        S zc[R];
 #pragma unroll
-        for (int k = 0; k < R; ++k) {
-            const int i = tid + k * B;
-            if constexpr (kCache) zc[k] = 0;
+        for (int k = 0; k < R; ++k)
+            if ((tailmask >> k) & 1u) q[k] = tail1 ? dot[1] : tq_l[a.ecol[NP + row_of(k)]];
+        // x += alpha p, r -= alpha q, z = D r (z is kept in q: q is dead after r's update)
+#pragma unroll
+        for (int g = 0; g < Q; ++g) {
+            const int i0 = G * (tid + g * B);
+            if (i0 < n) {
+                SG rv = *reinterpret_cast<const SG*>(r_l + i0);
+                const FG dv = *reinterpret_cast<const FG*>(d_l + i0);
+                SG pv;
+                if constexpr (!kCache) pv = *reinterpret_cast<const SG*>(p_l + i0);
+#pragma unroll
+                for (int h = 0; h < G; ++h) {
+                    const int k = g * G + h;
+                    x[k] += alpha * (kCache ? pc[k] : pv[h]);
+                    rv[h] = rv[h] - alpha * q[k];
+                    q[k] = dg(k, dv[h]) * rv[h];
+                    l2[0] += rv[h] * q[k];
+                    l2[1] += rv[h] * rv[h];
+                }
+                *reinterpret_cast<SG*>(r_l + i0) = rv;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < L; ++j) {
+            const int k = Q * G + j, i = G * Q * B + tid + j * B;
             if (i < n) {
-                if ((tailmask >> k) & 1u) q[k] = tail1 ? dot[1] : tq_l[a.ecol[NP + i]];
                 x[k] += alpha * (kCache ? pc[k] : p_l[i]);
                 const S rv = r_l[i] - alpha * q[k];
                 r_l[i] = rv;
-                const S z = (S)d_l[i] * rv;
-                if constexpr (kCache) zc[k] = z;
-                l2[0] += rv * z;
+                q[k] = (S)d_l[i] * rv;
+                l2[0] += rv * q[k];
                 l2[1] += rv * rv;
             }
         }
@@ -414,13 +455,22 @@ __device__ int pcg_regs(const FineArgs& a, const S* __restrict__ jv, S* __restri
         if (rr <= tgt * tgt) break;
         const S beta = l2[0] / rz;
         rz = l2[0];
+        // p = z + beta p
 #pragma unroll
-        for (int k = 0; k < R; ++k) {
-            const int i = tid + k * B;
-            if (i < n) {
-                if constexpr (kCache) p_l[i] = zc[k] + beta * pc[k];
-                else p_l[i] = (S)d_l[i] * r_l[i] + beta * p_l[i];
+        for (int g = 0; g < Q; ++g) {
+            const int i0 = G * (tid + g * B);
+            if (i0 < n) {
+                SG pv;
+                if constexpr (!kCache) pv = *reinterpret_cast<const SG*>(p_l + i0);
+#pragma unroll
+                for (int h = 0; h < G; ++h) pv[h] = q[g * G + h] + beta * (kCache ? pc[g * G + h] : pv[h]);
+                *reinterpret_cast<SG*>(p_l + i0) = pv;
             }
+        }
+#pragma unroll
+        for (int j = 0; j < L; ++j) {
+            const int i = G * Q * B + tid + j * B;
+            if (i < n) p_l[i] = q[Q * G + j] + beta * (kCache ? pc[Q * G + j] : p_l[i]);
         }
         __syncthreads();
     }
@@ -428,7 +478,7 @@ __device__ int pcg_regs(const FineArgs& a, const S* __restrict__ jv, S* __restri
     // the Galerkin start reads in groups
 #pragma unroll
     for (int k = 0; k < R; ++k) {
-        const int i = tid + k * B;
+        const int i = row_of(k);
         if (i < NP) xout[i] = i < n ? x[k] : (S)0;
     }
     return it;
