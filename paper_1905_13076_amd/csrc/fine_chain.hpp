@@ -488,7 +488,7 @@ __device__ int pcg_regs(const FineArgs& a, const S* __restrict__ jv, S* __restri
 // (V^T J V) c = V^T b over the last kh Newton corrections V_j = hist + j n_pad; J V_j is kept
 // in wv + j n_pad.  Two passes (the products, then the Galerkin sums from the stored
 // vectors) keep the live registers of each near those of one SpMV pass.
-template <typename S>
+template <typename S, int NW = 0>
 __device__ inline void galerkin_start(const FineArgs& a, const S* __restrict__ jv, const S* hist, int kh,
                                       S* __restrict__ wv, S* __restrict__ tq_l,
                                       const double* __restrict__ Rres, double rs, double* lds_d, int& ph_d,
@@ -593,7 +593,7 @@ __device__ inline void galerkin_start(const FineArgs& a, const S* __restrict__ j
         double t4[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) t4[u] = q0 + u < NG ? gs[q0 + u] : 0.0;
-        block_sum<double, 4>(t4, lds_d, ph_d);
+        block_sum<double, 4, NW>(t4, lds_d, ph_d);
 #pragma unroll
         for (int u = 0; u < 4; ++u)
             if (q0 + u < NG) gs[q0 + u] = t4[u];
@@ -659,7 +659,7 @@ __device__ inline void galerkin_start(const FineArgs& a, const S* __restrict__ j
 // the Galerkin sums; a Cholesky factorisation that drops dependent directions gives c on
 // every thread alike; x0 and r0 = b - (J V) c follow in the initial pass.  The solution is
 // accumulated in xout, which may be the oldest history vector (read before it is written).
-template <typename S, int PL>
+template <typename S, int PL, int NW = 0>
 __device__ int pcg_stream(const FineArgs& a, const S* __restrict__ jv, S* __restrict__ pv,
                           S* __restrict__ p_l, S* __restrict__ tq_l, const double* __restrict__ Rres,
                           double rs, double tgt, S* lds_s, int& ph, S* xout, const S* hist, int kh,
@@ -686,7 +686,7 @@ __device__ int pcg_stream(const FineArgs& a, const S* __restrict__ jv, S* __rest
         return b;
     };
     double cg[kHist] = {0.0};
-    if (kh > 0) galerkin_start<S>(a, jv, hist, kh, wv, tq_l, Rres, rs, lds_d, ph_d, cg);
+    if (kh > 0) galerkin_start<S, NW>(a, jv, hist, kh, wv, tq_l, Rres, rs, lds_d, ph_d, cg);
     // ---- initial residual, diagonal, direction ------------------------------------------------
     S loc[2] = {0, 0};
     for (int g = tid; g < G; g += B) {
@@ -717,7 +717,7 @@ __device__ int pcg_stream(const FineArgs& a, const S* __restrict__ jv, S* __rest
             loc[1] += r[k] * r[k];
         }
     }
-    block_sum<S, 2>(loc, lds_s, ph);
+    block_sum<S, 2, NW>(loc, lds_s, ph);
     S rz = loc[0];
     double rr = (double)loc[1];
     int it = 0;
@@ -771,7 +771,7 @@ __device__ int pcg_stream(const FineArgs& a, const S* __restrict__ jv, S* __rest
 #pragma unroll
             for (int k = 0; k < V; ++k) dot[0] += pown[k] * acc[k];
         }
-        block_sum<S, 1>(dot, lds_s, ph);
+        block_sum<S, 1, NW>(dot, lds_s, ph);
         const S pqv = dot[0];
         if (!(pqv > (S)0)) break;                 // loss of positivity: Newton decides
         const S alpha = rz / pqv;
@@ -789,7 +789,7 @@ __device__ int pcg_stream(const FineArgs& a, const S* __restrict__ jv, S* __rest
                 l2[1] += r[k] * r[k];
             }
         }
-        block_sum<S, 2>(l2, lds_s, ph);
+        block_sum<S, 2, NW>(l2, lds_s, ph);
         ++it;
         rr = (double)l2[1];
         if (rr <= tgt * tgt) break;
@@ -870,7 +870,7 @@ __device__ __forceinline__ void fine_chain(const FineArgs& a, const int c, unsig
         __syncthreads();
         const double cur = current(t, a.f0, a.n_h, a.wavtab);
         double v1[1] = {mass_prev(a, up, inv_dt, cp)};
-        block_sum<double, 1>(v1, lds_d, ph_d);
+        block_sum<double, 1, BLOCK / 64>(v1, lds_d, ph_d);
         const double scale = fabs(cur) * a.fnorm + sqrt(v1[0]);
         const double target = tol_nt * scale;
 
@@ -878,7 +878,7 @@ __device__ __forceinline__ void fine_chain(const FineArgs& a, const int c, unsig
         ++resid_evals;
         __syncthreads();
         double v2[1] = {resid_rows(a, u, cp, el, cur, R_)};
-        block_sum<double, 1>(v2, lds_d, ph_d);
+        block_sum<double, 1, BLOCK / 64>(v2, lds_d, ph_d);
         double rn = sqrt(v2[0]);
         if (!isfinite(rn)) { status = PPC_ERR_NONFINITE; fail_step = j; break; }
         // Newton starts from the extrapolation of the previous steps (cubic
@@ -899,7 +899,7 @@ __device__ __forceinline__ void fine_chain(const FineArgs& a, const int c, unsig
             ++resid_evals;
             __syncthreads();
             double v4[1] = {resid_rows(a, ut, cp, el, cur, Rt)};
-            block_sum<double, 1>(v4, lds_d, ph_d);
+            block_sum<double, 1, BLOCK / 64>(v4, lds_d, ph_d);
             const double rp = sqrt(v4[0]);
             if (rp < rn) {
                 double* tmp = R_;
@@ -954,11 +954,11 @@ __device__ __forceinline__ void fine_chain(const FineArgs& a, const int c, unsig
             const int kh = a.lin_start == 0 ? (n_solves < kHist ? n_solves : kHist) : 0;
             if constexpr (R > 0) {
                 double cg[kHist] = {0.0};
-                if (kh > 0) galerkin_start<S>(a, jv, pv + P_H0 * NP, kh, pv + P_W0 * NP, tq_l, R_, rs, lds_d, ph_d, cg);
+                if (kh > 0) galerkin_start<S, BLOCK / 64>(a, jv, pv + P_H0 * NP, kh, pv + P_W0 * NP, tq_l, R_, rs, lds_d, ph_d, cg);
                 k = pcg_regs<S, R, BLOCK>(a, jv, p_l, r_l, df_l, tq_l, R_, rs, px, ltarget * rs, lds_s, ph_s,
                                           pv + P_H0 * NP, pv + P_W0 * NP, kh, cg);
             } else {
-                k = pcg_stream<S, LP>(a, jv, pv, p_l, tq_l, R_, rs, ltarget * rs, lds_s, ph_s, px, pv + P_H0 * NP,
+                k = pcg_stream<S, LP, BLOCK / 64>(a, jv, pv, p_l, tq_l, R_, rs, ltarget * rs, lds_s, ph_s, px, pv + P_H0 * NP,
                                       kh, pv + P_W0 * NP, lds_d, ph_d);
             }
             ++n_solves;
@@ -973,7 +973,7 @@ __device__ __forceinline__ void fine_chain(const FineArgs& a, const int c, unsig
                 nrm[0] += dv * dv;
                 nrm[1] += u[i] * u[i];
             }
-            block_sum<double, 2>(nrm, lds_d, ph_d);
+            block_sum<double, 2, BLOCK / 64>(nrm, lds_d, ph_d);
             if (sqrt(nrm[0]) <= 4.0 * DBL_EPSILON * sqrt(nrm[1])) {
                 for (int i = threadIdx.x; i < n; i += blockDim.x) u[i] = u[i] + (double)px[i] * xs;
                 __syncthreads();
@@ -990,7 +990,7 @@ __device__ __forceinline__ void fine_chain(const FineArgs& a, const int c, unsig
                 ++resid_evals;
                 __syncthreads();
                 double v3[1] = {resid_rows(a, ut, cp, el, cur, Rt)};
-                block_sum<double, 1>(v3, lds_d, ph_d);
+                block_sum<double, 1, BLOCK / 64>(v3, lds_d, ph_d);
                 rt = sqrt(v3[0]);
                 if (rt <= (1.0 - 1e-4 * lam) * rn) { accepted = true; break; }
                 lam *= 0.5;
@@ -1102,7 +1102,7 @@ __device__ __forceinline__ void adjoint_chain(const FineArgs& a, const AdjArgs& 
             y[i] = lam[i] * inv_dt + gcoef * ((uj[i] - ujm[i]) - (nx1[i] - nx0[i]));
         __syncthreads();
         double v[1] = {mass_apply_neg(a, y, rhs)};
-        block_sum<double, 1>(v, lds_d, ph_d);
+        block_sum<double, 1, BLOCK / 64>(v, lds_d, ph_d);
         const double rn = sqrt(v[0]);
         nl_element_pass(a, uj, el);
         __syncthreads();
@@ -1117,7 +1117,7 @@ __device__ __forceinline__ void adjoint_chain(const FineArgs& a, const AdjArgs& 
             if constexpr (R > 0)
                 k = pcg_regs<S, R, BLOCK>(a, jv, p_l, r_l, df_l, tq_l, rhs, 1.0, px, b.tol_lin * rn, lds_s, ph_s);
             else
-                k = pcg_stream<S, LP>(a, jv, pv, p_l, tq_l, rhs, 1.0, b.tol_lin * rn, lds_s, ph_s, px, pv, 0,
+                k = pcg_stream<S, LP, BLOCK / 64>(a, jv, pv, p_l, tq_l, rhs, 1.0, b.tol_lin * rn, lds_s, ph_s, px, pv, 0,
                                       pv, lds_d, ph_d);
         } else {
             for (int i = threadIdx.x; i < n; i += blockDim.x) px[i] = 0;

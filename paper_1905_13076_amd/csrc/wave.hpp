@@ -46,8 +46,10 @@ __device__ inline T wave_sum(T v) {
 }
 
 // Sum of K values over the workgroup in a fixed order; every thread gets the result.
-// NW > 0 states the wave count at compile time: the wave partials are then read as one
-// contiguous run per value and added as a pairwise tree; NW == 0 adds them in wave order.
+// NW > 0 states the wave count at compile time (NW <= 16, K <= 4): lane 16 k + j of every
+// wave then reads wave j's partial of value k, one LDS read per wave for all K values, and
+// each 16-lane row adds its partials by the DPP steps of wave_sum, so every wave forms the
+// same bits.  NW == 0 adds the partials in wave order.
 template <typename T, int K, int NW = 0>
 __device__ inline void block_sum(T (&v)[K], T* lds, int& phase) {
 #pragma unroll
@@ -58,18 +60,18 @@ __device__ inline void block_sum(T (&v)[K], T* lds, int& phase) {
 #pragma unroll
         for (int k = 0; k < K; ++k) buf[k * 16 + w] = v[k];
     __syncthreads();
+    if constexpr (NW > 0) {
+        static_assert(NW <= 16 && K <= 4, "one 64-lane read covers at most 4 values of 16 waves");
+        T t = (lane < 16 * K && (lane & 15) < NW) ? buf[lane] : (T)0;
+        t += dpp_mov<0xB1>(t);    // quad_perm [1,0,3,2]
+        t += dpp_mov<0x4E>(t);    // quad_perm [2,3,0,1]
+        t += dpp_mov<0x141>(t);   // row_half_mirror
+        t += dpp_mov<0x140>(t);   // row_mirror
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-        if constexpr (NW > 0) {
-            T t[NW];
+        for (int k = 0; k < K; ++k) v[k] = read_lane(t, 16 * k);
+    } else {
 #pragma unroll
-            for (int j = 0; j < NW; ++j) t[j] = buf[k * 16 + j];
-#pragma unroll
-            for (int h = NW / 2; h > 0; h >>= 1)
-#pragma unroll
-                for (int j = 0; j < h; ++j) t[j] = t[2 * j] + t[2 * j + 1];
-            v[k] = t[0];
-        } else {
+        for (int k = 0; k < K; ++k) {
             const int nw = blockDim.x >> 6;
             T s = 0;
             for (int j = 0; j < nw; ++j) s += buf[k * 16 + j];

@@ -42,11 +42,12 @@ def test_c1_linear_fp64_matches_oracle():
     assert e_l <= 1e-10 and e_p <= 1e-10
     # Dirichlet ring is exactly zero
     assert np.all(U.cpu().numpy()[:, prob.dirichlet] == 0.0)
-    # same iteration history as the oracle's PP-PC (same algorithm, same rounding level)
+    # same iteration history as the oracle's PP-PC (same algorithm)
     assert abs(k - k_o) <= 1
-    # (entries near the rounding floor differ in the last digits: absolute floor 1e-14)
+    # each fine step is solved only to the Newton tolerance, 1e-13 of its scale, so the
+    # jumps of two correct solvers agree to that level, not to rounding: absolute floor 1e-13
     L = min(len(eps), len(hist_o))
-    np.testing.assert_allclose(eps[:L], hist_o[:L], rtol=1e-6, atol=1e-14)
+    np.testing.assert_allclose(eps[:L], hist_o[:L], rtol=1e-6, atol=1e-13)
 
 
 def test_c1_fine_sweep_matches_oracle():
