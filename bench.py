@@ -127,6 +127,9 @@ def parse():
                          "3.6e-8 against 3.1e-8)")
     ap.add_argument("--probe-m", type=int, default=4,
                     help="probe mode on c3 / c4: fine steps per chain of the probed sweep")
+    ap.add_argument("--calibration-copy", action="store_true",
+                    help="copy 512 MiB device-to-device before the solves (untimed): the kernel of "
+                         "known size that scales rocprofv3's FETCH_SIZE / WRITE_SIZE of the same run")
     ap.add_argument("--probe", choices=["fine"], default=None,
                     help="counter-collection mode: a 512 MiB device copy of known size (the "
                          "calibration kernel) and one fine sweep from the oracle fixed point")
@@ -758,6 +761,11 @@ def main():
     from paper_1905_13076_amd.traffic import fine_sweep_bytes
 
     torch.cuda.set_device(0)
+    if a.calibration_copy:
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        torch.empty_like(src).copy_(src)
+        torch.cuda.synchronize()
+        del src
     h = P.Handle(0)
     t0 = time.perf_counter()
     pr = P.Problem(h, prob)
