@@ -131,6 +131,7 @@ FineArgs make_fine_args(ppc_problem* pr, const ppc_params* p, const double* U, d
     a.rowptr = d.rowptr;
     a.colidx = d.colidx;
     a.mval = d.mval;
+    a.mell = d.mell;
     a.fload = d.fload;
     a.lawtab = pr->lawtab;
     a.wavtab = pr->wavtab;

@@ -187,25 +187,40 @@ __device__ inline void init_jac(const FineArgs& a, S* __restrict__ jv) {
     for (int v = threadIdx.x; v < a.nvals; v += blockDim.x) jv[v] = (S)a.jbase[v];
 }
 
-// cp = M u_prev / dt (CSR, kRowGroup lanes per row, once per time step); returns the
-// partial ||cp||^2.
+// cp = M u_prev / dt (once per time step) by ELL rows in the form of resid_rows: every row
+// loads its W values of M (mell) and columns before its gathers, tail rows by one wave each;
+// returns the partial ||cp||^2.
 __device__ inline double mass_prev(const FineArgs& a, const double* __restrict__ up, double inv_dt,
                                    double* __restrict__ cp) {
-    constexpr int G = kRowGroup;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    const int sub = lane % G, grp = lane / G;
-    constexpr int RPW = 64 / G;
+    const long NP = a.ell_pad;
+    const int n = a.n, W = a.W;
     double part = 0.0;
-    for (int base = wave * RPW; base < a.n; base += nw * RPW) {
-        const int i = base + grp;
-        double acc = 0.0;
-        if (i < a.n) {
-            const int k1 = a.rowptr[i + 1];
-            for (int k = a.rowptr[i] + sub; k < k1; k += G) acc += a.mval[k] * up[a.colidx[k]];
-        }
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        int col[kEllMaxWidth];
+        double val[kEllMaxWidth];
 #pragma unroll
-        for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-        if (i < a.n && sub == 0) {
+        for (int w = 0; w < kEllMaxWidth; ++w) {
+            col[w] = w < W ? a.ecol[w * NP + i] : 0;
+            val[w] = w < W ? a.mell[w * NP + i] : 0.0;
+        }
+        if (col[0] < 0) continue;                 // tail row
+        double acc = 0.0;
+#pragma unroll
+        for (int w = 0; w < kEllMaxWidth; ++w)
+            if (w < W) acc += val[w] * up[col[w]];
+        const double v = acc * inv_dt;
+        cp[i] = v;
+        part += v * v;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const long base = (long)W * NP;
+    for (int t = wave; t < a.ntail; t += nw) {
+        double acc = 0.0;
+        const int j1 = a.tail_ptr[t + 1];
+        for (int j = a.tail_ptr[t] + lane; j < j1; j += 64) acc += a.mell[base + j] * up[a.tail_col[j]];
+        acc = wave_sum(acc);
+        if (lane == 0) {
+            const int i = a.tail_row[t];
             const double v = acc * inv_dt;
             cp[i] = v;
             part += v * v;

@@ -90,6 +90,7 @@ struct DeviceMesh {
     unsigned short* ecol16 = nullptr;   // same columns as 16-bit indices (n < 65536), tail rows 0
     unsigned* ecolp = nullptr; // [ceil(ell_w/2)][n_pad]: 16-bit columns of slots 2w (low) and 2w+1 (high)
     int* vslot = nullptr;      // [n_vals] CSR slot of each value position (-1: padding)
+    double* mell = nullptr;    // [n_vals] conductivity mass M at each value position (padding 0)
     int* dpos = nullptr;       // [n_free] value position of the diagonal
     int* tail_row = nullptr;   // [n_tail]
     int* tail_ptr = nullptr;   // [n_tail + 1]
@@ -236,6 +237,7 @@ struct FineArgs {
     const int* nlv_src;
     const int* nlf_ptr;
     const int* nlf_src;
+    const double* mell;     // [nvals] M in the ELL value order
     // ELL pattern of the fine-sweep SpMV
     int W, ntail, nvals;
     int predictor;

@@ -257,6 +257,15 @@ __global__ void k_load(int n, const int* __restrict__ node_ptr, const int* __res
     }
 }
 
+// M at each ELL value position: mell_v = M_{vslot_v} (0 for padding)
+__global__ void k_mell(int nvals, const int* __restrict__ vslot, const double* __restrict__ mval,
+                       double* __restrict__ mell) {
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < nvals; v += gridDim.x * blockDim.x) {
+        const int s = vslot[v];
+        mell[v] = s >= 0 ? mval[s] : 0.0;
+    }
+}
+
 __global__ void k_to_f32(int n, const double* __restrict__ x, float* __restrict__ y) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) y[i] = (float)x[i];
 }
@@ -585,6 +594,8 @@ void build_problem(ppc_problem* pr, const ppc_mesh* mesh, const ppc_material* ma
                        d.js, d.area, d.diag, d.mval, d.fload, d.mdiag);
     d.mval32 = dalloc<float>(nnz);
     hipLaunchKernelGGL(k_to_f32, dim3(grid_for(nnz, 256)), dim3(256), 0, s, nnz, d.mval, d.mval32);
+    d.mell = dalloc<double>((size_t)d.n_vals);
+    hipLaunchKernelGGL(k_mell, dim3(grid_for(d.n_vals, 256)), dim3(256), 0, s, d.n_vals, d.vslot, d.mval, d.mell);
     hipLaunchKernelGGL(k_norm2, dim3(1), dim3(1024), 0, s, n, d.fload, fn);
     PPC_HIP(hipGetLastError());
     PPC_HIP(hipMemcpyAsync(&d.fnorm, fn, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -595,7 +606,7 @@ void build_problem(ppc_problem* pr, const ppc_mesh* mesh, const ppc_material* ma
 void mesh_free(DeviceMesh& d) {
     void* ptrs[] = {d.rowptr, d.colidx, d.diag, d.slot_ptr, d.slot_src, d.node_ptr, d.node_src,
                     d.efree, d.free_node, d.mat, d.xy, d.tri, d.area, d.k0, d.gx, d.gy,
-                    d.sigma, d.js, d.mval, d.mval32, d.mdiag, d.fload, d.ecol, d.ecol16, d.ecolp, d.vslot, d.dpos,
+                    d.sigma, d.js, d.mval, d.mval32, d.mdiag, d.fload, d.ecol, d.ecol16, d.ecolp, d.vslot, d.mell, d.dpos,
                     d.tail_row, d.tail_ptr, d.tail_col, d.nl_elem, d.nl_efree, d.nl_mat, d.nl_area,
                     d.nl_k0, d.nlv_val, d.nlv_ptr, d.nlv_src, d.nlf_ptr, d.nlf_src};
     for (void* p : ptrs)
