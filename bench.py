@@ -250,7 +250,7 @@ def probe_fine(a, prob, ref):
     h = P.Handle(0)
     pr = P.Problem(h, prob)
     prec = 0 if a.precision == "fp64" else 1
-    prm = P.problem_params(prob, precision=prec, tol_newton=a.tol_newton,
+    prm = P.problem_params(prob, precision=prec, tol_newton=a.tol_newton, lin_start=a.lin_start,
                            **({"tol_lin": 1e-4} if prec == 1 else {}))
     U = np.zeros((prob.N, pr.n_nodes))
     U[:, ref["free"]] = ref["U"]

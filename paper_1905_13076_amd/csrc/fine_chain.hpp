@@ -963,10 +963,15 @@ __device__ __forceinline__ void fine_chain(const FineArgs& a, const int c, unsig
             const double rs = (sizeof(S) == 4 && rn > 0.0) ? 1.0 / rn : 1.0;
             const double xs = (sizeof(S) == 4 && rn > 0.0) ? rn : 1.0;
             int k;
-            // the solution goes to the oldest history slot; with lin_start 0 the last
-            // (at most kHist) corrections seed the start
-            px = pv + (long)(P_H0 + n_solves % kHist) * NP;
-            const int kh = a.lin_start == 0 ? (n_solves < kHist ? n_solves : kHist) : 0;
+            // the first Newton correction of a step goes to the oldest history slot, and with
+            // lin_start 0 the last (at most kHist) first corrections seed its solve.  Later
+            // corrections of a step refine that step: their right-hand sides are not the smooth
+            // continuation in time that the history spans (a start from its span measured up
+            // to twice the PCG iterations of the zero start on chains taking five Newton
+            // iterations per step), so they start from zero and are not kept.
+            const bool first = it == 0;
+            px = pv + (long)(first ? P_H0 + n_solves % kHist : P_X) * NP;
+            const int kh = (a.lin_start == 0 && first) ? (n_solves < kHist ? n_solves : kHist) : 0;
             if constexpr (R > 0) {
                 double cg[kHist] = {0.0};
                 if (kh > 0) galerkin_start<S, BLOCK / 64>(a, jv, pv + P_H0 * NP, kh, pv + P_W0 * NP, tq_l, R_, rs, lds_d, ph_d, cg);
@@ -976,7 +981,7 @@ __device__ __forceinline__ void fine_chain(const FineArgs& a, const int c, unsig
                 k = pcg_stream<S, LP, BLOCK / 64>(a, jv, pv, p_l, tq_l, R_, rs, ltarget * rs, lds_s, ph_s, px, pv + P_H0 * NP,
                                       kh, pv + P_W0 * NP, lds_d, ph_d);
             }
-            ++n_solves;
+            if (first) ++n_solves;
             __syncthreads();
             lin_total += k;
             lin_max = k > lin_max ? k : lin_max;
