@@ -165,7 +165,6 @@ FineArgs make_fine_args(ppc_problem* pr, const ppc_params* p, const double* U, d
     a.ell_pad = (long)d.ell_pad;
     a.ecol = d.ecol;
     a.ecol16 = d.ecol16;
-    a.ecolp = d.ecolp;
     a.dpos = d.dpos;
     a.tail_row = d.tail_row;
     a.tail_ptr = d.tail_ptr;

@@ -88,7 +88,6 @@ struct DeviceMesh {
     int n_vals = 0;            // value positions: ell_w * n_pad + tail_nnz
     int* ecol = nullptr;       // [ell_w][n_pad]; tail rows: ecol[0][i] = -1, ecol[1][i] = tail index
     unsigned short* ecol16 = nullptr;   // same columns as 16-bit indices (n < 65536), tail rows 0
-    unsigned* ecolp = nullptr; // [ceil(ell_w/2)][n_pad]: 16-bit columns of slots 2w (low) and 2w+1 (high)
     int* vslot = nullptr;      // [n_vals] CSR slot of each value position (-1: padding)
     double* mell = nullptr;    // [n_vals] conductivity mass M at each value position (padding 0)
     int* dpos = nullptr;       // [n_free] value position of the diagonal
@@ -252,7 +251,6 @@ struct FineArgs {
     long ell_pad;
     const int* ecol;
     const unsigned short* ecol16;
-    const unsigned* ecolp;
     const int* dpos;
     const int* tail_row;
     const int* tail_ptr;

@@ -544,15 +544,6 @@ void build_problem(ppc_problem* pr, const ppc_mesh* mesh, const ppc_material* ma
         std::vector<unsigned short> e16(ecol.size());
         for (size_t v = 0; v < ecol.size(); ++v) e16[v] = (unsigned short)(ecol[v] < 0 ? 0 : ecol[v]);
         d.ecol16 = upload(e16, s);
-        const int W2 = (W + 1) / 2;
-        std::vector<unsigned> ep((size_t)W2 * NP, 0u);
-        for (int w2 = 0; w2 < W2; ++w2)
-            for (size_t i = 0; i < NP; ++i) {
-                const unsigned lo = e16[(size_t)(2 * w2) * NP + i];
-                const unsigned hi = 2 * w2 + 1 < W ? e16[(size_t)(2 * w2 + 1) * NP + i] : 0u;
-                ep[(size_t)w2 * NP + i] = lo | (hi << 16);
-            }
-        d.ecolp = upload(ep, s);
     }
     d.vslot = upload(vslot, s);
     d.dpos = upload(dpos, s);
@@ -606,7 +597,7 @@ void build_problem(ppc_problem* pr, const ppc_mesh* mesh, const ppc_material* ma
 void mesh_free(DeviceMesh& d) {
     void* ptrs[] = {d.rowptr, d.colidx, d.diag, d.slot_ptr, d.slot_src, d.node_ptr, d.node_src,
                     d.efree, d.free_node, d.mat, d.xy, d.tri, d.area, d.k0, d.gx, d.gy,
-                    d.sigma, d.js, d.mval, d.mval32, d.mdiag, d.fload, d.ecol, d.ecol16, d.ecolp, d.vslot, d.mell, d.dpos,
+                    d.sigma, d.js, d.mval, d.mval32, d.mdiag, d.fload, d.ecol, d.ecol16, d.vslot, d.mell, d.dpos,
                     d.tail_row, d.tail_ptr, d.tail_col, d.nl_elem, d.nl_efree, d.nl_mat, d.nl_area,
                     d.nl_k0, d.nlv_val, d.nlv_ptr, d.nlv_src, d.nlf_ptr, d.nlf_src};
     for (void* p : ptrs)
