@@ -674,16 +674,34 @@ def bench_c3(a):
     return 0
 
 
+def seq_cpu_sample(prob, ref, tol_newton, steps=100):
+    """Route S of the oracle on one host core: `steps` implicit-Euler steps of one chain from
+    the oracle's periodic state, at the GPU's Newton tolerance."""
+    from oracle import periodic
+    from oracle.fe import FE
+    from oracle.timestep import fine_propagate
+    fe = FE(prob)
+    steps = min(steps, prob.N * prob.m)
+    t0 = time.perf_counter()
+    fine_propagate(fe, ref["U"][0], 0.0, steps, periodic.fine_dt(prob), tol=tol_newton)
+    return {"t_step_seq": (time.perf_counter() - t0) / steps, "seq_steps": steps, "tol_newton": tol_newton,
+            "host": host_info()}
+
+
 def bench_time_stepping(a):
     """Classical time stepping on the same GPU: one steady state = periods stepped from zero
     until two periods' samples agree to --tol; progress (one line per call of a few
-    periods) on stderr."""
+    periods) on stderr.  The roofline is the fine kernel's algorithmic rate over its
+    event-timed launches (one chain of a period each); the CPU baseline is the oracle's
+    route S on one core, extrapolated to the GPU's period count."""
+    prob = workload(a.workload)
+    ref = load_reference(a.workload)
+    smp = seq_cpu_sample(prob, ref, a.tol_newton) if (a.cpu and ref is not None) else None
     import numpy as np
     import torch
     import paper_1905_13076_amd as P
+    from paper_1905_13076_amd.traffic import fine_sweep_bytes
     torch.cuda.set_device(0)
-    prob = workload(a.workload)
-    ref = load_reference(a.workload)
     h = P.Handle(0)
     pr = P.Problem(h, prob)
     prec = 0 if a.precision == "fp64" else 1
@@ -691,6 +709,7 @@ def bench_time_stepping(a):
     prm = P.problem_params(prob, tol_ppc=a.tol, precision=prec, max_iters=chunk, tol_newton=a.tol_newton,
                            **({"tol_lin": 1e-4} if prec == 1 else {}))
     walls, periods_all, fine_ms = [], [], 0.0
+    tot = dict.fromkeys(("lin_total", "resid_total", "newton_total", "steps_total", "fine_launches"), 0)
     for step in range(a.warmup + a.steps):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -702,6 +721,8 @@ def bench_time_stepping(a):
             steps += st["steps_total"]
             if step >= a.warmup:
                 fine_ms += st["fine_ms"]
+                for k2 in tot:
+                    tot[k2] += st[k2]
             print(f"[seq] step {step} periods {total} change {st['eps']:.3e}", file=sys.stderr, flush=True)
             if rc == 0 or total >= 2000:
                 break
@@ -718,6 +739,30 @@ def bench_time_stepping(a):
         Ug = U.cpu().numpy()[:, ref["free"]]
         err = float(np.linalg.norm(Ug - ref["U"]) / np.linalg.norm(ref["U"]))
     wall = sum(walls)
+    tot.update(n_free=st["n_free"], nnz=st["nnz"], n_tri=st["n_tri"])
+    launches = max(1, tot["fine_launches"])
+    bytes_launch = fine_sweep_bytes(tot, 1, prec) / launches
+    launch_ms = fine_ms / launches
+    achieved = bytes_launch / (launch_ms * 1e-3) / 1e9 if launch_ms > 0 else None
+    roofline = {
+        "kernel": "k_fine_sweep (one chain per launch: one period of N m steps)",
+        "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+        "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": None,
+        "regime": ("one workgroup on one CU stepping a single chain; its working set is "
+                   "cache-resident, so 'achieved' is the algorithmic rate (the method's minimal "
+                   "streaming bytes over launch time), not DRAM traffic"),
+        "bytes_per_launch": bytes_launch, "launch_ms": launch_ms, "launches": launches,
+    }
+    cpu = None
+    if smp is not None:
+        per = periods_all[-1]
+        t_s = per * prob.N * prob.m * smp["t_step_seq"]
+        cpu = {"value": 1.0 / t_s, "unit": "steady states/s", "cores": 1, "kind": "oracle",
+               "sample": (f"route S: {smp['seq_steps']} sequential implicit-Euler steps of one chain "
+                          f"(Newton to {smp['tol_newton']:g}) at {smp['t_step_seq'] * 1e3:.1f} ms each, "
+                          f"extrapolated to the GPU's {per} periods of {prob.N * prob.m} steps = "
+                          f"{t_s:.1f} s per steady state"),
+               "host": smp["host"]}
     print(json.dumps({
         "metric": "periodic steady states/s at 1e-6 rel. err vs FP64 oracle; achieved HBM GB/s",
         "value": a.steps / wall, "unit": "steady states/s", "n_gpus": 1, "steps": a.steps,
@@ -729,14 +774,14 @@ def bench_time_stepping(a):
                    "method": "classical time stepping (one chain per period)", "precision": a.precision,
                    "tol": a.tol, "periods": periods_all[-1], "err_vs_oracle": err,
                    "newton_per_step": newton / max(1, steps), "fine_ms_per_state": fine_ms / a.steps},
-        "roofline": None, "cpu_baseline": None}), flush=True)
+        "roofline": roofline, "cpu_baseline": cpu}), flush=True)
     return 0
 
 
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU: the path has no collectives; "
+        print(json.dumps({"error": "bench.py runs on one GPU: the path has no collectives; "
                                    "run with --gpus 1"}))
         return 2
     if a.workload == "c4reg":

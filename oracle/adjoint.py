@@ -1,7 +1,7 @@
 """Adjoint gradients of the period-averaged eddy-current loss (oracle, FP64).
 
 The paper computes the periodic steady state (Section 2, eq. (1)); the loss and its
-sensitivities are this build's use of it, stated here from the discrete equations.
+sensitivities are an addition to it, stated here from the discrete equations.
 
 With L = N m implicit-Euler steps of the periodic fine solution (u_L = u_0),
     R_j(u_j, u_{j-1}; theta) = M (u_j - u_{j-1})/dt + K(u_j; theta) u_j - f(t_j) = 0,

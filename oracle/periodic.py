@@ -383,7 +383,7 @@ def brauer_bmax(fe, U):
 
 
 def safeguard_step(fe, U, dU, b_cap):
-    """Step theta of the correction U + theta dU (a safeguard of this build; the paper's
+    """Step theta of the correction U + theta dU (a safeguard the paper does not have: its
     coarse problem is not a frozen linearisation): theta = 1 when max |B(U + dU)| <= b_cap,
     else (b_cap - b_U) / (b_new - b_U) with b_U = max |B(U)|, the largest step for which
     |B| stays below the cap (B is linear in u, so |B(U + theta dU)| <= (1 - theta) b_U +
