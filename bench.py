@@ -921,11 +921,11 @@ def main():
             "regime": ("cache-resident: the chains' working set fits L2 / MALL, so 'achieved' is the "
                        "algorithmic rate (the method's minimal streaming bytes over launch time), not DRAM traffic; "
                        "dram_gbs is the counter-measured DRAM rate of the profiled launch"),
-            "traffic_source": ("rocprofv3 FETCH_SIZE+WRITE_SIZE (copy-calibrated) of one C2 fine sweep "
-                               "(50 steps per chain) from the oracle fixed point, "
-                               "profiles/fine_sweep_c2_fp64_counters.md; algorithmic bytes of that launch "
-                               f"{traffic['algorithmic_bytes_same_launch']} (the timed launches also "
-                               "include the nested start's 2-step sweeps)")
+            "traffic_source": ("rocprofv3 FETCH_SIZE+WRITE_SIZE (copy-calibrated), averaged over every "
+                               "fine-sweep launch of one benchmark steady state at these settings "
+                               "(the nested start's sweeps included), "
+                               "profiles/fine_sweep_c2_fp64_counters.md; algorithmic bytes per launch "
+                               f"there {traffic['algorithmic_bytes_same_launch']}")
                               if traffic else None,
             "bytes_per_launch": bytes_launch,
             "launch_ms": launch_s * 1e3,
