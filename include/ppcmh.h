@@ -168,10 +168,12 @@ typedef struct {
                                1e-14 ||C F||_F), each Newton step by flexible GMRES (at most 30
                                vectors) preconditioned by the frozen harmonic solve.  Not with
                                method 1, n_harm or b_cap; not for batched problems */
-    int32_t lin_start;      /* start of each fine-step PCG solve: 2 = the Galerkin projection
-                               of the Newton system on the chain's last three Newton
-                               corrections (x0 in their span minimising the J-norm error; the
-                               same solution to the PCG tolerance, fewer iterations); 1 = zero;
+    int32_t lin_start;      /* start of each fine-step PCG solve: 2 = for the first Newton
+                               correction of a step, the Galerkin projection of the Newton
+                               system on the chain's last three first corrections (x0 in their
+                               span minimising the J-norm error; the same solution to the PCG
+                               tolerance, fewer iterations), zero for later corrections of the
+                               step; 1 = zero;
                                0 = by precision: the Galerkin start with FP64 PCG (precision
                                0), zero with FP32 PCG (precision 1), whichever measured faster.
                                The adjoint's solves start from zero */
