@@ -6,7 +6,10 @@ eps = ||J||_F/||U||_F <= tol, every fine sweep, jump, linearisation, DFT, harmon
 solve and inverse DFT on the GPU, with the problem already resident in HBM.  The
 workload is the nonlinear coax (nr = 60 x ntheta = 120, 7,081 free nodes, steel
 sheath with a Brauer B-H law, N = 40 subintervals x 50 implicit-Euler steps,
-21 harmonic systems, FP64) with synthetic seeded inputs.
+21 harmonic systems, FP64) with synthetic seeded inputs, at tolerances that keep the error
+against the FP64 oracle under the metric's 1e-6: PP-PC to eps <= 1e-7, Newton to 1e-10 of
+each step's scale with the adaptive fine tolerance (theta = 1e-3: early sweeps solve only to
+theta eps of the previous iteration, the late ones to 1e-10), harmonic solves to 1e-6.
 
 Prints one JSON line: steady states per second, the roofline of the dominant kernel
 (the fine sweep) from its measured launch durations and algorithmic bytes, the error
@@ -20,7 +23,7 @@ from rest with the coarse-correction safeguard at 3 T, which these thin, strongl
 sheaths need).
 
 The default workload is the nonlinear coax above because one of its steady states takes
-about 1.5 s.  The two larger configurations do not fit a run of minutes: a steady state of
+under a second.  The two larger configurations do not fit a run of minutes: a steady state of
 the large coax (nr = 400, 319,201 free nodes, N = 200 x 100, 101 harmonics) takes about
 35-40 minutes and one batched solve of the 256 designs about 30 minutes on one MI355X, by
 their measured per-iteration costs.  `--workload c3` still runs whole steady states of the
